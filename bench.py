@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Throughput of the chi(2) split-step z-loop on one MI355X.
+
+A "step" is one z-step of the method (RK4 half-step, forward transforms,
+propagator, inverse transforms, RK4 half-step) over the whole grid.  The
+timed workload is the 3-field OPG solve on a 256^3 grid (about 400 MB of
+complex64 state, larger than the 256 MB last-level cache), seeded synthetic
+input, fields resident in HBM before timing starts.
+
+Prints one JSON line: grid-point z-steps per second, the HBM roofline of the
+dominant kernel (event-timed launches), and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "grid-point·z-steps/s + % HBM peak; adjoint/forward time; batched vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000, help="timed z-steps (1000 = full solve)")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="opg256", choices=["opg256", "sfg128", "shg32"])
+    ap.add_argument("--timing-steps", type=int, default=200,
+                    help="z-steps of the event-timed run used for the roofline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle z-steps in the CPU sample")
+    return ap.parse_args()
+
+
+def make_workload(name):
+    from paper_2609_08384_amd import inputs
+    return {"opg256": inputs.opg256, "sfg128": inputs.sfg128, "shg32": inputs.shg32}[name]()
+
+
+def cpu_baseline(wl, nsteps):
+    """The FP64 oracle (test infrastructure) on the first nsteps z-steps of
+    the same workload, on this host's cores."""
+    import torch
+    from oracle import ssfm
+    fields = [ssfm.FieldParams(kappa=f.kappa, diffraction=f.diffraction, tan_rho=f.tan_rho,
+                               delay=f.delay, k2=f.k2, k3=f.k3, alpha=f.alpha) for f in wl.fields]
+    prob = ssfm.Problem(wl.nx, wl.ny, wl.nt, wl.nf, wl.dz, fields, dk_const=wl.dk_const,
+                        dk=None if wl.dk is None else list(wl.dk))
+    orc = ssfm.Oracle(prob)
+    a = [torch.from_numpy(x).to(torch.complex128) for x in wl.init]
+    a = orc.step(a, 0)  # first step outside the clock (allocator warm-up)
+    t0 = time.perf_counter()
+    for n in range(1, 1 + nsteps):
+        a = orc.step(a, n)
+    dt = time.perf_counter() - t0
+    return {"value": wl.points * nsteps / dt, "unit": "grid-point·z-steps/s",
+            "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"{wl.name}: {nsteps} z-steps of the full {wl.nx}x{wl.ny}x{wl.nt} grid, "
+                      f"{wl.nf} fields, complex128, {dt:.1f} s",
+            "cpu": platform.processor() or platform.machine()}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: only one GPU is supported (asked for {max(args.gpus, world)}); "
+              "the engine has no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2609_08384_amd import brahms
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = make_workload(args.workload)
+    init = [torch.from_numpy(a).to(dev) for a in wl.init]
+    fields = [a.clone() for a in init]
+    plan = brahms.Plan(wl.nx, wl.ny, wl.nt, wl.nf, brahms.params_from_workload(wl)).bind(fields)
+
+    def reset():
+        for f, a in zip(fields, init):
+            f.copy_(a)
+        plan.set_z(0.0)
+        torch.cuda.synchronize()
+
+    # warm-up, then restart the solve from the entrance face
+    plan.step(args.warmup)
+    reset()
+
+    steps = args.steps
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    plan.step(steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    value = wl.points * steps / wall
+
+    finite = all(bool(torch.isfinite(torch.view_as_real(f)).all()) for f in fields)
+
+    # event-timed run of the same solve for per-kernel durations
+    reset()
+    plan.timing_enable(True)
+    tsteps = min(args.timing_steps, steps)
+    plan.step(tsteps)
+    tim = plan.timing_read()
+    plan.timing_enable(False)
+    passes = {k: v for k, v in tim.items() if k != "tables"}
+    dom = max(passes, key=lambda k: passes[k][0])
+    dom_ms, dom_n = passes[dom]
+    avg_ms = dom_ms / max(dom_n, 1)
+    # algorithmic bytes of one pass launch: every field read once and written
+    # once, 2 * 8 B per complex64 value
+    bytes_per_launch = 2 * 8 * wl.nf * wl.points
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": bytes_per_launch}
+    per_kernel = {k: {"avg_ms": round(v[0] / max(v[1], 1), 5), "launches": v[1],
+                      "GBps": (round(bytes_per_launch / (v[0] / v[1] * 1e-3) / 1e9, 1)
+                               if v[1] and k != "tables" else None)} for k, v in tim.items()}
+    step_bytes = 3 * bytes_per_launch
+    plan.destroy()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        del fields, init
+        torch.cuda.empty_cache()
+        cpu = cpu_baseline(wl, args.cpu_steps)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-point·z-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded)",
+        "config": {"workload": f"{wl.name}: {wl.nf}-field chi(2) split-step, "
+                               f"{wl.nx}x{wl.ny}x{wl.nt} grid, {wl.nz} z-steps",
+                   "nx": wl.nx, "ny": wl.ny, "nt": wl.nt, "nf": wl.nf, "nz": wl.nz,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "hbm_frac_step": round(step_bytes / (wall / steps) / 1e9 / HBM_PEAK_GBS, 4),
+        "event_ms_per_step": ev_ms / steps,
+        "per_kernel": per_kernel,
+        "fields_finite": finite,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,146 @@
+/* brahms.h -- C ABI of the MI355X (gfx950) engine for the chi(2)
+ * split-step Fourier z-loop of BRAHMS (arXiv 2609.08384).
+ *
+ * The engine propagates nf = 2 (SHG) or nf = 3 (SFG / OPG) complex envelopes
+ * A_j(x, y, tau) through a crystal along z by the symmetric split-step
+ * scheme N/2 - L - N/2 (Sec. 3.1, eq. expon): each z-step is a fourth-order
+ * Runge-Kutta half-step of the chi(2) coupling, the linear step (dispersion
+ * eq. dispOp, diffraction and walk-off eq. diffOp) applied in Fourier space,
+ * and a second Runge-Kutta half-step.  The equations solved, in the units of
+ * brahms_field_params (x, y, tau in grid cells scaled by dx, dy, dt; z in
+ * crystal lengths), are
+ *
+ *   nf = 3 (0 = p with w_p = w_s + w_i, 1 = s, 2 = i), eqs. CEp/CEs/CEi:
+ *     dA_p/dz = L_p A_p + i kappa_p A_s A_i   exp(-i Phi(z))
+ *     dA_s/dz = L_s A_s + i kappa_s A_p A_i^* exp(+i Phi(z))
+ *     dA_i/dz = L_i A_i + i kappa_i A_p A_s^* exp(+i Phi(z))
+ *   nf = 2 (0 = fundamental F, 1 = second harmonic S), the degenerate case:
+ *     dF/dz = L_F F + i kappa_F S F^* exp(+i Phi(z))
+ *     dS/dz = L_S S + i kappa_S F^2   exp(-i Phi(z))
+ *   L_j = i D_j (d2/dx2 + d2/dy2) - tan(rho_j) d/dx - delta_j d/dtau
+ *         - i (k''_j / 2) d2/dtau2 + (k'''_j / 6) d3/dtau3 - alpha_j / 2
+ *   Phi(z) = integral_0^z dk(z') dz', dk piecewise constant per z-step,
+ *
+ * with periodic boundaries in x, y and tau.
+ *
+ * Data layout: every field is a caller-owned device buffer of nx*ny*nt
+ * complex64 values (interleaved float re, im), x fastest, then y, then tau
+ * (the x -> y -> tau index hierarchy of Sec. 4.3), at least 256-byte
+ * aligned.  The engine updates the fields in place.
+ *
+ * Ownership: the library never allocates device memory.  The caller passes
+ * the fields and one workspace buffer of brahms_plan_workspace_size() bytes
+ * (256-byte aligned); the plan borrows both until it is destroyed or bound
+ * again.  Every call after brahms_plan_create is asynchronous on the stream
+ * given at creation (a hipStream_t, NULL = the legacy default stream), except
+ * when BRAHMS_CHECK_FINITE is set, which synchronises that stream at the end
+ * of each call.  A plan is not thread-safe; distinct plans are independent.
+ *
+ * Errors: every call returns a brahms_status and never throws;
+ * brahms_last_error() returns a thread-local description of the last failure.
+ */
+#ifndef BRAHMS_H_
+#define BRAHMS_H_
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BRAHMS_OK = 0,
+  BRAHMS_E_INVALID_ARG = 1,  /* bad size, pointer, parameter or step count   */
+  BRAHMS_E_UNSUPPORTED = 2,  /* an axis length the transforms do not handle  */
+  BRAHMS_E_DEVICE = 3,       /* a HIP runtime error                          */
+  BRAHMS_E_NONFINITE = 4,    /* a field became NaN/Inf (dz too large, Sec. 3.2) */
+  BRAHMS_E_STATE = 5         /* call out of order (e.g. step before bind)    */
+} brahms_status;
+
+/* Flags of brahms_params.flags */
+#define BRAHMS_CHECK_FINITE 1u  /* test fields for NaN/Inf after each call */
+
+typedef struct brahms_plan_s* brahms_plan;
+
+/* Coefficients of one field (eqs. dispOp, diffOp and the coupling of
+ * eqs. CEp/CEs/CEi), in normalised units. */
+typedef struct {
+  double kappa;        /* nonlinear coupling kappa_j = 2 pi d_eff / (n_j lambda_j) */
+  double diffraction;  /* D_j = 1 / (2 k_j)                                  */
+  double tan_rho;      /* spatial walk-off tan(rho_j)                        */
+  double delay;        /* group-delay coefficient delta_j (frame mismatch)   */
+  double k2;           /* group-velocity dispersion k''_j                    */
+  double k3;           /* third-order dispersion k'''_j                      */
+  double alpha;        /* linear power attenuation alpha_j                   */
+} brahms_field_params;
+
+typedef struct {
+  double dz;                    /* z-step (> 0); step n spans [n dz, (n+1) dz]    */
+  double dk_const;              /* phase mismatch dk (eq. mismatch) when dk==NULL */
+  const double* dk;             /* host array: per-step dk_n, copied at create    */
+  int n_dk;                     /* length of dk (number of steps it covers)       */
+  double dx, dy, dt;            /* grid spacings; 0 means 1                       */
+  brahms_field_params field[3]; /* first nf entries used                          */
+  unsigned flags;               /* BRAHMS_CHECK_FINITE                            */
+} brahms_params;
+
+/* Create a plan for an nx x ny x nt grid with nfields in {2, 3}.
+ * Axis lengths must be 1, 2, 4, 8, 16, 32, 64, 96, 128 or 256
+ * (BRAHMS_E_UNSUPPORTED otherwise).  The parameters are copied.
+ * Errors: BRAHMS_E_INVALID_ARG for a non-positive size, nf outside {2, 3},
+ * NULL params/out, dz <= 0, a non-finite coefficient, or dk != NULL with
+ * n_dk < 1. */
+brahms_status brahms_plan_create(int nx, int ny, int nt, int nfields,
+                                 const brahms_params* params, void* hip_stream,
+                                 brahms_plan* out);
+
+/* Bytes of device workspace the plan needs (tables and per-step
+ * propagators). */
+brahms_status brahms_plan_workspace_size(brahms_plan plan, size_t* bytes);
+
+/* Attach nfields field buffers and the workspace (device pointers, see the
+ * layout and ownership notes above) and upload the plan's tables.  Resets
+ * nothing else: z keeps its value.  Errors: BRAHMS_E_INVALID_ARG for NULL or
+ * misaligned pointers, BRAHMS_E_DEVICE for a failed upload. */
+brahms_status brahms_plan_bind(brahms_plan plan, void* const* fields, void* workspace);
+
+/* Advance nsteps z-steps (Sec. 3.1: N/2 - L - N/2 per step) from the current
+ * step index; nsteps = 0 is a no-op.  Errors: BRAHMS_E_STATE before bind,
+ * BRAHMS_E_INVALID_ARG for nsteps < 0 or steps beyond the dk profile,
+ * BRAHMS_E_NONFINITE (with BRAHMS_CHECK_FINITE) when a field holds NaN/Inf
+ * afterwards; the step index then counts the completed steps and the field
+ * contents are unspecified. */
+brahms_status brahms_step(brahms_plan plan, int nsteps);
+
+/* Propagate to z_end: n = round((z_end - z) / dz) steps.  z_end must lie
+ * within 1e-9 max(1, |z_end|) of a multiple of dz and not before z. */
+brahms_status brahms_propagate(brahms_plan plan, double z_end);
+
+/* Current z = (step index) * dz. */
+brahms_status brahms_get_z(brahms_plan plan, double* z);
+
+/* Set the step index to round(z / dz) (resume from saved fields); z must be
+ * a non-negative multiple of dz within the tolerance of brahms_propagate. */
+brahms_status brahms_set_z(brahms_plan plan, double z);
+
+brahms_status brahms_plan_destroy(brahms_plan plan);
+
+/* Kernel timing (diagnostics, not part of the method).  While enabled, every
+ * kernel launch of brahms_step is bracketed by HIP events recorded on the
+ * plan's stream (at most 65536 launches are timed between two reads).
+ * brahms_timing_read synchronises that stream, then writes, per launch kind
+ * (0 = X pass, 1 = Y pass, 2 = tau pass, 3 = per-step table kernel), the summed
+ * duration in milliseconds and the number of timed launches, and clears the
+ * record.  Errors: BRAHMS_E_INVALID_ARG for NULL outputs, BRAHMS_E_DEVICE. */
+#define BRAHMS_TIMING_KINDS 4
+brahms_status brahms_timing_enable(brahms_plan plan, int enable);
+brahms_status brahms_timing_read(brahms_plan plan, double* ms, long long* launches);
+
+/* Thread-local message for the last failing call (empty if none). */
+const char* brahms_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BRAHMS_H_ */

@@ -1,0 +1,242 @@
+"""Python binding of the C ABI in include/brahms.h (argument marshalling only).
+
+Every step of the propagation runs in the HIP library; this module only
+translates arguments, owns nothing but torch tensors for device memory, and
+raises if the library is missing.  Names follow the C calls.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libbrahms.so")
+
+BRAHMS_OK = 0
+BRAHMS_E_INVALID_ARG = 1
+BRAHMS_E_UNSUPPORTED = 2
+BRAHMS_E_DEVICE = 3
+BRAHMS_E_NONFINITE = 4
+BRAHMS_E_STATE = 5
+BRAHMS_CHECK_FINITE = 1
+
+STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_UNSUPPORTED", 3: "E_DEVICE",
+                4: "E_NONFINITE", 5: "E_STATE"}
+
+SUPPORTED_LENGTHS = (1, 2, 4, 8, 16, 32, 64, 96, 128, 256)
+TIMING_KINDS = 4
+TIMING_NAMES = ("x_pass", "y_pass", "t_pass", "tables")
+
+
+class BrahmsError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: BRAHMS_{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class FieldParamsC(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_double), ("diffraction", ctypes.c_double),
+                ("tan_rho", ctypes.c_double), ("delay", ctypes.c_double),
+                ("k2", ctypes.c_double), ("k3", ctypes.c_double), ("alpha", ctypes.c_double)]
+
+
+class ParamsC(ctypes.Structure):
+    _fields_ = [("dz", ctypes.c_double), ("dk_const", ctypes.c_double),
+                ("dk", ctypes.POINTER(ctypes.c_double)), ("n_dk", ctypes.c_int),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dt", ctypes.c_double),
+                ("field", FieldParamsC * 3), ("flags", ctypes.c_uint)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libbrahms.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP engine library not found at {path}; build it with "
+                           "`python -m paper_2609_08384_amd.build` (or __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "brahms_plan_create": [i, i, i, i, ctypes.POINTER(ParamsC), vp, ctypes.POINTER(vp)],
+        "brahms_plan_workspace_size": [vp, ctypes.POINTER(ctypes.c_size_t)],
+        "brahms_plan_bind": [vp, ctypes.POINTER(vp), vp],
+        "brahms_step": [vp, i],
+        "brahms_propagate": [vp, d],
+        "brahms_get_z": [vp, ctypes.POINTER(d)],
+        "brahms_set_z": [vp, d],
+        "brahms_plan_destroy": [vp],
+        "brahms_timing_enable": [vp, i],
+        "brahms_timing_read": [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.brahms_last_error.argtypes = []
+    lib.brahms_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != BRAHMS_OK:
+        msg = _lib.brahms_last_error().decode() if _lib is not None else ""
+        raise BrahmsError(status, where, msg)
+
+
+@dataclass
+class FieldParams:
+    kappa: float = 0.0
+    diffraction: float = 0.0
+    tan_rho: float = 0.0
+    delay: float = 0.0
+    k2: float = 0.0
+    k3: float = 0.0
+    alpha: float = 0.0
+
+
+@dataclass
+class Params:
+    dz: float
+    fields: List[FieldParams]
+    dk_const: float = 0.0
+    dk: Optional[Sequence[float]] = None
+    dx: float = 1.0
+    dy: float = 1.0
+    dt: float = 1.0
+    check_finite: bool = False
+
+
+def params_from_workload(wl) -> Params:
+    fs = [FieldParams(f.kappa, f.diffraction, f.tan_rho, f.delay, f.k2, f.k3, f.alpha)
+          for f in wl.fields]
+    dk = None if wl.dk is None else [float(v) for v in wl.dk]
+    return Params(dz=wl.dz, fields=fs, dk_const=wl.dk_const, dk=dk)
+
+
+def _params_c(p: Params, nf: int):
+    c = ParamsC()
+    c.dz = p.dz
+    c.dk_const = p.dk_const
+    keep = None
+    if p.dk is not None:
+        keep = (ctypes.c_double * len(p.dk))(*[float(v) for v in p.dk])
+        c.dk = ctypes.cast(keep, ctypes.POINTER(ctypes.c_double))
+        c.n_dk = len(p.dk)
+    else:
+        c.dk = None
+        c.n_dk = 0
+    c.dx, c.dy, c.dt = p.dx, p.dy, p.dt
+    for j, f in enumerate(p.fields[:3]):
+        c.field[j] = FieldParamsC(f.kappa, f.diffraction, f.tan_rho, f.delay, f.k2, f.k3, f.alpha)
+    c.flags = BRAHMS_CHECK_FINITE if p.check_finite else 0
+    return c, keep
+
+
+class Plan:
+    """brahms_plan: an nx x ny x nt grid with nf fields, bound to torch tensors.
+
+    Fields are complex64 CUDA tensors of shape [nt, ny, nx] (x fastest),
+    updated in place.  The workspace is a torch uint8 tensor owned here.
+    """
+
+    def __init__(self, nx: int, ny: int, nt: int, nf: int, params: Params,
+                 stream: Optional[torch.cuda.Stream] = None):
+        self._lib = load_library()
+        self.nx, self.ny, self.nt, self.nf = nx, ny, nt, nf
+        self.params = params
+        self.stream = stream
+        handle = ctypes.c_void_p()
+        pc, keep = _params_c(params, nf)
+        sptr = ctypes.c_void_p(stream.cuda_stream if stream is not None else
+                               (torch.cuda.current_stream().cuda_stream
+                                if torch.cuda.is_available() else 0))
+        _check(self._lib.brahms_plan_create(nx, ny, nt, nf, ctypes.byref(pc), sptr,
+                                            ctypes.byref(handle)), "brahms_plan_create")
+        del keep
+        self._h = handle
+        size = ctypes.c_size_t()
+        _check(self._lib.brahms_plan_workspace_size(self._h, ctypes.byref(size)),
+               "brahms_plan_workspace_size")
+        self.workspace_bytes = int(size.value)
+        self.workspace = None
+        self.fields: List[torch.Tensor] = []
+
+    def bind(self, fields: Sequence[torch.Tensor], workspace: Optional[torch.Tensor] = None):
+        if len(fields) != self.nf:
+            raise ValueError(f"need {self.nf} fields")
+        for f in fields:
+            if (f.dtype != torch.complex64 or not f.is_cuda or not f.is_contiguous()
+                    or tuple(f.shape) != (self.nt, self.ny, self.nx)):
+                raise ValueError("fields must be contiguous complex64 CUDA tensors of shape "
+                                 f"[{self.nt}, {self.ny}, {self.nx}]")
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8,
+                                    device=fields[0].device)
+        ptr = workspace.data_ptr()
+        aligned = (ptr + 255) // 256 * 256
+        arr = (ctypes.c_void_p * self.nf)(*[f.data_ptr() for f in fields])
+        _check(self._lib.brahms_plan_bind(self._h, arr, ctypes.c_void_p(aligned)),
+               "brahms_plan_bind")
+        self.workspace = workspace
+        self.fields = list(fields)
+        return self
+
+    def step(self, nsteps: int):
+        _check(self._lib.brahms_step(self._h, int(nsteps)), "brahms_step")
+
+    def propagate(self, z_end: float):
+        _check(self._lib.brahms_propagate(self._h, float(z_end)), "brahms_propagate")
+
+    @property
+    def z(self) -> float:
+        out = ctypes.c_double()
+        _check(self._lib.brahms_get_z(self._h, ctypes.byref(out)), "brahms_get_z")
+        return out.value
+
+    def set_z(self, z: float):
+        _check(self._lib.brahms_set_z(self._h, float(z)), "brahms_set_z")
+
+    def timing_enable(self, enable: bool = True):
+        _check(self._lib.brahms_timing_enable(self._h, 1 if enable else 0), "brahms_timing_enable")
+
+    def timing_read(self):
+        """{kind: (summed ms, launches)} for kinds x, y, t, tables; clears."""
+        ms = (ctypes.c_double * TIMING_KINDS)()
+        cnt = (ctypes.c_longlong * TIMING_KINDS)()
+        _check(self._lib.brahms_timing_read(self._h, ms, cnt), "brahms_timing_read")
+        return {name: (ms[k], int(cnt[k])) for k, name in enumerate(TIMING_NAMES)}
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(self._lib.brahms_plan_destroy(self._h), "brahms_plan_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def run_workload(wl, nsteps: Optional[int] = None, device: str = "cuda:0",
+                 stream: Optional[torch.cuda.Stream] = None) -> List[torch.Tensor]:
+    """Upload a seeded workload's entrance fields, propagate nsteps (default:
+    all of them) and return the device fields."""
+    nsteps = wl.nz if nsteps is None else nsteps
+    fields = [torch.from_numpy(a).to(device) for a in wl.init]
+    plan = Plan(wl.nx, wl.ny, wl.nt, wl.nf, params_from_workload(wl), stream=stream)
+    plan.bind(fields)
+    plan.step(nsteps)
+    torch.cuda.synchronize()
+    plan.destroy()
+    return fields

@@ -1,0 +1,441 @@
+// Host engine and C ABI of the chi(2) split-step z-loop (see include/brahms.h).
+//
+// A plan holds only host-side state.  Device state lives in caller memory:
+// the fields, and one workspace holding the axis twiddles, the integrated
+// mismatch profile, and a ring of per-step tables (propagators and RK4
+// coefficients) that a small kernel refills every kChunk steps.  A z-step is
+// three launches on the caller's stream: X pass (RK4 half-step + x line
+// transforms), Y pass (y line transforms), T pass (tau line transforms + RK4
+// half-step).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/brahms.h"
+#include "kernels.hpp"
+
+using namespace brahms;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+brahms_status fail(brahms_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(BRAHMS_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kChunk = 64;   // steps per table refill
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool supported_length(int n) {
+  switch (n) {
+    case 1: case 2: case 4: case 8: case 16: case 32: case 64: case 96: case 128: case 256:
+      return true;
+    default:
+      return false;
+  }
+}
+
+}  // namespace
+
+struct brahms_plan_s {
+  int nx = 0, ny = 0, nt = 0, nf = 0;
+  double dz = 0, dx = 1, dy = 1, dt = 1, dk_const = 0;
+  std::vector<double> dk;      // per-step profile (empty: constant)
+  std::vector<double> phi0;    // Phi_n prefix of the profile
+  brahms_field_params fp[3] = {};
+  unsigned flags = 0;
+  hipStream_t stream = nullptr;
+  float2* fields[3] = {nullptr, nullptr, nullptr};
+  char* ws = nullptr;
+  bool bound = false;
+  long long step = 0;          // z = step * dz
+  // workspace offsets (bytes)
+  size_t off_tw[3] = {0, 0, 0};
+  size_t off_phi0 = 0, off_dk = 0, off_prop = 0, off_nl = 0, off_flag = 0, ws_size = 0;
+  // launch timing (diagnostics)
+  bool timing = false;
+  struct Timed { int kind; hipEvent_t start, stop; };
+  std::vector<Timed> timed;             // one entry per timed launch
+  std::vector<hipEvent_t> pool;         // reusable events
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// kernel dispatch: each supported axis length maps to a (N1, N2) split with
+// N2 threads per line and N1 values per thread.
+// ---------------------------------------------------------------------------
+template <int N1, int N2>
+hipError_t launch_axis(int axis, int nf, const brahms_plan_s& p, PassArgs a) {
+  using G = LineGeom<N1, N2>;
+  const dim3 block(kBlock);
+  if (axis == AX_X) {
+    const long lines = long(p.ny) * p.nt;
+    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
+    if (nf == 3) hipLaunchKernelGGL((axis_pass<N1, N2, AX_X, 3, NL_BEFORE>), grid, block, 0, p.stream, a);
+    else hipLaunchKernelGGL((axis_pass<N1, N2, AX_X, 2, NL_BEFORE>), grid, block, 0, p.stream, a);
+  } else if (axis == AX_Y) {
+    const dim3 grid(unsigned((p.nx + G::LPB - 1) / G::LPB), unsigned(p.nt), unsigned(nf));
+    hipLaunchKernelGGL((axis_pass<N1, N2, AX_Y, 1, NL_NONE>), grid, block, 0, p.stream, a);
+  } else {
+    const long lines = long(p.nx) * p.ny;
+    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
+    if (nf == 3) hipLaunchKernelGGL((axis_pass<N1, N2, AX_T, 3, NL_AFTER>), grid, block, 0, p.stream, a);
+    else hipLaunchKernelGGL((axis_pass<N1, N2, AX_T, 2, NL_AFTER>), grid, block, 0, p.stream, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t dispatch_axis(int n, int axis, int nf, const brahms_plan_s& p, PassArgs a) {
+  switch (n) {
+    case 1: return launch_axis<1, 1>(axis, nf, p, a);
+    case 2: return launch_axis<2, 1>(axis, nf, p, a);
+    case 4: return launch_axis<4, 1>(axis, nf, p, a);
+    case 8: return launch_axis<4, 2>(axis, nf, p, a);
+    case 16: return launch_axis<4, 4>(axis, nf, p, a);
+    case 32: return launch_axis<8, 4>(axis, nf, p, a);
+    case 64: return launch_axis<8, 8>(axis, nf, p, a);
+    case 96: return launch_axis<24, 4>(axis, nf, p, a);
+    case 128: return launch_axis<16, 8>(axis, nf, p, a);
+    case 256: return launch_axis<16, 16>(axis, nf, p, a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool finite_params(const brahms_params* pr, int nf) {
+  if (!std::isfinite(pr->dz) || !std::isfinite(pr->dk_const) || !std::isfinite(pr->dx) ||
+      !std::isfinite(pr->dy) || !std::isfinite(pr->dt))
+    return false;
+  for (int j = 0; j < nf; ++j) {
+    const brahms_field_params& f = pr->field[j];
+    const double v[7] = {f.kappa, f.diffraction, f.tan_rho, f.delay, f.k2, f.k3, f.alpha};
+    for (double x : v)
+      if (!std::isfinite(x)) return false;
+  }
+  return true;
+}
+
+void layout(brahms_plan_s& p) {
+  size_t off = 0;
+  const int n[3] = {p.nx, p.ny, p.nt};
+  for (int a = 0; a < 3; ++a) {
+    p.off_tw[a] = off;
+    off = align_up(off + sizeof(float2) * size_t(n[a]));
+  }
+  p.off_phi0 = off;
+  off = align_up(off + sizeof(double) * (p.dk.size() + 1));
+  p.off_dk = off;
+  off = align_up(off + sizeof(double) * (p.dk.size() + 1));
+  p.off_prop = off;
+  off = align_up(off + sizeof(float2) * size_t(kChunk) * p.nf * (p.nx + p.ny + p.nt));
+  p.off_nl = off;
+  off = align_up(off + sizeof(float2) * size_t(kChunk) * 2 * p.nf * kNlCoef);
+  p.off_flag = off;
+  off = align_up(off + sizeof(int));
+  p.ws_size = off;
+}
+
+std::vector<float2> forward_twiddles(int n) {
+  std::vector<float2> tw(n);
+  for (int m = 0; m < n; ++m) {
+    // exp(-2 pi i m / n) evaluated in double, reduced exactly by symmetry
+    double c = 0.0, s = 0.0;
+    unit_root(m, n, c, s);
+    tw[m] = make_float2(float(c), float(-s));
+  }
+  return tw;
+}
+
+brahms_status check_plan(brahms_plan p) {
+  if (p == nullptr) return fail(BRAHMS_E_INVALID_ARG, "plan is NULL");
+  return BRAHMS_OK;
+}
+
+__global__ void clear_flag(int* flag) { *flag = 0; }
+
+constexpr size_t kMaxTimed = 65536;
+
+brahms_status take_event(brahms_plan_s& p, hipEvent_t* ev) {
+  if (!p.pool.empty()) {
+    *ev = p.pool.back();
+    p.pool.pop_back();
+    return BRAHMS_OK;
+  }
+  HIP_TRY(hipEventCreate(ev));
+  return BRAHMS_OK;
+}
+
+// Record a start event before a launch of the given kind (when timing).
+brahms_status timing_start(brahms_plan_s& p, int kind) {
+  if (!p.timing || p.timed.size() >= kMaxTimed) return BRAHMS_OK;
+  brahms_plan_s::Timed t{kind, nullptr, nullptr};
+  if (brahms_status st = take_event(p, &t.start)) return st;
+  if (brahms_status st = take_event(p, &t.stop)) return st;
+  HIP_TRY(hipEventRecord(t.start, p.stream));
+  p.timed.push_back(t);
+  return BRAHMS_OK;
+}
+
+// Record the stop event of the launch opened by the last timing_start.
+brahms_status timing_stop(brahms_plan_s& p) {
+  if (!p.timing || p.timed.empty() || p.timed.size() > kMaxTimed) return BRAHMS_OK;
+  HIP_TRY(hipEventRecord(p.timed.back().stop, p.stream));
+  return BRAHMS_OK;
+}
+
+brahms_status run_steps(brahms_plan_s& p, int nsteps) {
+  const int per_field = p.nx + p.ny + p.nt;
+  float2* prop = reinterpret_cast<float2*>(p.ws + p.off_prop);
+  float2* nl = reinterpret_cast<float2*>(p.ws + p.off_nl);
+  const int n[3] = {p.nx, p.ny, p.nt};
+  int done = 0;
+  while (done < nsteps) {
+    const int count = std::min(kChunk, nsteps - done);
+    TableArgs ta{};
+    ta.prop = prop;
+    ta.nl = nl;
+    ta.phi0 = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_phi0);
+    ta.dk = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_dk);
+    ta.n0 = p.step;
+    ta.count = count;
+    ta.nx = p.nx; ta.ny = p.ny; ta.nt = p.nt; ta.nf = p.nf;
+    ta.dz = p.dz; ta.dx = p.dx; ta.dy = p.dy; ta.dt = p.dt; ta.dk_const = p.dk_const;
+    for (int j = 0; j < p.nf; ++j) {
+      const brahms_field_params& f = p.fp[j];
+      ta.fc[j] = FieldCoef{f.kappa, f.diffraction, f.tan_rho, f.delay, f.k2, f.k3, f.alpha};
+    }
+    const long total = long(count) * p.nf * per_field + long(count) * 2 * p.nf;
+    const bool timed_tab = p.timing && p.timed.size() < kMaxTimed;
+    if (brahms_status st = timing_start(p, 3)) return st;
+    hipLaunchKernelGGL(step_tables, dim3(unsigned((total + 255) / 256)), dim3(256), 0, p.stream, ta);
+    HIP_TRY(hipGetLastError());
+    if (timed_tab)
+      if (brahms_status st = timing_stop(p)) return st;
+    for (int s = 0; s < count; ++s) {
+      const float2* row = prop + size_t(s) * p.nf * per_field;
+      // tables of one step: [nf][nx | ny | nt]
+      for (int ax = 0; ax < 3; ++ax) {
+        PassArgs a{};
+        for (int j = 0; j < 3; ++j) a.f[j] = p.fields[j];
+        a.tw = reinterpret_cast<const float2*>(p.ws + p.off_tw[ax]);
+        a.nx = p.nx; a.ny = p.ny; a.nt = p.nt;
+        a.nl = nl + (size_t(s) * 2 + (ax == AX_X ? 0 : 1)) * p.nf * kNlCoef;
+        a.prop = row;
+        a.axis_off = (ax == AX_X) ? 0 : (ax == AX_Y ? p.nx : p.nx + p.ny);
+        a.field_stride = per_field;
+        const bool timed = p.timing && p.timed.size() < kMaxTimed;
+        if (brahms_status st = timing_start(p, ax)) return st;
+        HIP_TRY(dispatch_axis(n[ax], ax, p.nf, p, a));
+        if (timed)
+          if (brahms_status st = timing_stop(p)) return st;
+      }
+    }
+    p.step += count;
+    done += count;
+  }
+  return BRAHMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* brahms_last_error(void) { return g_last_error.c_str(); }
+
+brahms_status brahms_plan_create(int nx, int ny, int nt, int nfields, const brahms_params* params,
+                                 void* hip_stream, brahms_plan* out) {
+  g_last_error.clear();
+  if (out == nullptr) return fail(BRAHMS_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (params == nullptr) return fail(BRAHMS_E_INVALID_ARG, "params is NULL");
+  if (nx < 1 || ny < 1 || nt < 1) return fail(BRAHMS_E_INVALID_ARG, "axis length < 1");
+  if (nfields != 2 && nfields != 3) return fail(BRAHMS_E_INVALID_ARG, "nfields must be 2 or 3");
+  if (!finite_params(params, nfields)) return fail(BRAHMS_E_INVALID_ARG, "non-finite parameter");
+  if (!(params->dz > 0.0)) return fail(BRAHMS_E_INVALID_ARG, "dz must be > 0");
+  if (params->dx < 0.0 || params->dy < 0.0 || params->dt < 0.0)
+    return fail(BRAHMS_E_INVALID_ARG, "negative grid spacing");
+  if (params->dk != nullptr && params->n_dk < 1)
+    return fail(BRAHMS_E_INVALID_ARG, "dk profile given with n_dk < 1");
+  if (!supported_length(nx) || !supported_length(ny) || !supported_length(nt))
+    return fail(BRAHMS_E_UNSUPPORTED,
+                "axis lengths must be one of 1, 2, 4, 8, 16, 32, 64, 96, 128, 256");
+  auto* p = new brahms_plan_s();
+  p->nx = nx; p->ny = ny; p->nt = nt; p->nf = nfields;
+  p->dz = params->dz;
+  p->dx = params->dx > 0 ? params->dx : 1.0;
+  p->dy = params->dy > 0 ? params->dy : 1.0;
+  p->dt = params->dt > 0 ? params->dt : 1.0;
+  p->dk_const = params->dk_const;
+  if (params->dk != nullptr) {
+    p->dk.assign(params->dk, params->dk + params->n_dk);
+    for (double v : p->dk)
+      if (!std::isfinite(v)) {
+        delete p;
+        return fail(BRAHMS_E_INVALID_ARG, "non-finite dk entry");
+      }
+    p->phi0.resize(p->dk.size() + 1);
+    p->phi0[0] = 0.0;
+    for (size_t k = 0; k < p->dk.size(); ++k) p->phi0[k + 1] = p->phi0[k] + p->dk[k] * p->dz;
+  }
+  for (int j = 0; j < nfields; ++j) p->fp[j] = params->field[j];
+  p->flags = params->flags;
+  p->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  layout(*p);
+  *out = p;
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_plan_workspace_size(brahms_plan plan, size_t* bytes) {
+  if (brahms_status st = check_plan(plan)) return st;
+  if (bytes == nullptr) return fail(BRAHMS_E_INVALID_ARG, "bytes is NULL");
+  *bytes = plan->ws_size;
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_plan_bind(brahms_plan plan, void* const* fields, void* workspace) {
+  if (brahms_status st = check_plan(plan)) return st;
+  if (fields == nullptr || workspace == nullptr)
+    return fail(BRAHMS_E_INVALID_ARG, "fields or workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(BRAHMS_E_INVALID_ARG, "workspace must be 256-byte aligned");
+  for (int j = 0; j < plan->nf; ++j) {
+    if (fields[j] == nullptr) return fail(BRAHMS_E_INVALID_ARG, "field pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(fields[j]) % 8 != 0)
+      return fail(BRAHMS_E_INVALID_ARG, "field pointer must be 8-byte aligned");
+  }
+  plan->bound = false;
+  for (int j = 0; j < 3; ++j) plan->fields[j] = j < plan->nf ? static_cast<float2*>(fields[j]) : nullptr;
+  plan->ws = static_cast<char*>(workspace);
+  const int n[3] = {plan->nx, plan->ny, plan->nt};
+  for (int a = 0; a < 3; ++a) {
+    std::vector<float2> tw = forward_twiddles(n[a]);
+    HIP_TRY(hipMemcpyAsync(plan->ws + plan->off_tw[a], tw.data(), sizeof(float2) * tw.size(),
+                           hipMemcpyHostToDevice, plan->stream));
+    HIP_TRY(hipStreamSynchronize(plan->stream));  // tw is a host temporary
+  }
+  if (!plan->dk.empty()) {
+    HIP_TRY(hipMemcpyAsync(plan->ws + plan->off_phi0, plan->phi0.data(),
+                           sizeof(double) * plan->phi0.size(), hipMemcpyHostToDevice, plan->stream));
+    HIP_TRY(hipMemcpyAsync(plan->ws + plan->off_dk, plan->dk.data(), sizeof(double) * plan->dk.size(),
+                           hipMemcpyHostToDevice, plan->stream));
+    HIP_TRY(hipStreamSynchronize(plan->stream));
+  }
+  plan->bound = true;
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_step(brahms_plan plan, int nsteps) {
+  if (brahms_status st = check_plan(plan)) return st;
+  if (!plan->bound) return fail(BRAHMS_E_STATE, "brahms_step before brahms_plan_bind");
+  if (nsteps < 0) return fail(BRAHMS_E_INVALID_ARG, "nsteps < 0");
+  if (nsteps == 0) return BRAHMS_OK;
+  if (!plan->dk.empty() && plan->step + nsteps > (long long)plan->dk.size())
+    return fail(BRAHMS_E_INVALID_ARG, "steps beyond the end of the dk profile");
+  if (brahms_status st = run_steps(*plan, nsteps)) return st;
+  if (plan->flags & BRAHMS_CHECK_FINITE) {
+    int* flag = reinterpret_cast<int*>(plan->ws + plan->off_flag);
+    hipLaunchKernelGGL(clear_flag, dim3(1), dim3(1), 0, plan->stream, flag);
+    const long n = long(plan->nx) * plan->ny * plan->nt;
+    for (int j = 0; j < plan->nf; ++j)
+      hipLaunchKernelGGL(finite_check, dim3(1024), dim3(256), 0, plan->stream, plan->fields[j], n, flag);
+    HIP_TRY(hipGetLastError());
+    int host_flag = 0;
+    HIP_TRY(hipMemcpyAsync(&host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, plan->stream));
+    HIP_TRY(hipStreamSynchronize(plan->stream));
+    if (host_flag) return fail(BRAHMS_E_NONFINITE, "a field holds NaN or Inf (dz too large?)");
+  }
+  return BRAHMS_OK;
+}
+
+static bool steps_to(double z_from_steps_dz, double z_end, double dz, long long* n_out) {
+  const double r = z_end / dz;
+  const double n = std::nearbyint(r);
+  const double tol = 1e-9 * std::max(1.0, std::fabs(z_end));
+  if (std::fabs(n * dz - z_end) > tol) return false;
+  (void)z_from_steps_dz;
+  *n_out = (long long)n;
+  return true;
+}
+
+brahms_status brahms_propagate(brahms_plan plan, double z_end) {
+  if (brahms_status st = check_plan(plan)) return st;
+  if (!std::isfinite(z_end)) return fail(BRAHMS_E_INVALID_ARG, "z_end not finite");
+  long long target = 0;
+  if (!steps_to(0.0, z_end, plan->dz, &target))
+    return fail(BRAHMS_E_INVALID_ARG, "z_end is not a multiple of dz");
+  if (target < plan->step) return fail(BRAHMS_E_INVALID_ARG, "z_end lies before the current z");
+  if (target - plan->step > 0x7fffffffLL) return fail(BRAHMS_E_INVALID_ARG, "too many steps");
+  return brahms_step(plan, int(target - plan->step));
+}
+
+brahms_status brahms_get_z(brahms_plan plan, double* z) {
+  if (brahms_status st = check_plan(plan)) return st;
+  if (z == nullptr) return fail(BRAHMS_E_INVALID_ARG, "z is NULL");
+  *z = double(plan->step) * plan->dz;
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_set_z(brahms_plan plan, double z) {
+  if (brahms_status st = check_plan(plan)) return st;
+  long long n = 0;
+  if (!std::isfinite(z) || z < 0.0 || !steps_to(0.0, z, plan->dz, &n))
+    return fail(BRAHMS_E_INVALID_ARG, "z must be a non-negative multiple of dz");
+  plan->step = n;
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_timing_enable(brahms_plan plan, int enable) {
+  if (brahms_status st = check_plan(plan)) return st;
+  plan->timing = enable != 0;
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_timing_read(brahms_plan plan, double* ms, long long* launches) {
+  if (brahms_status st = check_plan(plan)) return st;
+  if (ms == nullptr || launches == nullptr) return fail(BRAHMS_E_INVALID_ARG, "NULL output");
+  for (int k = 0; k < BRAHMS_TIMING_KINDS; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  HIP_TRY(hipStreamSynchronize(plan->stream));
+  for (const auto& t : plan->timed) {
+    float el = 0.f;
+    HIP_TRY(hipEventElapsedTime(&el, t.start, t.stop));
+    ms[t.kind] += el;
+    launches[t.kind] += 1;
+  }
+  for (const auto& t : plan->timed) {
+    plan->pool.push_back(t.start);
+    plan->pool.push_back(t.stop);
+  }
+  plan->timed.clear();
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_plan_destroy(brahms_plan plan) {
+  if (plan == nullptr) return fail(BRAHMS_E_INVALID_ARG, "plan is NULL");
+  for (const auto& t : plan->timed) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  for (hipEvent_t e : plan->pool) (void)hipEventDestroy(e);
+  delete plan;
+  return BRAHMS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,388 @@
+// Device kernels of the chi(2) split-step z-loop (gfx950).
+//
+// One z-step (symmetric splitting N/2 - L - N/2, Sec. 3.1 eq. expon) is three
+// HBM passes over the fields, each a batch of independent 1D lines:
+//
+//   X pass : RK4 half-step of the coupled chi(2) equations (eqs. CEp/CEs/CEi),
+//            then FFT_x . P_x . IFFT_x                    (all fields together)
+//   Y pass : FFT_y . P_y . IFFT_y                          (one field per block)
+//   T pass : FFT_tau . P_tau . IFFT_tau, then the second RK4 half-step
+//
+// The linear step exp(L dz) is separable, L = L_x + L_y + L_tau with the
+// three parts acting on different axes, so its Fourier-space form is the
+// product of three commuting 1D transform-multiply-inverse operators; this is
+// the paper's own split into a tau step and an xy step (Sec. 4.3), taken one
+// axis further.  Fields stay x-fastest, [nt][ny][nx] complex64, in place:
+// the y and tau passes read their lines with a stride instead of
+// materialising the paper's reordered copy.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dft.hpp"
+
+namespace brahms {
+
+constexpr int kBlock = 256;        // threads per block in every pass
+constexpr int kNlCoef = 6;         // RK4 coefficients per field per half-step
+
+enum Axis { AX_X = 0, AX_Y = 1, AX_T = 2 };
+enum NlMode { NL_NONE = 0, NL_BEFORE = 1, NL_AFTER = 2 };
+
+struct PassArgs {
+  float2* f[3];          // field base pointers (complex64, [nt][ny][nx])
+  const float2* tw;      // forward twiddles exp(-2 pi i m / N), m < N, this axis
+  const float2* prop;    // per-step propagators, field j's table of this
+                         // axis at prop + j * field_stride + axis_off
+  const float2* nl;      // RK4 coefficients of this half-step, [nf][6]
+  int nx, ny, nt;
+  int axis_off, field_stride;
+};
+
+// ---------------------------------------------------------------------------
+// chi(2) RK4 point update.  With c_j(z) = i kappa_j exp(sigma_j i Phi(z)) and
+// the bilinear products Q_j (p: s i, s: p i*, i: p s*; SHG F: S F*, S: F F)
+// one classical RK4 step of size h from z_a is
+//   y2 = y + a1 Q(y),  y3 = y + a2 Q(y2),  y4 = y + a3 Q(y3),
+//   y' = y + b1 Q(y) + b2 Q(y2) + b2 Q(y3) + b4 Q(y4)
+// with a1 = h/2 c(z_a), a2 = h/2 c(z_m), a3 = h c(z_m), b1 = h/6 c(z_a),
+// b2 = h/3 c(z_m), b4 = h/6 c(z_a + h), z_m = z_a + h/2.  The coefficients
+// are formed in double precision per half-step by the table kernel.
+// ---------------------------------------------------------------------------
+template <int NF>
+__device__ inline void chi2_products(const float2* y, float2* q) {
+  if constexpr (NF == 3) {
+    q[0] = cmul(y[1], y[2]);
+    q[1] = cmulc(y[0], y[2]);
+    q[2] = cmulc(y[0], y[1]);
+  } else {
+    q[0] = cmulc(y[1], y[0]);
+    q[1] = cmul(y[0], y[0]);
+  }
+}
+
+__device__ inline float2 cfma(float2 acc, float2 c, float2 q) {  // acc + c q
+  return make_float2(fmaf(c.x, q.x, fmaf(-c.y, q.y, acc.x)),
+                     fmaf(c.x, q.y, fmaf(c.y, q.x, acc.y)));
+}
+
+template <int NF>
+__device__ inline void rk4_point(float2* y, const float2 (*co)[kNlCoef]) {
+  float2 q[NF], acc[NF], ys[NF];
+  chi2_products<NF>(y, q);
+#pragma unroll
+  for (int j = 0; j < NF; ++j) {
+    acc[j] = cfma(y[j], co[j][3], q[j]);
+    ys[j] = cfma(y[j], co[j][0], q[j]);
+  }
+  chi2_products<NF>(ys, q);
+#pragma unroll
+  for (int j = 0; j < NF; ++j) {
+    acc[j] = cfma(acc[j], co[j][4], q[j]);
+    ys[j] = cfma(y[j], co[j][1], q[j]);
+  }
+  chi2_products<NF>(ys, q);
+#pragma unroll
+  for (int j = 0; j < NF; ++j) {
+    acc[j] = cfma(acc[j], co[j][4], q[j]);
+    ys[j] = cfma(y[j], co[j][2], q[j]);
+  }
+  chi2_products<NF>(ys, q);
+#pragma unroll
+  for (int j = 0; j < NF; ++j) y[j] = cfma(acc[j], co[j][5], q[j]);
+}
+
+// ---------------------------------------------------------------------------
+// One line transform of length N = N1 N2 (N2 divides N1) by N2 threads.
+// Thread t holds x[t + N2 e] in slot e (e < N1).  Stage 1: an N1-point DFT in
+// registers over e, times exp(-+2 pi i t k1 / N).  Exchange through LDS.
+// Stage 2: for each k1 = t + N2 a, an N2-point DFT over the N2 threads' values.
+// The result X[k1 + N1 k2] lands in slot a + (N1/N2) k2, i.e. thread t again
+// holds index t + N2 e in slot e, so the inverse transform starts from the
+// same layout without another exchange.
+// ---------------------------------------------------------------------------
+template <int N1, int N2>
+struct LineGeom {
+  static constexpr int N = N1 * N2;
+  static constexpr int LPB = kBlock / N2;                  // lines per block
+  static constexpr int ROW = (N2 > 1) ? N2 + 1 : 1;        // padded LDS row
+  static constexpr int LS0 = N1 * ROW;
+  static constexpr int LSTRIDE = (N2 > 1) ? (LS0 | 1) : LS0;  // odd stride
+  static constexpr int LDS_ELEMS = (N2 > 1) ? LPB * LSTRIDE : 1;
+};
+
+template <int N1, int N2, bool INV>
+__device__ inline void line_fft(float2 (&v)[N1], int t, float2* lbuf, const float2* tw) {
+  using G = LineGeom<N1, N2>;
+  dft<N1, INV>(v);
+  if constexpr (N2 > 1) {
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) {
+      float2 w = tw[t * k1];
+      if (INV) w.y = -w.y;
+      v[k1] = cmul(v[k1], w);
+    }
+    __syncthreads();  // earlier readers of this block's LDS are done
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) lbuf[k1 * G::ROW + t] = v[k1];
+    __syncthreads();
+    constexpr int R = N1 / N2;
+#pragma unroll
+    for (int a = 0; a < R; ++a) {
+      float2 u[N2];
+      const int k1 = t + N2 * a;
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) u[n2] = lbuf[k1 * G::ROW + n2];
+      dft<N2, INV>(u);
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) v[a + R * k2] = u[k2];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The fused axis pass.  AX selects the line family:
+//   X: line = (y, tau), element stride 1, lanes t-fastest (contiguous loads)
+//   Y: line = (x, tau), element stride nx, lanes x-fastest (coalesced rows)
+//   T: line = (x, y),   element stride nx*ny, lanes (x,y)-fastest
+// NF is the number of fields held by one thread (Y: 1, one field per block).
+// ---------------------------------------------------------------------------
+template <int N1, int N2, int AX, int NF, int NL>
+__global__ __launch_bounds__(kBlock) void axis_pass(PassArgs args) {
+  using G = LineGeom<N1, N2>;
+  constexpr int N = G::N;
+  __shared__ float2 lds[G::LDS_ELEMS];
+
+  const int tid = threadIdx.x;
+  int t, li;
+  long base;
+  long estride;
+  bool valid;
+  float2* fp[NF];
+  if constexpr (AX == AX_X) {
+    t = tid % N2;
+    li = tid / N2;
+    const long line = long(blockIdx.x) * G::LPB + li;
+    valid = line < long(args.ny) * args.nt;
+    base = line * args.nx;
+    estride = 1;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) fp[j] = args.f[j];
+  } else if constexpr (AX == AX_Y) {
+    li = tid % G::LPB;
+    t = tid / G::LPB;
+    const int col = blockIdx.x * G::LPB + li;
+    valid = col < args.nx;
+    base = long(col) + long(args.nx) * args.ny * blockIdx.y;
+    estride = args.nx;
+    fp[0] = args.f[blockIdx.z];
+  } else {
+    li = tid % G::LPB;
+    t = tid / G::LPB;
+    const long q = long(blockIdx.x) * G::LPB + li;
+    valid = q < long(args.nx) * args.ny;
+    base = q;
+    estride = long(args.nx) * args.ny;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) fp[j] = args.f[j];
+  }
+  float2* lbuf = lds + li * G::LSTRIDE;
+
+  float2 v[NF][N1];
+#pragma unroll
+  for (int j = 0; j < NF; ++j) {
+#pragma unroll
+    for (int e = 0; e < N1; ++e)
+      v[j][e] = valid ? fp[j][base + long(t + N2 * e) * estride] : make_float2(0.f, 0.f);
+  }
+
+  if constexpr (NL == NL_BEFORE) {
+    float2 co[NF][kNlCoef];
+#pragma unroll
+    for (int j = 0; j < NF; ++j)
+#pragma unroll
+      for (int c = 0; c < kNlCoef; ++c) co[j][c] = args.nl[j * kNlCoef + c];
+#pragma unroll
+    for (int e = 0; e < N1; ++e) {
+      float2 y[NF];
+#pragma unroll
+      for (int j = 0; j < NF; ++j) y[j] = v[j][e];
+      rk4_point<NF>(y, co);
+#pragma unroll
+      for (int j = 0; j < NF; ++j) v[j][e] = y[j];
+    }
+  }
+
+  const int field0 = (AX == AX_Y) ? int(blockIdx.z) : 0;
+#pragma unroll
+  for (int j = 0; j < NF; ++j) {
+    line_fft<N1, N2, false>(v[j], t, lbuf, args.tw);
+    const float2* pr = args.prop + (field0 + j) * args.field_stride + args.axis_off;
+#pragma unroll
+    for (int e = 0; e < N1; ++e) v[j][e] = cmul(v[j][e], pr[t + N2 * e]);
+    line_fft<N1, N2, true>(v[j], t, lbuf, args.tw);
+    if constexpr (NL != NL_AFTER) {
+      if (valid) {
+#pragma unroll
+        for (int e = 0; e < N1; ++e) fp[j][base + long(t + N2 * e) * estride] = v[j][e];
+      }
+    }
+  }
+
+  if constexpr (NL == NL_AFTER) {
+    float2 co[NF][kNlCoef];
+#pragma unroll
+    for (int j = 0; j < NF; ++j)
+#pragma unroll
+      for (int c = 0; c < kNlCoef; ++c) co[j][c] = args.nl[j * kNlCoef + c];
+#pragma unroll
+    for (int e = 0; e < N1; ++e) {
+      float2 y[NF];
+#pragma unroll
+      for (int j = 0; j < NF; ++j) y[j] = v[j][e];
+      rk4_point<NF>(y, co);
+#pragma unroll
+      for (int j = 0; j < NF; ++j) v[j][e] = y[j];
+    }
+    if (valid) {
+#pragma unroll
+      for (int j = 0; j < NF; ++j)
+#pragma unroll
+        for (int e = 0; e < N1; ++e) fp[j][base + long(t + N2 * e) * estride] = v[j][e];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-step tables, formed in double precision.
+//
+// Propagator of field j along one axis for step n (z_n = n dz):
+//   P_n(k) = s * U(z_{n+1}, k) * conj(U(z_n, k)),   U(z, k) = fl32(exp(i phi(k) z))
+// with phi the imaginary part of that axis's share of the symbol Lambda_j,
+// the phase reduced mod 2 pi in double before the sine and cosine, and s the
+// 1/N normalisation (times exp(-alpha dz/2) on the tau axis).  Because U is
+// rounded at every z_n separately, the phase rounding errors of consecutive
+// steps cancel (a telescoping product) instead of accumulating coherently.
+//
+// RK4 coefficients of the two half-steps of step n (see rk4_point), with
+// Phi(z) = Phi_n + dk_n (z - z_n) the integrated mismatch.
+// ---------------------------------------------------------------------------
+struct FieldCoef {
+  double kappa, diffraction, tan_rho, delay, k2, k3, alpha;
+};
+
+struct TableArgs {
+  float2* prop;          // [count][nf][nx + ny + nt]
+  float2* nl;            // [count][2][nf][6]
+  const double* phi0;    // Phi_n prefix (profile) or null
+  const double* dk;      // dk_n (profile) or null
+  long n0;
+  int count;
+  int nx, ny, nt, nf;
+  double dz, dx, dy, dt, dk_const;
+  FieldCoef fc[3];
+};
+
+__device__ inline double reduce_2pi(double a) {
+  const double two_pi = 6.283185307179586476925286766559;
+  double r = fmod(a, two_pi);
+  return r < 0.0 ? r + two_pi : r;
+}
+
+__device__ inline double ang_freq(int m, int n, double d) {
+  const int mm = (m >= (n + 1) / 2) ? m - n : m;
+  return 6.283185307179586476925286766559 * double(mm) / (double(n) * d);
+}
+
+__device__ inline double2 rounded_unit(double theta) {
+  double s, c;
+  sincos(reduce_2pi(theta), &s, &c);
+  return make_double2(double(float(c)), double(float(s)));
+}
+
+__global__ void step_tables(TableArgs a) {
+  const int per_field = a.nx + a.ny + a.nt;
+  const int per_step = a.nf * per_field;
+  const long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long nprop = long(a.count) * per_step;
+  if (gid < nprop) {
+    const int s = int(gid / per_step);
+    const int r = int(gid % per_step);
+    const int j = r / per_field;
+    int m = r % per_field;
+    const FieldCoef& f = a.fc[j];
+    const long n = a.n0 + s;
+    double phi, scale;
+    if (m < a.nx) {
+      const double kx = ang_freq(m, a.nx, a.dx);
+      phi = -f.diffraction * kx * kx - f.tan_rho * kx;
+      scale = 1.0 / a.nx;
+    } else if (m < a.nx + a.ny) {
+      m -= a.nx;
+      const double ky = ang_freq(m, a.ny, a.dy);
+      phi = -f.diffraction * ky * ky;
+      scale = 1.0 / a.ny;
+    } else {
+      m -= a.nx + a.ny;
+      const double w = ang_freq(m, a.nt, a.dt);
+      phi = -f.delay * w + 0.5 * f.k2 * w * w - (f.k3 / 6.0) * w * w * w;
+      scale = exp(-0.5 * f.alpha * a.dz) / a.nt;
+    }
+    const double2 u1 = rounded_unit(phi * (double(n + 1) * a.dz));
+    const double2 u0 = rounded_unit(phi * (double(n) * a.dz));
+    const double re = (u1.x * u0.x + u1.y * u0.y) * scale;
+    const double im = (u1.y * u0.x - u1.x * u0.y) * scale;
+    a.prop[gid] = make_float2(float(re), float(im));
+    return;
+  }
+  const long g2 = gid - nprop;
+  const long nco = long(a.count) * 2 * a.nf;
+  if (g2 >= nco) return;
+  const int s = int(g2 / (2 * a.nf));
+  const int half = int((g2 / a.nf) % 2);
+  const int j = int(g2 % a.nf);
+  const long n = a.n0 + s;
+  double phi_n, dkn;
+  if (a.dk != nullptr) {
+    phi_n = a.phi0[n];
+    dkn = a.dk[n];
+  } else {
+    dkn = a.dk_const;
+    phi_n = dkn * (double(n) * a.dz);
+  }
+  // sigma_j: exp(-i Phi) on the sum-frequency field, exp(+i Phi) on the others
+  double sigma;
+  if (a.nf == 3) sigma = (j == 0) ? -1.0 : 1.0;
+  else sigma = (j == 0) ? 1.0 : -1.0;
+  const double h = 0.5 * a.dz;
+  const double kap = a.fc[j].kappa;
+  double2 c[3];  // c_j at z_a, z_a + h/2, z_a + h
+  for (int k = 0; k < 3; ++k) {
+    const double off = (double(half) * 2.0 + double(k)) * 0.25 * a.dz;  // z - z_n
+    const double ph = reduce_2pi(phi_n + dkn * off);
+    double sn, cs;
+    sincos(ph, &sn, &cs);
+    // i kappa (cos + i sigma sin) = kappa (-sigma sin + i cos)
+    c[k] = make_double2(-kap * sigma * sn, kap * cs);
+  }
+  const double w[6] = {h / 2, h / 2, h, h / 6, h / 3, h / 6};
+  const int which[6] = {0, 1, 1, 0, 1, 2};
+  float2* out = a.nl + g2 * kNlCoef;
+  for (int k = 0; k < 6; ++k)
+    out[k] = make_float2(float(w[k] * c[which[k]].x), float(w[k] * c[which[k]].y));
+}
+
+// Set a flag when any field value is not finite (the step-size hazard of
+// Sec. 3.2: a too-large dz makes the nonlinear increment blow up).
+__global__ void finite_check(const float2* f, long n, int* flag) {
+  long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long stride = long(gridDim.x) * blockDim.x;
+  int bad = 0;
+  for (; i < n; i += stride) {
+    const float2 v = f[i];
+    bad |= !(isfinite(v.x) && isfinite(v.y));
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+}  // namespace brahms

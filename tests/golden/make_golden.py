@@ -1,0 +1,86 @@
+"""Write oracle reference data for the large parity workloads.
+
+Runs only the FP64 oracle (oracle/ssfm.py) on the seeded complex64 entrance
+fields of a workload and stores, per field:
+  * the complex values at 4096 seeded uniformly random grid points and at the
+    4096 points of largest oracle amplitude,
+  * the power trace P(tau) = sum_xy |A|^2 (the output quantity of Sec. 6),
+  * the fluence map sum_tau |A|^2 summed over 4 x 4 transverse blocks,
+  * the energies and Manley-Rowe combinations.
+Usage: python -m tests.golden.make_golden <workload> [nsteps] [threads]
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from oracle import ssfm  # noqa: E402
+from paper_2609_08384_amd import inputs  # noqa: E402
+from tests.util import oracle_problem, to_torch  # noqa: E402
+
+WORKLOADS = {"sfg128": inputs.sfg128, "opg256": inputs.opg256, "shg_adjoint": inputs.shg_adjoint,
+             "shg32": inputs.shg32}
+NSAMPLE = 4096
+
+
+def sample_points(shape, seed=1234):
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(shape))
+    return np.sort(rng.choice(n, size=min(NSAMPLE, n), replace=False))
+
+
+def summarize(fields, prob):
+    out = {}
+    nt, ny, nx = fields[0].shape
+    uni = sample_points((nt, ny, nx))
+    out["uniform_idx"] = uni
+    for j, a in enumerate(fields):
+        flat = a.reshape(-1)
+        out[f"f{j}_uniform"] = flat[uni].numpy()
+        top = torch.topk(flat.abs(), min(NSAMPLE, flat.numel())).indices.sort().values
+        out[f"f{j}_top_idx"] = top.numpy()
+        out[f"f{j}_top"] = flat[top].numpy()
+        inten = a.abs() ** 2
+        out[f"f{j}_power"] = inten.sum(dim=(1, 2)).numpy()
+        flu = inten.sum(dim=0)
+        by, bx = max(1, ny // 64), max(1, nx // 64)
+        out[f"f{j}_fluence"] = flu.reshape(ny // by, by, nx // bx, bx).sum(dim=(1, 3)).numpy()
+    out["energies"] = np.array(ssfm.energies(fields, prob))
+    out["manley_rowe"] = np.array(ssfm.manley_rowe(fields, prob))
+    return out
+
+
+def main():
+    name = sys.argv[1]
+    wl = WORKLOADS[name]()
+    nsteps = int(sys.argv[2]) if len(sys.argv) > 2 else wl.nz
+    if len(sys.argv) > 3:
+        torch.set_num_threads(int(sys.argv[3]))
+    prob = oracle_problem(wl)
+    orc = ssfm.Oracle(prob)
+    a = [to_torch(x) for x in wl.init]
+    mr0 = np.array(ssfm.manley_rowe(a, prob))
+    t0 = time.time()
+    for n in range(nsteps):
+        a = orc.step(a, n)
+        if n % 10 == 9 or n == nsteps - 1:
+            print(f"{name}: step {n + 1}/{nsteps} {time.time() - t0:.0f}s", flush=True)
+    res = summarize(a, prob)
+    res["manley_rowe_in"] = mr0
+    res["nsteps"] = np.array(nsteps)
+    path = os.path.join(HERE, f"{name}_{nsteps}.npz")
+    np.savez_compressed(path, **res)
+    print("wrote", path, flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,174 @@
+"""GPU parity: the HIP engine (through the C ABI) against the FP64 oracle on
+the same seeded complex64 inputs.  Tolerances are relative L2 per field."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ssfm
+from paper_2609_08384_amd import brahms, inputs
+from tests.util import oracle_problem, rel_l2, to_torch
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+EPS32 = 2.0 ** -24
+
+
+def _accumulation_bound(n_updates, scale):
+    """Worst case of storing a complex64 state after each of n_updates
+    increments: n_updates half-ulps (sqrt 2 for complex) of the largest
+    magnitude reached.  Constant increments (plane waves) make these
+    rounding errors coherent, so this, not sqrt(n), is the bound to test."""
+    return n_updates * EPS32 * math.sqrt(2.0) * scale
+
+
+def _wl(nx, ny, nt, nf, nz, dz, fields, dk_const=0.0, dk=None, init=None):
+    wl = inputs.Workload("case", nx, ny, nt, nf, nz, dz, fields, dk_const=dk_const, dk=dk)
+    wl.init = init
+    return wl
+
+
+def _gpu(wl, nsteps=None):
+    out = brahms.run_workload(wl, nsteps=nsteps, device=DEV)
+    return [f.cpu().numpy() for f in out]
+
+
+def _oracle(wl, nsteps=None):
+    nsteps = wl.nz if nsteps is None else nsteps
+    out = ssfm.propagate([to_torch(a) for a in wl.init], oracle_problem(wl), nsteps)
+    return [a.numpy() for a in out]
+
+
+def _all_terms(nf, scale=1.0, kappa=0.0):
+    base = [dict(diffraction=1.7, tan_rho=0.9, delay=-1.3, k2=2.1, k3=0.7, alpha=0.2),
+            dict(diffraction=0.8, tan_rho=-0.4, delay=0.6, k2=-1.5, k3=-0.3, alpha=0.0),
+            dict(diffraction=2.6, tan_rho=0.2, delay=1.1, k2=0.9, k3=0.2, alpha=0.1)]
+    return [inputs.FieldSpec(kappa=kappa * (1 - 0.2 * j), **{k: v * scale for k, v in base[j].items()})
+            for j in range(nf)]
+
+
+SHAPES = [(32, 16, 8), (16, 32, 64), (64, 8, 4), (96, 64, 2), (128, 4, 16), (256, 2, 1),
+          (1, 1, 256), (8, 256, 1), (4, 96, 32), (2, 128, 8), (1, 4, 128), (128, 96, 96)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_linear_step_each_axis_length(shape):
+    """kappa = 0: one step is the linear step alone (FFT, propagator, inverse)."""
+    nx, ny, nt = shape
+    rng = np.random.default_rng(sum(shape))
+    init = inputs.random_fields(rng, 3, nx, ny, nt)
+    wl = _wl(nx, ny, nt, 3, 1, 0.05, _all_terms(3), init=init)
+    g, o = _gpu(wl), _oracle(wl)
+    for j in range(3):
+        assert rel_l2(g[j], o[j]) < 2e-6, (shape, j)
+
+
+def test_plane_wave_depleted_shg():
+    """Uniform fields: only the k = 0 mode, so the loop is the RK4 half-steps
+    alone; depleted SHG has F = F0 sech(G z), S = i sqrt(kS/kF) F0 tanh(G z)."""
+    kf, ks, f0, nz = 1.3, 0.6, 1.5, 100
+    init = [np.full((4, 4, 4), f0, np.complex64), np.zeros((4, 4, 4), np.complex64)]
+    wl = _wl(4, 4, 4, 2, nz, 1.0 / nz, [inputs.FieldSpec(kappa=kf), inputs.FieldSpec(kappa=ks)], init=init)
+    f, s = _gpu(wl)
+    g = math.sqrt(kf * ks) * f0
+    bound = _accumulation_bound(2 * nz, f0)
+    assert np.abs(f - f0 / math.cosh(g)).max() < bound
+    assert np.abs(s - 1j * math.sqrt(ks / kf) * f0 * math.tanh(g)).max() < bound
+
+
+@pytest.mark.parametrize("dk", [0.0, 3.0, -7.5])
+def test_plane_wave_undepleted_shg_sinc(dk):
+    f0, ks, nz = 0.8 + 0.3j, 1.7, 100
+    init = [np.full((2, 2, 2), f0, np.complex64), np.zeros((2, 2, 2), np.complex64)]
+    wl = _wl(2, 2, 2, 2, nz, 1.0 / nz, [inputs.FieldSpec(kappa=0.0), inputs.FieldSpec(kappa=ks)],
+             dk_const=dk, init=init)
+    f, s = _gpu(wl)
+    integral = 1.0 if dk == 0 else (1 - np.exp(-1j * dk)) / (1j * dk)
+    want = 1j * ks * complex(np.complex64(f0)) ** 2 * integral
+    bound = _accumulation_bound(2 * nz, ks * abs(f0) ** 2) + 1e-7
+    assert np.abs(s - want).max() < bound
+
+
+def test_plane_wave_opa():
+    ap, as0, ks, ki, nz = 1.2 * np.exp(0.4j), 0.01 - 0.02j, 1.5, 0.9, 100
+    init = [np.full((2, 4, 2), ap, np.complex64), np.full((2, 4, 2), as0, np.complex64),
+            np.zeros((2, 4, 2), np.complex64)]
+    wl = _wl(2, 4, 2, 3, nz, 1.0 / nz, [inputs.FieldSpec(kappa=0.0), inputs.FieldSpec(kappa=ks),
+                                         inputs.FieldSpec(kappa=ki)], init=init)
+    p, s, i = _gpu(wl)
+    ap, as0 = complex(np.complex64(ap)), complex(np.complex64(as0))
+    g = math.sqrt(ks * ki) * abs(ap)
+    ws = as0 * math.cosh(g)
+    wi = 1j * ki * ap * np.conj(as0) * math.sinh(g) / g
+    assert np.abs(s - ws).max() < _accumulation_bound(2 * nz, abs(ws)) + 1e-7 * abs(ws)
+    assert np.abs(i - wi).max() < _accumulation_bound(2 * nz, abs(wi)) + 1e-7 * abs(wi)
+
+
+@pytest.mark.parametrize("nf,shape", [(2, (32, 32, 32)), (3, (32, 32, 32)), (3, (64, 16, 96)),
+                                      (2, (96, 96, 4)), (3, (16, 128, 64))])
+def test_coupled_steps_random(nf, shape):
+    """All linear terms and the chi(2) coupling, 10 steps, ragged tiles."""
+    nx, ny, nt = shape
+    rng = np.random.default_rng(100 + nf)
+    init = inputs.random_fields(rng, nf, nx, ny, nt, scale=0.7, smooth=min(nx, ny, nt) / 2.0)
+    wl = _wl(nx, ny, nt, nf, 10, 0.02, _all_terms(nf, kappa=1.5), dk_const=2.3, init=init)
+    g, o = _gpu(wl), _oracle(wl)
+    for j in range(nf):
+        assert rel_l2(g[j], o[j]) < 5e-6, j
+
+
+def test_dk_profile_matches_oracle():
+    rng = np.random.default_rng(9)
+    nx = ny = nt = 16
+    init = inputs.random_fields(rng, 2, nx, ny, nt, scale=0.8, smooth=6.0)
+    dk = 2.0 + rng.standard_normal(40)
+    wl = _wl(nx, ny, nt, 2, 40, 0.025, _all_terms(2, kappa=1.0), dk=dk, init=init)
+    g, o = _gpu(wl), _oracle(wl)
+    for j in range(2):
+        assert rel_l2(g[j], o[j]) < 5e-6
+
+
+def test_shg32_full_run():
+    """SHG 32^3, 100 steps (the small benchmark workload): <= 1e-5 per field."""
+    wl = inputs.shg32()
+    g, o = _gpu(wl), _oracle(wl)
+    for j in range(2):
+        assert rel_l2(g[j], o[j]) < 1e-5, j
+
+
+def test_deterministic_and_resumable():
+    """Two identical runs agree bitwise (no races, no atomics in the step),
+    and 30 + 20 steps through set_z equal 50 steps in one call."""
+    wl = inputs.shg32()
+    a = _gpu(wl, 50)
+    b = _gpu(wl, 50)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+    fields = [torch.from_numpy(x).to(DEV) for x in wl.init]
+    plan = brahms.Plan(wl.nx, wl.ny, wl.nt, wl.nf, brahms.params_from_workload(wl)).bind(fields)
+    plan.propagate(30 * wl.dz)
+    saved = [f.clone() for f in fields]
+    plan.destroy()
+    plan2 = brahms.Plan(wl.nx, wl.ny, wl.nt, wl.nf, brahms.params_from_workload(wl)).bind(saved)
+    plan2.set_z(30 * wl.dz)
+    assert abs(plan2.z - 0.3) < 1e-12
+    plan2.propagate(0.5)
+    torch.cuda.synchronize()
+    for x, y in zip(saved, a):
+        assert np.array_equal(x.cpu().numpy().view(np.uint8), y.view(np.uint8))
+
+
+def test_nonfinite_detected():
+    """A dz far too large for kappa |A| (Sec. 3.2) blows the fields up; with
+    BRAHMS_CHECK_FINITE the call reports E_NONFINITE."""
+    init = [np.full((8, 8, 8), 30.0, np.complex64), np.full((8, 8, 8), 30.0, np.complex64)]
+    p = brahms.Params(dz=0.5, fields=[brahms.FieldParams(kappa=50.0), brahms.FieldParams(kappa=50.0)],
+                      check_finite=True)
+    fields = [torch.from_numpy(a).to(DEV) for a in init]
+    plan = brahms.Plan(8, 8, 8, 2, p).bind(fields)
+    with pytest.raises(brahms.BrahmsError) as ei:
+        plan.step(40)
+    assert ei.value.status == brahms.BRAHMS_E_NONFINITE
+    plan.destroy()
