@@ -5,9 +5,10 @@
 //   inverse  V[k] = sum_n v[n] exp(+2 pi i n k / N)   (unnormalised)
 // N is a compile-time product of 2s and 3s.  Every loop is fully unrolled and
 // every index is a compile-time constant, so the arrays live in registers and
-// the twiddle constants fold into literals.  The roots of unity are evaluated
-// at compile time in double precision (exact quadrant symmetry plus a Taylor
-// series on at most a half quadrant) and rounded once to float.
+// the choice of each twiddle operation folds at compile time; the irrational
+// constants are uniform run-time values (DftConsts).  unit_root evaluates
+// roots of unity in double precision (exact quadrant symmetry plus a Taylor
+// series on at most a half quadrant) for the host-side tables.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -57,25 +58,6 @@ constexpr void unit_root(long m, long n, double& c, double& s) {
   }
 }
 
-template <int N>
-struct RootTable {
-  float c[N];
-  float s[N];
-  constexpr RootTable() : c(), s() {
-    for (int m = 0; m < N; ++m) {
-      double cc = 0.0, ss = 0.0;
-      unit_root(m, N, cc, ss);
-      c[m] = float(cc);
-      s[m] = float(ss);
-    }
-  }
-};
-
-template <int N>
-struct Roots {
-  static constexpr RootTable<N> table{};
-};
-
 __host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __host__ __device__ inline float2 cmul(float2 a, float2 b) {
@@ -90,39 +72,62 @@ __host__ __device__ inline float2 rot_quarter(float2 a) {
   return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
 }
 
-// a * exp(-+ 2 pi i m / N) with m a compile-time constant after unrolling;
-// trivial rotations cost no multiplies.
+// The irrational constants the register DFTs need (radices 2, 3, 4, 6, 8,
+// 12, 16, 24 all divide 48, so every root is a multiple of 2 pi / 48 and
+// reduces by exact quadrant symmetry to one of these first-quadrant values).
+// They are run-time values supplied per z-step: rounding them afresh at every
+// step (stochastically, from a double-precision value) keeps their rounding
+// errors independent from step to step, so the errors of repeated transform
+// round trips grow like sqrt(steps) instead of linearly.
+struct DftConsts {
+  float h;         // cos(pi/4) = sin(pi/4)
+  float c8, s8;    // cos(pi/8), sin(pi/8)
+  float r3;        // cos(pi/6) = sin(pi/3)
+  float c12, s12;  // cos(pi/12), sin(pi/12)
+  float pad0, pad1;
+};
+
+// a * exp(-+ 2 pi i m / N) with m a compile-time constant after unrolling
+// (every branch below folds away); quarter turns cost no multiplies.
 template <int N, bool INV>
-__host__ __device__ inline float2 twiddle_const(float2 a, int m) {
+__host__ __device__ inline float2 twiddle_const(float2 a, int m, const DftConsts& K) {
+  static_assert(48 % N == 0, "register DFT radices must divide 48");
   m %= N;
   if (m == 0) return a;
-  if ((4 * m) % N == 0) {
-    int q = (4 * m) / N;  // exp(-i q pi/2)
-    if (q == 2) return make_float2(-a.x, -a.y);
-    if (q == 1) return rot_quarter<INV>(a);
-    return rot_quarter<!INV>(a);
+  const int r = m * (48 / N);   // angle in units of 2 pi / 48
+  const int q = r / 12;         // quarter turns
+  const int rem = r % 12;       // remaining angle in units of pi / 24
+  float2 b = a;
+  if (rem != 0) {
+    float c = 0.f, s = 0.f;
+    if (rem == 6) {
+      // exp(-+i pi/4) = h (1 -+ i)
+      b = INV ? make_float2(K.h * (a.x - a.y), K.h * (a.x + a.y))
+              : make_float2(K.h * (a.x + a.y), K.h * (a.y - a.x));
+    } else {
+      switch (rem) {
+        case 2: c = K.c12; s = K.s12; break;
+        case 3: c = K.c8; s = K.s8; break;
+        case 4: c = K.r3; s = 0.5f; break;
+        case 8: c = 0.5f; s = K.r3; break;
+        case 9: c = K.s8; s = K.c8; break;
+        default: c = K.s12; s = K.c12; break;  // rem == 10
+      }
+      if (!INV) s = -s;
+      b = make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+    }
   }
-  if ((8 * m) % N == 0) {
-    // odd multiple of pi/4: exp(-+i o pi/4) = (+-1 +- i) / sqrt(2)
-    const float h = 0.70710678118654752440f;
-    int o = (8 * m) / N;  // 1, 3, 5, 7
-    float c = (o == 1 || o == 7) ? h : -h;
-    float s = (o == 1 || o == 3) ? h : -h;  // sin(o pi/4)
-    if (!INV) s = -s;
-    // (a.x + i a.y)(c + i s) with |c| = |s| = h
-    float p = a.x * c, q = a.y * s, r = a.x * s, u = a.y * c;
-    return make_float2(p - q, r + u);
-  }
-  const float c = Roots<N>::table.c[m];
-  const float s = INV ? Roots<N>::table.s[m] : -Roots<N>::table.s[m];
-  return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+  if (q == 1) return rot_quarter<INV>(b);
+  if (q == 2) return make_float2(-b.x, -b.y);
+  if (q == 3) return rot_quarter<!INV>(b);
+  return b;
 }
 
 template <int N, bool INV>
 struct Dft {
   static constexpr int P = (N % 4 == 0 && N > 4) ? 4 : ((N % 2 == 0) ? 2 : 3);
   static constexpr int Q = N / P;
-  __host__ __device__ static inline void run(float2* v) {
+  __host__ __device__ static inline void run(float2* v, const DftConsts& K) {
     // n = Q n1 + n2, k = k1 + P k2
     float2 y[N];
 #pragma unroll
@@ -130,16 +135,16 @@ struct Dft {
       float2 u[P];
 #pragma unroll
       for (int n1 = 0; n1 < P; ++n1) u[n1] = v[Q * n1 + n2];
-      Dft<P, INV>::run(u);
+      Dft<P, INV>::run(u, K);
 #pragma unroll
-      for (int k1 = 0; k1 < P; ++k1) y[n2 * P + k1] = twiddle_const<N, INV>(u[k1], n2 * k1);
+      for (int k1 = 0; k1 < P; ++k1) y[n2 * P + k1] = twiddle_const<N, INV>(u[k1], n2 * k1, K);
     }
 #pragma unroll
     for (int k1 = 0; k1 < P; ++k1) {
       float2 w[Q];
 #pragma unroll
       for (int n2 = 0; n2 < Q; ++n2) w[n2] = y[n2 * P + k1];
-      Dft<Q, INV>::run(w);
+      Dft<Q, INV>::run(w, K);
 #pragma unroll
       for (int k2 = 0; k2 < Q; ++k2) v[k1 + P * k2] = w[k2];
     }
@@ -148,12 +153,12 @@ struct Dft {
 
 template <bool INV>
 struct Dft<1, INV> {
-  __host__ __device__ static inline void run(float2*) {}
+  __host__ __device__ static inline void run(float2*, const DftConsts&) {}
 };
 
 template <bool INV>
 struct Dft<2, INV> {
-  __host__ __device__ static inline void run(float2* v) {
+  __host__ __device__ static inline void run(float2* v, const DftConsts&) {
     float2 a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
@@ -162,8 +167,8 @@ struct Dft<2, INV> {
 
 template <bool INV>
 struct Dft<3, INV> {
-  __host__ __device__ static inline void run(float2* v) {
-    const float h = 0.86602540378443864676f;  // sin(2 pi/3)
+  __host__ __device__ static inline void run(float2* v, const DftConsts& K) {
+    const float h = K.r3;  // sin(2 pi/3)
     float2 a = v[0];
     float2 t1 = cadd(v[1], v[2]);
     float2 t2 = csub(v[1], v[2]);
@@ -183,7 +188,7 @@ struct Dft<3, INV> {
 
 template <bool INV>
 struct Dft<4, INV> {
-  __host__ __device__ static inline void run(float2* v) {
+  __host__ __device__ static inline void run(float2* v, const DftConsts&) {
     float2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
     float2 s13 = cadd(v[1], v[3]), d13 = csub(v[1], v[3]);
     float2 r = rot_quarter<INV>(d13);  // -i d13 forward, +i d13 inverse
@@ -195,6 +200,6 @@ struct Dft<4, INV> {
 };
 
 template <int N, bool INV>
-__host__ __device__ inline void dft(float2* v) { Dft<N, INV>::run(v); }
+__host__ __device__ inline void dft(float2* v, const DftConsts& K) { Dft<N, INV>::run(v, K); }
 
 }  // namespace brahms

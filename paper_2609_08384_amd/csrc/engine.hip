@@ -65,7 +65,6 @@ struct brahms_plan_s {
   bool bound = false;
   long long step = 0;          // z = step * dz
   // workspace offsets (bytes)
-  size_t off_tw[3] = {0, 0, 0};
   size_t off_phi0 = 0, off_dk = 0, off_prop = 0, off_nl = 0, off_flag = 0, ws_size = 0;
   // launch timing (diagnostics)
   bool timing = false;
@@ -132,33 +131,17 @@ bool finite_params(const brahms_params* pr, int nf) {
 
 void layout(brahms_plan_s& p) {
   size_t off = 0;
-  const int n[3] = {p.nx, p.ny, p.nt};
-  for (int a = 0; a < 3; ++a) {
-    p.off_tw[a] = off;
-    off = align_up(off + sizeof(float2) * size_t(n[a]));
-  }
   p.off_phi0 = off;
   off = align_up(off + sizeof(double) * (p.dk.size() + 1));
   p.off_dk = off;
   off = align_up(off + sizeof(double) * (p.dk.size() + 1));
   p.off_prop = off;
-  off = align_up(off + sizeof(float2) * size_t(kChunk) * p.nf * (p.nx + p.ny + p.nt));
+  off = align_up(off + sizeof(float2) * size_t(kChunk) * table_row_stride(p.nf, p.nx, p.ny, p.nt));
   p.off_nl = off;
   off = align_up(off + sizeof(float2) * size_t(kChunk) * 2 * p.nf * kNlCoef);
   p.off_flag = off;
   off = align_up(off + sizeof(int));
   p.ws_size = off;
-}
-
-std::vector<float2> forward_twiddles(int n) {
-  std::vector<float2> tw(n);
-  for (int m = 0; m < n; ++m) {
-    // exp(-2 pi i m / n) evaluated in double, reduced exactly by symmetry
-    double c = 0.0, s = 0.0;
-    unit_root(m, n, c, s);
-    tw[m] = make_float2(float(c), float(-s));
-  }
-  return tw;
 }
 
 brahms_status check_plan(brahms_plan p) {
@@ -200,6 +183,7 @@ brahms_status timing_stop(brahms_plan_s& p) {
 
 brahms_status run_steps(brahms_plan_s& p, int nsteps) {
   const int per_field = p.nx + p.ny + p.nt;
+  const int row_stride = table_row_stride(p.nf, p.nx, p.ny, p.nt);
   float2* prop = reinterpret_cast<float2*>(p.ws + p.off_prop);
   float2* nl = reinterpret_cast<float2*>(p.ws + p.off_nl);
   const int n[3] = {p.nx, p.ny, p.nt};
@@ -207,7 +191,8 @@ brahms_status run_steps(brahms_plan_s& p, int nsteps) {
   while (done < nsteps) {
     const int count = std::min(kChunk, nsteps - done);
     TableArgs ta{};
-    ta.prop = prop;
+    ta.rows = prop;
+    ta.row_stride = row_stride;
     ta.nl = nl;
     ta.phi0 = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_phi0);
     ta.dk = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_dk);
@@ -219,7 +204,7 @@ brahms_status run_steps(brahms_plan_s& p, int nsteps) {
       const brahms_field_params& f = p.fp[j];
       ta.fc[j] = FieldCoef{f.kappa, f.diffraction, f.tan_rho, f.delay, f.k2, f.k3, f.alpha};
     }
-    const long total = long(count) * p.nf * per_field + long(count) * 2 * p.nf;
+    const long total = long(count) * ((p.nf + 1) * per_field + 1) + long(count) * 2 * p.nf;
     const bool timed_tab = p.timing && p.timed.size() < kMaxTimed;
     if (brahms_status st = timing_start(p, 3)) return st;
     hipLaunchKernelGGL(step_tables, dim3(unsigned((total + 255) / 256)), dim3(256), 0, p.stream, ta);
@@ -227,16 +212,16 @@ brahms_status run_steps(brahms_plan_s& p, int nsteps) {
     if (timed_tab)
       if (brahms_status st = timing_stop(p)) return st;
     for (int s = 0; s < count; ++s) {
-      const float2* row = prop + size_t(s) * p.nf * per_field;
-      // tables of one step: [nf][nx | ny | nt]
+      const float2* row = prop + size_t(s) * row_stride;
       for (int ax = 0; ax < 3; ++ax) {
         PassArgs a{};
         for (int j = 0; j < 3; ++j) a.f[j] = p.fields[j];
-        a.tw = reinterpret_cast<const float2*>(p.ws + p.off_tw[ax]);
+        a.axis_off = (ax == AX_X) ? 0 : (ax == AX_Y ? p.nx : p.nx + p.ny);
+        a.tw = row + p.nf * per_field + a.axis_off;
+        a.consts = reinterpret_cast<const DftConsts*>(row + (p.nf + 1) * per_field);
         a.nx = p.nx; a.ny = p.ny; a.nt = p.nt;
         a.nl = nl + (size_t(s) * 2 + (ax == AX_X ? 0 : 1)) * p.nf * kNlCoef;
         a.prop = row;
-        a.axis_off = (ax == AX_X) ? 0 : (ax == AX_Y ? p.nx : p.nx + p.ny);
         a.field_stride = per_field;
         const bool timed = p.timing && p.timed.size() < kMaxTimed;
         if (brahms_status st = timing_start(p, ax)) return st;
@@ -321,13 +306,6 @@ brahms_status brahms_plan_bind(brahms_plan plan, void* const* fields, void* work
   plan->bound = false;
   for (int j = 0; j < 3; ++j) plan->fields[j] = j < plan->nf ? static_cast<float2*>(fields[j]) : nullptr;
   plan->ws = static_cast<char*>(workspace);
-  const int n[3] = {plan->nx, plan->ny, plan->nt};
-  for (int a = 0; a < 3; ++a) {
-    std::vector<float2> tw = forward_twiddles(n[a]);
-    HIP_TRY(hipMemcpyAsync(plan->ws + plan->off_tw[a], tw.data(), sizeof(float2) * tw.size(),
-                           hipMemcpyHostToDevice, plan->stream));
-    HIP_TRY(hipStreamSynchronize(plan->stream));  // tw is a host temporary
-  }
   if (!plan->dk.empty()) {
     HIP_TRY(hipMemcpyAsync(plan->ws + plan->off_phi0, plan->phi0.data(),
                            sizeof(double) * plan->phi0.size(), hipMemcpyHostToDevice, plan->stream));

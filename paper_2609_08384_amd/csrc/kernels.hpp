@@ -31,10 +31,11 @@ enum NlMode { NL_NONE = 0, NL_BEFORE = 1, NL_AFTER = 2 };
 
 struct PassArgs {
   float2* f[3];          // field base pointers (complex64, [nt][ny][nx])
-  const float2* tw;      // forward twiddles exp(-2 pi i m / N), m < N, this axis
-  const float2* prop;    // per-step propagators, field j's table of this
+  const float2* tw;      // this step's forward twiddles exp(-2 pi i m / N), m < N
+  const float2* prop;    // this step's propagators, field j's table of this
                          // axis at prop + j * field_stride + axis_off
   const float2* nl;      // RK4 coefficients of this half-step, [nf][6]
+  const DftConsts* consts;  // this step's register-DFT constants
   int nx, ny, nt;
   int axis_off, field_stride;
 };
@@ -112,9 +113,10 @@ struct LineGeom {
 };
 
 template <int N1, int N2, bool INV>
-__device__ inline void line_fft(float2 (&v)[N1], int t, float2* lbuf, const float2* tw) {
+__device__ inline void line_fft(float2 (&v)[N1], int t, float2* lbuf, const float2* tw,
+                                const DftConsts& K) {
   using G = LineGeom<N1, N2>;
-  dft<N1, INV>(v);
+  dft<N1, INV>(v, K);
   if constexpr (N2 > 1) {
 #pragma unroll
     for (int k1 = 1; k1 < N1; ++k1) {
@@ -133,7 +135,7 @@ __device__ inline void line_fft(float2 (&v)[N1], int t, float2* lbuf, const floa
       const int k1 = t + N2 * a;
 #pragma unroll
       for (int n2 = 0; n2 < N2; ++n2) u[n2] = lbuf[k1 * G::ROW + n2];
-      dft<N2, INV>(u);
+      dft<N2, INV>(u, K);
 #pragma unroll
       for (int k2 = 0; k2 < N2; ++k2) v[a + R * k2] = u[k2];
     }
@@ -187,6 +189,7 @@ __global__ __launch_bounds__(kBlock) void axis_pass(PassArgs args) {
     for (int j = 0; j < NF; ++j) fp[j] = args.f[j];
   }
   float2* lbuf = lds + li * G::LSTRIDE;
+  const DftConsts K = *args.consts;
 
   float2 v[NF][N1];
 #pragma unroll
@@ -216,11 +219,11 @@ __global__ __launch_bounds__(kBlock) void axis_pass(PassArgs args) {
   const int field0 = (AX == AX_Y) ? int(blockIdx.z) : 0;
 #pragma unroll
   for (int j = 0; j < NF; ++j) {
-    line_fft<N1, N2, false>(v[j], t, lbuf, args.tw);
+    line_fft<N1, N2, false>(v[j], t, lbuf, args.tw, K);
     const float2* pr = args.prop + (field0 + j) * args.field_stride + args.axis_off;
 #pragma unroll
     for (int e = 0; e < N1; ++e) v[j][e] = cmul(v[j][e], pr[t + N2 * e]);
-    line_fft<N1, N2, true>(v[j], t, lbuf, args.tw);
+    line_fft<N1, N2, true>(v[j], t, lbuf, args.tw, K);
     if constexpr (NL != NL_AFTER) {
       if (valid) {
 #pragma unroll
@@ -264,24 +267,36 @@ __global__ __launch_bounds__(kBlock) void axis_pass(PassArgs args) {
 // rounded at every z_n separately, the phase rounding errors of consecutive
 // steps cancel (a telescoping product) instead of accumulating coherently.
 //
-// RK4 coefficients of the two half-steps of step n (see rk4_point), with
-// Phi(z) = Phi_n + dk_n (z - z_n) the integrated mismatch.
+// The transform twiddles, the register-DFT constants and the RK4
+// coefficients (see rk4_point; Phi(z) = Phi_n + dk_n (z - z_n) is the
+// integrated mismatch) are rounded to float stochastically, with a
+// counter-based hash of (step, entry) as the random source, so that their
+// rounding errors are independent from one z-step to the next; a fixed
+// rounding would repeat the same error every step and add up linearly.
+//
+// Row layout of one step (float2 units): [nf][nx | ny | nt] propagators,
+// [nx | ny | nt] twiddles, 4 float2 of DftConsts.
 // ---------------------------------------------------------------------------
 struct FieldCoef {
   double kappa, diffraction, tan_rho, delay, k2, k3, alpha;
 };
 
 struct TableArgs {
-  float2* prop;          // [count][nf][nx + ny + nt]
+  float2* rows;          // [count][row_stride]
   float2* nl;            // [count][2][nf][6]
   const double* phi0;    // Phi_n prefix (profile) or null
   const double* dk;      // dk_n (profile) or null
   long n0;
   int count;
   int nx, ny, nt, nf;
+  int row_stride;
   double dz, dx, dy, dt, dk_const;
   FieldCoef fc[3];
 };
+
+__host__ __device__ inline int table_row_stride(int nf, int nx, int ny, int nt) {
+  return (nf + 1) * (nx + ny + nt) + 4;
+}
 
 __device__ inline double reduce_2pi(double a) {
   const double two_pi = 6.283185307179586476925286766559;
@@ -300,42 +315,100 @@ __device__ inline double2 rounded_unit(double theta) {
   return make_double2(double(float(c)), double(float(s)));
 }
 
+// 32-bit integer hash (xorshift-multiply finaliser).
+__device__ inline unsigned mix32(unsigned x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+__device__ inline unsigned entry_bits(long n, unsigned slot) {
+  return mix32(mix32(unsigned(n) * 0x9e3779b1u ^ unsigned(n >> 32)) ^ (slot * 0x85ebca6bu + 0x632be5abu));
+}
+
+// Round v to one of its two float neighbours, up with probability equal to
+// the distance from the lower one (unbiased), using 24 random bits.
+__device__ inline float stochastic_round(double v, unsigned bits) {
+  const float f = float(v);
+  const double d = double(f);
+  if (d == v) return f;
+  float lo, hi;
+  if (d < v) {
+    lo = f;
+    hi = nextafterf(f, HUGE_VALF);
+  } else {
+    hi = f;
+    lo = nextafterf(f, -HUGE_VALF);
+  }
+  const double p = (v - double(lo)) / (double(hi) - double(lo));
+  const double u = double(bits >> 8) * (1.0 / 16777216.0);
+  return (u < p) ? hi : lo;
+}
+
 __global__ void step_tables(TableArgs a) {
   const int per_field = a.nx + a.ny + a.nt;
-  const int per_step = a.nf * per_field;
+  const int per_step = (a.nf + 1) * per_field + 1;  // + one thread for DftConsts
   const long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  const long nprop = long(a.count) * per_step;
-  if (gid < nprop) {
+  const long nrow = long(a.count) * per_step;
+  if (gid < nrow) {
     const int s = int(gid / per_step);
     const int r = int(gid % per_step);
-    const int j = r / per_field;
-    int m = r % per_field;
-    const FieldCoef& f = a.fc[j];
     const long n = a.n0 + s;
-    double phi, scale;
+    float2* row = a.rows + long(s) * a.row_stride;
+    if (r == per_step - 1) {
+      // register-DFT constants of this step
+      const double v[6] = {0.70710678118654752440, 0.92387953251128675613, 0.38268343236508977173,
+                           0.86602540378443864676, 0.96592582628906828675, 0.25881904510252076235};
+      float* out = reinterpret_cast<float*>(row + (a.nf + 1) * per_field);
+      for (int k = 0; k < 6; ++k) out[k] = stochastic_round(v[k], entry_bits(n, 0x40000000u + k));
+      out[6] = 0.f;
+      out[7] = 0.f;
+      return;
+    }
+    int m = r % per_field;
+    int nax, axis;
+    double d;
     if (m < a.nx) {
-      const double kx = ang_freq(m, a.nx, a.dx);
-      phi = -f.diffraction * kx * kx - f.tan_rho * kx;
-      scale = 1.0 / a.nx;
+      axis = 0; nax = a.nx; d = a.dx;
     } else if (m < a.nx + a.ny) {
-      m -= a.nx;
-      const double ky = ang_freq(m, a.ny, a.dy);
-      phi = -f.diffraction * ky * ky;
+      axis = 1; nax = a.ny; d = a.dy; m -= a.nx;
+    } else {
+      axis = 2; nax = a.nt; d = a.dt; m -= a.nx + a.ny;
+    }
+    if (r >= a.nf * per_field) {
+      // forward twiddle exp(-2 pi i m / nax) of this axis
+      double sn, cs;
+      sincospi(2.0 * double(m) / double(nax), &sn, &cs);
+      const unsigned slot = 2u * unsigned(r);
+      row[r] = make_float2(stochastic_round(cs, entry_bits(n, slot)),
+                           stochastic_round(-sn, entry_bits(n, slot + 1)));
+      return;
+    }
+    const int j = r / per_field;
+    const FieldCoef& f = a.fc[j];
+    const double k = ang_freq(m, nax, d);
+    double phi, scale;
+    if (axis == 0) {
+      phi = -f.diffraction * k * k - f.tan_rho * k;
+      scale = 1.0 / a.nx;
+    } else if (axis == 1) {
+      phi = -f.diffraction * k * k;
       scale = 1.0 / a.ny;
     } else {
-      m -= a.nx + a.ny;
-      const double w = ang_freq(m, a.nt, a.dt);
-      phi = -f.delay * w + 0.5 * f.k2 * w * w - (f.k3 / 6.0) * w * w * w;
+      phi = -f.delay * k + 0.5 * f.k2 * k * k - (f.k3 / 6.0) * k * k * k;
       scale = exp(-0.5 * f.alpha * a.dz) / a.nt;
     }
     const double2 u1 = rounded_unit(phi * (double(n + 1) * a.dz));
     const double2 u0 = rounded_unit(phi * (double(n) * a.dz));
     const double re = (u1.x * u0.x + u1.y * u0.y) * scale;
     const double im = (u1.y * u0.x - u1.x * u0.y) * scale;
-    a.prop[gid] = make_float2(float(re), float(im));
+    row[r] = make_float2(float(re), float(im));
     return;
   }
-  const long g2 = gid - nprop;
+  const long g2 = gid - nrow;
   const long nco = long(a.count) * 2 * a.nf;
   if (g2 >= nco) return;
   const int s = int(g2 / (2 * a.nf));
@@ -368,8 +441,11 @@ __global__ void step_tables(TableArgs a) {
   const double w[6] = {h / 2, h / 2, h, h / 6, h / 3, h / 6};
   const int which[6] = {0, 1, 1, 0, 1, 2};
   float2* out = a.nl + g2 * kNlCoef;
-  for (int k = 0; k < 6; ++k)
-    out[k] = make_float2(float(w[k] * c[which[k]].x), float(w[k] * c[which[k]].y));
+  for (int k = 0; k < 6; ++k) {
+    const unsigned slot = 0x50000000u + unsigned((half * a.nf + j) * kNlCoef + k) * 2u;
+    out[k] = make_float2(stochastic_round(w[k] * c[which[k]].x, entry_bits(n, slot)),
+                         stochastic_round(w[k] * c[which[k]].y, entry_bits(n, slot + 1)));
+  }
 }
 
 // Set a flag when any field value is not finite (the step-size hazard of

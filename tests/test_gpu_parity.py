@@ -172,3 +172,41 @@ def test_nonfinite_detected():
         plan.step(40)
     assert ei.value.status == brahms.BRAHMS_E_NONFINITE
     plan.destroy()
+
+
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def _check_golden(out, name, tol):
+    """Compare a GPU run with the oracle reference data written by
+    tests/golden/make_golden.py: sampled values, power traces P(tau),
+    fluence maps and Manley-Rowe combinations."""
+    g = np.load(f"{GOLDEN}/{name}.npz")
+    for j, a in enumerate(out):
+        flat = a.reshape(-1)
+        assert rel_l2(flat[g["uniform_idx"]], g[f"f{j}_uniform"]) < tol, (j, "uniform")
+        assert rel_l2(flat[g[f"f{j}_top_idx"]], g[f"f{j}_top"]) < tol, (j, "top")
+        inten = np.abs(a.astype(np.complex128)) ** 2
+        assert rel_l2(inten.sum(axis=(1, 2)), g[f"f{j}_power"]) < 2 * tol, (j, "power")
+        nt, ny, nx = a.shape
+        by, bx = max(1, ny // 64), max(1, nx // 64)
+        flu = inten.sum(axis=0).reshape(ny // by, by, nx // bx, bx).sum(axis=(1, 3))
+        assert rel_l2(flu, g[f"f{j}_fluence"]) < 2 * tol, (j, "fluence")
+    return g
+
+
+def test_sfg128_full_run_vs_oracle():
+    """SFG 128^3, 500 steps, pump depletion: <= 2e-5 per field."""
+    wl = inputs.sfg128()
+    out = _gpu(wl)
+    g = _check_golden(out, "sfg128_500", 2e-5)
+    e = [float((np.abs(a.astype(np.complex128)) ** 2).sum()) for a in out]
+    assert np.allclose(e, g["energies"], rtol=4e-5)
+
+
+def test_opg256_first_steps_vs_oracle():
+    """OPG 256^3 (the benchmark workload), first 10 steps at full size, in the
+    launch configuration the benchmark times: <= 3e-5 per field."""
+    wl = inputs.opg256()
+    out = _gpu(wl, 10)
+    _check_golden(out, "opg256_10", 3e-5)
