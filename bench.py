@@ -39,7 +39,32 @@ def parse():
                     help="z-steps of the event-timed run used for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle z-steps in the CPU sample")
+    ap.add_argument("--pass-order", default="auto", choices=["auto", "0", "1"],
+                    help="plan schedule: autotuned (default) or a fixed pass order")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="time a plain 1 GiB device-to-device copy instead (reference for "
+                         "achievable bandwidth and for scaling hardware byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """Plain device copy of a known size: 2 x 1 GiB of HBM traffic per copy."""
+    import torch
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    reps = 10
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "avg_ms": ms,
+                      "GBps_read_plus_write": 2 * n / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def make_workload(name):
@@ -78,6 +103,10 @@ def main():
               "the engine has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
     import numpy as np
     import torch
     from paper_2609_08384_amd import brahms
@@ -88,6 +117,12 @@ def main():
     init = [torch.from_numpy(a).to(dev) for a in wl.init]
     fields = [a.clone() for a in init]
     plan = brahms.Plan(wl.nx, wl.ny, wl.nt, wl.nf, brahms.params_from_workload(wl)).bind(fields)
+    if args.pass_order == "auto":
+        from paper_2609_08384_amd import autotune
+        schedule = autotune.apply(plan, dev)
+    else:
+        plan.set_schedule(int(args.pass_order))
+        schedule = plan.get_schedule()
 
     def reset():
         for f, a in zip(fields, init):
@@ -159,7 +194,7 @@ def main():
         "config": {"workload": f"{wl.name}: {wl.nf}-field chi(2) split-step, "
                                f"{wl.nx}x{wl.ny}x{wl.nt} grid, {wl.nz} z-steps",
                    "nx": wl.nx, "ny": wl.ny, "nt": wl.nt, "nf": wl.nf, "nz": wl.nz,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", "schedule": schedule},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "hbm_frac_step": round(step_bytes / (wall / steps) / 1e9 / HBM_PEAK_GBS, 4),

@@ -125,6 +125,23 @@ brahms_status brahms_set_z(brahms_plan plan, double z);
 
 brahms_status brahms_plan_destroy(brahms_plan plan);
 
+/* Execution schedule of a plan (no effect on what is computed, only on how;
+ * results of different schedules agree to rounding).  The linear step is
+ * applied as three commuting one-axis operators (Sec. 3.1: the dispersion
+ * and diffraction operators commute), each a pass over the fields; the first
+ * pass of a z-step also performs the first Runge-Kutta half-step and the last
+ * pass the second one.
+ *   pass_order 0: x pass, y pass, tau pass (default)
+ *   pass_order 1: tau pass, y pass, x pass
+ * The autotuner in the Python package times the candidates per grid shape. */
+typedef struct {
+  int pass_order;
+  int reserved[7];
+} brahms_schedule;
+
+brahms_status brahms_plan_set_schedule(brahms_plan plan, const brahms_schedule* sched);
+brahms_status brahms_plan_get_schedule(brahms_plan plan, brahms_schedule* sched);
+
 /* Kernel timing (diagnostics, not part of the method).  While enabled, every
  * kernel launch of brahms_step is bracketed by HIP events recorded on the
  * plan's stream (at most 65536 launches are timed between two reads).

@@ -179,11 +179,19 @@ def phase_function(prob: Problem) -> Callable[[float], float]:
 # nonlinear operator N (eqs. CEp/CEs/CEi) and the RK4 half-step
 # ---------------------------------------------------------------------------
 
-def nonlinear_rhs(a: List[torch.Tensor], phi: float,
+def _unit(phi):
+    """exp(i phi) for a float or a (differentiable) real tensor phi."""
+    if isinstance(phi, torch.Tensor):
+        return torch.polar(torch.ones_like(phi), phi)
+    return complex(math.cos(phi), math.sin(phi))
+
+
+def nonlinear_rhs(a: List[torch.Tensor], phi,
                   prob: Problem) -> List[torch.Tensor]:
-    """Right-hand side of the nonlinear part alone, at mismatch phase phi."""
-    e_m = complex(math.cos(phi), -math.sin(phi))   # exp(-i Phi)
-    e_p = complex(math.cos(phi), math.sin(phi))    # exp(+i Phi)
+    """Right-hand side of the nonlinear part alone, at mismatch phase phi
+    (a float, or a real tensor when gradients in phi are wanted)."""
+    e_m = _unit(-phi)   # exp(-i Phi)
+    e_p = _unit(phi)    # exp(+i Phi)
     k = [fp.kappa for fp in prob.fields]
     if prob.nf == 3:
         ap, as_, ai = a
@@ -196,7 +204,7 @@ def nonlinear_rhs(a: List[torch.Tensor], phi: float,
 
 
 def rk4(a: List[torch.Tensor], z: float, h: float, prob: Problem,
-        phi: Callable[[float], float]) -> List[torch.Tensor]:
+        phi: Callable) -> List[torch.Tensor]:
     """One classical RK4 step of size h for dA/dz = N(A, z), starting at z."""
     def f(y, zz):
         return nonlinear_rhs(y, phi(zz), prob)

@@ -1,0 +1,111 @@
+"""Schedule autotuner: picks, per grid shape and field count, the plan
+schedule (see brahms_schedule in include/brahms.h) that runs fastest on this
+GPU, by timing each candidate on scratch fields, and caches the choice.
+
+This is the plan-by-measurement idea of the paper's CPU backend (FFTW
+planning with measurement, Sec. 5.1) applied to the GPU schedules.  The
+timing loop only calls the C ABI; every candidate computes the same result to
+rounding.
+"""
+from __future__ import annotations
+
+import json
+import os
+import threading
+from typing import Dict, Optional
+
+import torch
+
+from . import brahms
+
+CANDIDATES = [{"pass_order": 0}, {"pass_order": 1}]
+_lock = threading.Lock()
+_memo: Dict[str, dict] = {}
+
+
+def cache_path() -> str:
+    root = os.environ.get("BRAHMS_CACHE_DIR") or os.path.join(
+        os.path.expanduser("~"), ".cache", "brahms")
+    return os.path.join(root, "schedules.json")
+
+
+def _arch(device) -> str:
+    props = torch.cuda.get_device_properties(device)
+    return getattr(props, "gcnArchName", "unknown").split(":")[0]
+
+
+def _key(arch: str, nx: int, ny: int, nt: int, nf: int) -> str:
+    return f"{arch}:{nx}x{ny}x{nt}:nf{nf}"
+
+
+def _load() -> dict:
+    try:
+        with open(cache_path()) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(entries: dict):
+    path = cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + f".tmp{os.getpid()}"
+        with open(tmp, "w") as fh:
+            json.dump(entries, fh, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass  # a read-only home only loses the cache
+
+
+def measure(nx: int, ny: int, nt: int, nf: int, params: brahms.Params, schedule: dict,
+            device="cuda:0", steps: int = 12, warmup: int = 3) -> float:
+    """Milliseconds per z-step of one schedule on scratch fields."""
+    gen = torch.Generator(device="cpu").manual_seed(1234)
+    fields = [(0.1 * torch.randn(nt, ny, nx, dtype=torch.complex64, generator=gen)).to(device)
+              for _ in range(nf)]
+    plan = brahms.Plan(nx, ny, nt, nf, params)
+    plan.set_schedule(**schedule)
+    plan.bind(fields)
+    plan.step(warmup)
+    torch.cuda.synchronize(device)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    plan.step(steps)
+    ev1.record()
+    torch.cuda.synchronize(device)
+    plan.destroy()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def tune(nx: int, ny: int, nt: int, nf: int, params: brahms.Params, device="cuda:0",
+         refresh: bool = False) -> dict:
+    """Best schedule for this shape (cached in memory and on disk)."""
+    arch = _arch(device)
+    key = _key(arch, nx, ny, nt, nf)
+    with _lock:
+        if not refresh:
+            if key in _memo:
+                return _memo[key]
+            disk = _load()
+            if key in disk:
+                _memo[key] = disk[key]["schedule"]
+                return _memo[key]
+        # time with the same linear coefficients but no coupling blow-up risk
+        scratch = brahms.Params(dz=params.dz, fields=params.fields, dk_const=params.dk_const,
+                                dk=None, dx=params.dx, dy=params.dy, dt=params.dt)
+        times = [(measure(nx, ny, nt, nf, scratch, c, device), c) for c in CANDIDATES]
+        best_ms, best = min(times, key=lambda tc: tc[0])
+        _memo[key] = dict(best)
+        disk = _load()
+        disk[key] = {"schedule": dict(best), "ms_per_step": best_ms,
+                     "candidates": [{"schedule": c, "ms_per_step": t} for t, c in times]}
+        _store(disk)
+        return _memo[key]
+
+
+def apply(plan: brahms.Plan, device="cuda:0") -> dict:
+    """Tune (or look up) the plan's shape and set the chosen schedule."""
+    sched = tune(plan.nx, plan.ny, plan.nt, plan.nf, plan.params, device)
+    plan.set_schedule(**sched)
+    return sched

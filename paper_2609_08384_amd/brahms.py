@@ -39,6 +39,10 @@ class BrahmsError(RuntimeError):
         self.status = status
 
 
+class ScheduleC(ctypes.Structure):
+    _fields_ = [("pass_order", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
+
+
 class FieldParamsC(ctypes.Structure):
     _fields_ = [("kappa", ctypes.c_double), ("diffraction", ctypes.c_double),
                 ("tan_rho", ctypes.c_double), ("delay", ctypes.c_double),
@@ -74,6 +78,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "brahms_get_z": [vp, ctypes.POINTER(d)],
         "brahms_set_z": [vp, d],
         "brahms_plan_destroy": [vp],
+        "brahms_plan_set_schedule": [vp, ctypes.POINTER(ScheduleC)],
+        "brahms_plan_get_schedule": [vp, ctypes.POINTER(ScheduleC)],
         "brahms_timing_enable": [vp, i],
         "brahms_timing_read": [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)],
     }
@@ -206,6 +212,18 @@ class Plan:
     def set_z(self, z: float):
         _check(self._lib.brahms_set_z(self._h, float(z)), "brahms_set_z")
 
+    def set_schedule(self, pass_order: int):
+        sc = ScheduleC()
+        sc.pass_order = int(pass_order)
+        _check(self._lib.brahms_plan_set_schedule(self._h, ctypes.byref(sc)),
+               "brahms_plan_set_schedule")
+
+    def get_schedule(self) -> dict:
+        sc = ScheduleC()
+        _check(self._lib.brahms_plan_get_schedule(self._h, ctypes.byref(sc)),
+               "brahms_plan_get_schedule")
+        return {"pass_order": sc.pass_order}
+
     def timing_enable(self, enable: bool = True):
         _check(self._lib.brahms_timing_enable(self._h, 1 if enable else 0), "brahms_timing_enable")
 
@@ -229,12 +247,15 @@ class Plan:
 
 
 def run_workload(wl, nsteps: Optional[int] = None, device: str = "cuda:0",
-                 stream: Optional[torch.cuda.Stream] = None) -> List[torch.Tensor]:
+                 stream: Optional[torch.cuda.Stream] = None,
+                 pass_order: Optional[int] = None) -> List[torch.Tensor]:
     """Upload a seeded workload's entrance fields, propagate nsteps (default:
     all of them) and return the device fields."""
     nsteps = wl.nz if nsteps is None else nsteps
     fields = [torch.from_numpy(a).to(device) for a in wl.init]
     plan = Plan(wl.nx, wl.ny, wl.nt, wl.nf, params_from_workload(wl), stream=stream)
+    if pass_order is not None:
+        plan.set_schedule(pass_order)
     plan.bind(fields)
     plan.step(nsteps)
     torch.cuda.synchronize()

@@ -64,6 +64,7 @@ struct brahms_plan_s {
   char* ws = nullptr;
   bool bound = false;
   long long step = 0;          // z = step * dz
+  int order = 0;               // 0: x, y, tau passes; 1: tau, y, x
   // workspace offsets (bytes)
   size_t off_phi0 = 0, off_dk = 0, off_prop = 0, off_nl = 0, off_flag = 0, ws_size = 0;
   // launch timing (diagnostics)
@@ -79,39 +80,80 @@ namespace {
 // kernel dispatch: each supported axis length maps to a (N1, N2) split with
 // N2 threads per line and N1 values per thread.
 // ---------------------------------------------------------------------------
+template <int N1, int N2, int AX, int NF, int NL>
+void launch_pass(bool full, dim3 grid, hipStream_t st, const PassArgs& a) {
+  if (full) hipLaunchKernelGGL((axis_pass<N1, N2, AX, NF, NL, true>), grid, dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL((axis_pass<N1, N2, AX, NF, NL, false>), grid, dim3(kBlock), 0, st, a);
+}
+
+#ifndef BRAHMS_TILE_SPREAD
+#define BRAHMS_TILE_SPREAD 1
+#endif
+
+unsigned gcd_u(unsigned a, unsigned b) {
+  while (b) {
+    const unsigned r = a % b;
+    a = b;
+    b = r;
+  }
+  return a;
+}
+
+// Multiplier of the block -> tile permutation of the tau pass: coprime with
+// the tile count (so the map is a bijection) and about tiles/64, so that
+// consecutive blocks land about 1/64 of the plane apart.
+unsigned tile_multiplier(unsigned tiles) {
+  if (!BRAHMS_TILE_SPREAD || tiles < 128) return 1;
+  unsigned m = tiles / 64 + 1;
+  while (gcd_u(m, tiles) != 1) ++m;
+  return m;
+}
+
+template <int N1, int N2, int AX>
+void launch_nl(int nf, int nl, bool full, dim3 grid, hipStream_t st, const PassArgs& a) {
+  if (nf == 3) {
+    if (nl == NL_BEFORE) launch_pass<N1, N2, AX, 3, NL_BEFORE>(full, grid, st, a);
+    else launch_pass<N1, N2, AX, 3, NL_AFTER>(full, grid, st, a);
+  } else {
+    if (nl == NL_BEFORE) launch_pass<N1, N2, AX, 2, NL_BEFORE>(full, grid, st, a);
+    else launch_pass<N1, N2, AX, 2, NL_AFTER>(full, grid, st, a);
+  }
+}
+
+// One pass along `axis`; nl says where the RK4 half-step goes (NL_NONE only
+// for the y pass, which is always the middle pass of a step).
 template <int N1, int N2>
-hipError_t launch_axis(int axis, int nf, const brahms_plan_s& p, PassArgs a) {
+hipError_t launch_axis(int axis, int nl, int nf, const brahms_plan_s& p, PassArgs a) {
   using G = LineGeom<N1, N2>;
-  const dim3 block(kBlock);
+  a.tile_mul = 1;
   if (axis == AX_X) {
     const long lines = long(p.ny) * p.nt;
     const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
-    if (nf == 3) hipLaunchKernelGGL((axis_pass<N1, N2, AX_X, 3, NL_BEFORE>), grid, block, 0, p.stream, a);
-    else hipLaunchKernelGGL((axis_pass<N1, N2, AX_X, 2, NL_BEFORE>), grid, block, 0, p.stream, a);
+    launch_nl<N1, N2, AX_X>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
   } else if (axis == AX_Y) {
     const dim3 grid(unsigned((p.nx + G::LPB - 1) / G::LPB), unsigned(p.nt), unsigned(nf));
-    hipLaunchKernelGGL((axis_pass<N1, N2, AX_Y, 1, NL_NONE>), grid, block, 0, p.stream, a);
+    launch_pass<N1, N2, AX_Y, 1, NL_NONE>(p.nx % G::LPB == 0, grid, p.stream, a);
   } else {
     const long lines = long(p.nx) * p.ny;
     const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
-    if (nf == 3) hipLaunchKernelGGL((axis_pass<N1, N2, AX_T, 3, NL_AFTER>), grid, block, 0, p.stream, a);
-    else hipLaunchKernelGGL((axis_pass<N1, N2, AX_T, 2, NL_AFTER>), grid, block, 0, p.stream, a);
+    a.tile_mul = tile_multiplier(grid.x);
+    launch_nl<N1, N2, AX_T>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
   }
   return hipGetLastError();
 }
 
-hipError_t dispatch_axis(int n, int axis, int nf, const brahms_plan_s& p, PassArgs a) {
+hipError_t dispatch_axis(int n, int axis, int nl, int nf, const brahms_plan_s& p, PassArgs a) {
   switch (n) {
-    case 1: return launch_axis<1, 1>(axis, nf, p, a);
-    case 2: return launch_axis<2, 1>(axis, nf, p, a);
-    case 4: return launch_axis<4, 1>(axis, nf, p, a);
-    case 8: return launch_axis<4, 2>(axis, nf, p, a);
-    case 16: return launch_axis<4, 4>(axis, nf, p, a);
-    case 32: return launch_axis<8, 4>(axis, nf, p, a);
-    case 64: return launch_axis<8, 8>(axis, nf, p, a);
-    case 96: return launch_axis<24, 4>(axis, nf, p, a);
-    case 128: return launch_axis<16, 8>(axis, nf, p, a);
-    case 256: return launch_axis<16, 16>(axis, nf, p, a);
+    case 1: return launch_axis<1, 1>(axis, nl, nf, p, a);
+    case 2: return launch_axis<2, 1>(axis, nl, nf, p, a);
+    case 4: return launch_axis<4, 1>(axis, nl, nf, p, a);
+    case 8: return launch_axis<4, 2>(axis, nl, nf, p, a);
+    case 16: return launch_axis<4, 4>(axis, nl, nf, p, a);
+    case 32: return launch_axis<8, 4>(axis, nl, nf, p, a);
+    case 64: return launch_axis<8, 8>(axis, nl, nf, p, a);
+    case 96: return launch_axis<24, 4>(axis, nl, nf, p, a);
+    case 128: return launch_axis<16, 8>(axis, nl, nf, p, a);
+    case 256: return launch_axis<16, 16>(axis, nl, nf, p, a);
     default: return hipErrorInvalidValue;
   }
 }
@@ -213,19 +255,25 @@ brahms_status run_steps(brahms_plan_s& p, int nsteps) {
       if (brahms_status st = timing_stop(p)) return st;
     for (int s = 0; s < count; ++s) {
       const float2* row = prop + size_t(s) * row_stride;
-      for (int ax = 0; ax < 3; ++ax) {
+      // pass order of the step: the first pass carries the first RK4
+      // half-step, the last pass the second one (the axis operators commute)
+      const int seq[3] = {p.order == 0 ? int(AX_X) : int(AX_T), int(AX_Y),
+                          p.order == 0 ? int(AX_T) : int(AX_X)};
+      for (int k = 0; k < 3; ++k) {
+        const int ax = seq[k];
+        const int nlmode = k == 0 ? NL_BEFORE : (k == 2 ? NL_AFTER : NL_NONE);
         PassArgs a{};
         for (int j = 0; j < 3; ++j) a.f[j] = p.fields[j];
         a.axis_off = (ax == AX_X) ? 0 : (ax == AX_Y ? p.nx : p.nx + p.ny);
         a.tw = row + p.nf * per_field + a.axis_off;
         a.consts = reinterpret_cast<const DftConsts*>(row + (p.nf + 1) * per_field);
         a.nx = p.nx; a.ny = p.ny; a.nt = p.nt;
-        a.nl = nl + (size_t(s) * 2 + (ax == AX_X ? 0 : 1)) * p.nf * kNlCoef;
+        a.nl = nl + (size_t(s) * 2 + (k == 0 ? 0 : 1)) * p.nf * kNlCoef;
         a.prop = row;
         a.field_stride = per_field;
         const bool timed = p.timing && p.timed.size() < kMaxTimed;
         if (brahms_status st = timing_start(p, ax)) return st;
-        HIP_TRY(dispatch_axis(n[ax], ax, p.nf, p, a));
+        HIP_TRY(dispatch_axis(n[ax], ax, nlmode, p.nf, p, a));
         if (timed)
           if (brahms_status st = timing_stop(p)) return st;
       }
@@ -374,6 +422,23 @@ brahms_status brahms_set_z(brahms_plan plan, double z) {
   if (!std::isfinite(z) || z < 0.0 || !steps_to(0.0, z, plan->dz, &n))
     return fail(BRAHMS_E_INVALID_ARG, "z must be a non-negative multiple of dz");
   plan->step = n;
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_plan_set_schedule(brahms_plan plan, const brahms_schedule* sched) {
+  if (brahms_status st = check_plan(plan)) return st;
+  if (sched == nullptr) return fail(BRAHMS_E_INVALID_ARG, "schedule is NULL");
+  if (sched->pass_order != 0 && sched->pass_order != 1)
+    return fail(BRAHMS_E_INVALID_ARG, "pass_order must be 0 or 1");
+  plan->order = sched->pass_order;
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_plan_get_schedule(brahms_plan plan, brahms_schedule* sched) {
+  if (brahms_status st = check_plan(plan)) return st;
+  if (sched == nullptr) return fail(BRAHMS_E_INVALID_ARG, "schedule is NULL");
+  *sched = brahms_schedule{};
+  sched->pass_order = plan->order;
   return BRAHMS_OK;
 }
 

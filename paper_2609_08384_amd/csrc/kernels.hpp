@@ -38,6 +38,7 @@ struct PassArgs {
   const DftConsts* consts;  // this step's register-DFT constants
   int nx, ny, nt;
   int axis_off, field_stride;
+  unsigned tile_mul;     // block -> tile map: tile = (block * tile_mul) mod tiles
 };
 
 // ---------------------------------------------------------------------------
@@ -143,51 +144,105 @@ __device__ inline void line_fft(float2 (&v)[N1], int t, float2* lbuf, const floa
 }
 
 // ---------------------------------------------------------------------------
+// Field access.  Field values are streamed once per pass; the addresses are a
+// uniform base (scalar registers) plus a 32-bit element offset.
+// ---------------------------------------------------------------------------
+#ifndef BRAHMS_NT_X
+#define BRAHMS_NT_X 1
+#endif
+#ifndef BRAHMS_NT_YT
+#define BRAHMS_NT_YT 0
+#endif
+#ifndef BRAHMS_MIN_BLOCKS
+#define BRAHMS_MIN_BLOCKS 1
+#endif
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+template <bool NT>
+__device__ inline float2 load_field(const float2* base, unsigned idx) {
+  if constexpr (NT) {
+    const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(base) + idx);
+    return make_float2(v.x, v.y);
+  } else {
+    return base[idx];
+  }
+}
+
+template <bool NT>
+__device__ inline void store_field(float2* base, unsigned idx, float2 v) {
+  if constexpr (NT) {
+    f32x2 w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, reinterpret_cast<f32x2*>(base) + idx);
+  } else {
+    base[idx] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // The fused axis pass.  AX selects the line family:
 //   X: line = (y, tau), element stride 1, lanes t-fastest (contiguous loads)
 //   Y: line = (x, tau), element stride nx, lanes x-fastest (coalesced rows)
 //   T: line = (x, y),   element stride nx*ny, lanes (x,y)-fastest
 // NF is the number of fields held by one thread (Y: 1, one field per block).
+// FULL: every line of every block exists (no bounds masks).
 // ---------------------------------------------------------------------------
-template <int N1, int N2, int AX, int NF, int NL>
-__global__ __launch_bounds__(kBlock) void axis_pass(PassArgs args) {
+template <int N1, int N2, int AX, int NF, int NL, bool FULL>
+__global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass(PassArgs args) {
   using G = LineGeom<N1, N2>;
   constexpr int N = G::N;
+  constexpr bool NT = (AX == AX_X) ? bool(BRAHMS_NT_X) : bool(BRAHMS_NT_YT);
   __shared__ float2 lds[G::LDS_ELEMS];
+  __shared__ float2 s_tw[N];
+  __shared__ float2 s_prop[NF * N];
 
   const int tid = threadIdx.x;
+  const int field0 = (AX == AX_Y) ? int(blockIdx.z) : 0;
+  // this step's twiddles and this block's propagators, staged once
+  for (int i = tid; i < N; i += kBlock) s_tw[i] = args.tw[i];
+  for (int i = tid; i < NF * N; i += kBlock)
+    s_prop[i] = args.prop[(field0 + i / N) * args.field_stride + args.axis_off + i % N];
+
   int t, li;
-  long base;
-  long estride;
-  bool valid;
-  float2* fp[NF];
+  unsigned base, estride;
+  bool valid = true;
+  const float2* fin[NF];
+  float2* fout[NF];
   if constexpr (AX == AX_X) {
     t = tid % N2;
     li = tid / N2;
-    const long line = long(blockIdx.x) * G::LPB + li;
-    valid = line < long(args.ny) * args.nt;
-    base = line * args.nx;
+    const unsigned line = blockIdx.x * unsigned(G::LPB) + li;
+    if constexpr (!FULL) valid = line < unsigned(args.ny) * unsigned(args.nt);
+    base = line * unsigned(args.nx);
     estride = 1;
-#pragma unroll
-    for (int j = 0; j < NF; ++j) fp[j] = args.f[j];
   } else if constexpr (AX == AX_Y) {
     li = tid % G::LPB;
     t = tid / G::LPB;
-    const int col = blockIdx.x * G::LPB + li;
-    valid = col < args.nx;
-    base = long(col) + long(args.nx) * args.ny * blockIdx.y;
+    const unsigned col = blockIdx.x * unsigned(G::LPB) + li;
+    if constexpr (!FULL) valid = col < unsigned(args.nx);
+    base = col + unsigned(args.nx) * unsigned(args.ny) * blockIdx.y;
     estride = args.nx;
-    fp[0] = args.f[blockIdx.z];
   } else {
     li = tid % G::LPB;
     t = tid / G::LPB;
-    const long q = long(blockIdx.x) * G::LPB + li;
-    valid = q < long(args.nx) * args.ny;
+    // tiles of consecutive (x, y) columns; concurrently running blocks are
+    // spread over the whole plane so that their strided rows fall into many
+    // memory channels rather than one narrow address window
+    const unsigned tile = unsigned((unsigned long long)blockIdx.x * args.tile_mul % gridDim.x);
+    const unsigned q = tile * unsigned(G::LPB) + li;
+    if constexpr (!FULL) valid = q < unsigned(args.nx) * unsigned(args.ny);
     base = q;
-    estride = long(args.nx) * args.ny;
-#pragma unroll
-    for (int j = 0; j < NF; ++j) fp[j] = args.f[j];
+    estride = unsigned(args.nx) * unsigned(args.ny);
   }
+#pragma unroll
+  for (int j = 0; j < NF; ++j) {
+    fin[j] = args.f[field0 + j];
+    fout[j] = args.f[field0 + j];
+  }
+  const unsigned idx0 = base + unsigned(t) * estride;
+  const unsigned estep = unsigned(N2) * estride;
   float2* lbuf = lds + li * G::LSTRIDE;
   const DftConsts K = *args.consts;
 
@@ -196,8 +251,9 @@ __global__ __launch_bounds__(kBlock) void axis_pass(PassArgs args) {
   for (int j = 0; j < NF; ++j) {
 #pragma unroll
     for (int e = 0; e < N1; ++e)
-      v[j][e] = valid ? fp[j][base + long(t + N2 * e) * estride] : make_float2(0.f, 0.f);
+      v[j][e] = valid ? load_field<NT>(fin[j], idx0 + unsigned(e) * estep) : make_float2(0.f, 0.f);
   }
+  __syncthreads();  // s_tw, s_prop staged
 
   if constexpr (NL == NL_BEFORE) {
     float2 co[NF][kNlCoef];
@@ -216,18 +272,16 @@ __global__ __launch_bounds__(kBlock) void axis_pass(PassArgs args) {
     }
   }
 
-  const int field0 = (AX == AX_Y) ? int(blockIdx.z) : 0;
 #pragma unroll
   for (int j = 0; j < NF; ++j) {
-    line_fft<N1, N2, false>(v[j], t, lbuf, args.tw, K);
-    const float2* pr = args.prop + (field0 + j) * args.field_stride + args.axis_off;
+    line_fft<N1, N2, false>(v[j], t, lbuf, s_tw, K);
 #pragma unroll
-    for (int e = 0; e < N1; ++e) v[j][e] = cmul(v[j][e], pr[t + N2 * e]);
-    line_fft<N1, N2, true>(v[j], t, lbuf, args.tw, K);
+    for (int e = 0; e < N1; ++e) v[j][e] = cmul(v[j][e], s_prop[j * N + t + N2 * e]);
+    line_fft<N1, N2, true>(v[j], t, lbuf, s_tw, K);
     if constexpr (NL != NL_AFTER) {
       if (valid) {
 #pragma unroll
-        for (int e = 0; e < N1; ++e) fp[j][base + long(t + N2 * e) * estride] = v[j][e];
+        for (int e = 0; e < N1; ++e) store_field<NT>(fout[j], idx0 + unsigned(e) * estep, v[j][e]);
       }
     }
   }
@@ -251,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void axis_pass(PassArgs args) {
 #pragma unroll
       for (int j = 0; j < NF; ++j)
 #pragma unroll
-        for (int e = 0; e < N1; ++e) fp[j][base + long(t + N2 * e) * estride] = v[j][e];
+        for (int e = 0; e < N1; ++e) store_field<NT>(fout[j], idx0 + unsigned(e) * estep, v[j][e]);
     }
   }
 }

@@ -30,8 +30,8 @@ def _wl(nx, ny, nt, nf, nz, dz, fields, dk_const=0.0, dk=None, init=None):
     return wl
 
 
-def _gpu(wl, nsteps=None):
-    out = brahms.run_workload(wl, nsteps=nsteps, device=DEV)
+def _gpu(wl, nsteps=None, pass_order=None):
+    out = brahms.run_workload(wl, nsteps=nsteps, device=DEV, pass_order=pass_order)
     return [f.cpu().numpy() for f in out]
 
 
@@ -106,15 +106,17 @@ def test_plane_wave_opa():
     assert np.abs(i - wi).max() < _accumulation_bound(2 * nz, abs(wi)) + 1e-7 * abs(wi)
 
 
+@pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("nf,shape", [(2, (32, 32, 32)), (3, (32, 32, 32)), (3, (64, 16, 96)),
                                       (2, (96, 96, 4)), (3, (16, 128, 64))])
-def test_coupled_steps_random(nf, shape):
-    """All linear terms and the chi(2) coupling, 10 steps, ragged tiles."""
+def test_coupled_steps_random(nf, shape, order):
+    """All linear terms and the chi(2) coupling, 10 steps, ragged tiles, both
+    pass orders."""
     nx, ny, nt = shape
     rng = np.random.default_rng(100 + nf)
     init = inputs.random_fields(rng, nf, nx, ny, nt, scale=0.7, smooth=min(nx, ny, nt) / 2.0)
     wl = _wl(nx, ny, nt, nf, 10, 0.02, _all_terms(nf, kappa=1.5), dk_const=2.3, init=init)
-    g, o = _gpu(wl), _oracle(wl)
+    g, o = _gpu(wl, pass_order=order), _oracle(wl)
     for j in range(nf):
         assert rel_l2(g[j], o[j]) < 5e-6, j
 
@@ -130,10 +132,11 @@ def test_dk_profile_matches_oracle():
         assert rel_l2(g[j], o[j]) < 5e-6
 
 
-def test_shg32_full_run():
+@pytest.mark.parametrize("order", [0, 1])
+def test_shg32_full_run(order):
     """SHG 32^3, 100 steps (the small benchmark workload): <= 1e-5 per field."""
     wl = inputs.shg32()
-    g, o = _gpu(wl), _oracle(wl)
+    g, o = _gpu(wl, pass_order=order), _oracle(wl)
     for j in range(2):
         assert rel_l2(g[j], o[j]) < 1e-5, j
 
@@ -195,18 +198,20 @@ def _check_golden(out, name, tol):
     return g
 
 
-def test_sfg128_full_run_vs_oracle():
+@pytest.mark.parametrize("order", [0, 1])
+def test_sfg128_full_run_vs_oracle(order):
     """SFG 128^3, 500 steps, pump depletion: <= 2e-5 per field."""
     wl = inputs.sfg128()
-    out = _gpu(wl)
+    out = _gpu(wl, pass_order=order)
     g = _check_golden(out, "sfg128_500", 2e-5)
     e = [float((np.abs(a.astype(np.complex128)) ** 2).sum()) for a in out]
     assert np.allclose(e, g["energies"], rtol=4e-5)
 
 
-def test_opg256_first_steps_vs_oracle():
+@pytest.mark.parametrize("order", [0, 1])
+def test_opg256_first_steps_vs_oracle(order):
     """OPG 256^3 (the benchmark workload), first 10 steps at full size, in the
-    launch configuration the benchmark times: <= 3e-5 per field."""
+    launch configurations the benchmark may time: <= 3e-5 per field."""
     wl = inputs.opg256()
-    out = _gpu(wl, 10)
+    out = _gpu(wl, 10, pass_order=order)
     _check_golden(out, "opg256_10", 3e-5)
