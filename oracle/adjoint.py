@@ -67,7 +67,7 @@ def gradients(fields_in: Sequence, dk: Sequence[float], prob: ssfm.Problem, nste
     out = forward(a, d, prob, nsteps)
     j = loss(out, prob)
     grads = torch.autograd.grad(j, a + [d])
-    return float(j), [g.detach() for g in grads[:-1]], grads[-1].detach()
+    return float(j.detach()), [g.detach() for g in grads[:-1]], grads[-1].detach()
 
 
 def loss_value(fields_in: Sequence, dk: Sequence[float], prob: ssfm.Problem, nsteps: int,
