@@ -153,6 +153,33 @@ brahms_status brahms_plan_get_schedule(brahms_plan plan, brahms_schedule* sched)
 brahms_status brahms_timing_enable(brahms_plan plan, int enable);
 brahms_status brahms_timing_read(brahms_plan plan, double* ms, long long* launches);
 
+/* Adjoint (reverse-mode gradient) of the z-loop, for inverse design.  Not in
+ * the paper; it differentiates exactly the discrete map that brahms_step
+ * computes (Sec. 3.1: RK4 half-steps and the Fourier-space linear step).
+ * Cotangents follow the convention g = dJ/dRe(A) + i dJ/dIm(A) of a real loss
+ * J, the layout of the fields.
+ *
+ * brahms_adjoint_workspace_size: device bytes needed for nsteps steps with a
+ *   checkpoint every checkpoint_every (1..64) steps: ceil(nsteps/K) + 2K + 1
+ *   states of nf fields plus small reduction buffers.
+ * brahms_adjoint_forward: from the current step index n0, advance the bound
+ *   fields nsteps steps exactly as brahms_step does, storing checkpoints in
+ *   adj_workspace (caller-owned, 256-byte aligned, kept until the backward
+ *   call).  The fields end at z = (n0 + nsteps) dz.
+ * brahms_adjoint_backward: grad holds nf device buffers (field layout) with
+ *   dJ/dA(z_end) on entry and dJ/dA(z0) on exit.  grad_dk (host, may be NULL)
+ *   receives dJ/ddk: n_dk entries (entries past the window are zero) when a
+ *   per-step profile was given at create, else one entry dJ/d(dk_const).
+ *   The z counter is left at z_end.  Synchronises the plan's stream when
+ *   grad_dk is not NULL.
+ * Errors: BRAHMS_E_STATE (not bound / no forward record), BRAHMS_E_INVALID_ARG
+ * (sizes, pointers, steps beyond the dk profile), BRAHMS_E_DEVICE. */
+brahms_status brahms_adjoint_workspace_size(brahms_plan plan, int nsteps, int checkpoint_every,
+                                            size_t* bytes);
+brahms_status brahms_adjoint_forward(brahms_plan plan, int nsteps, int checkpoint_every,
+                                     void* adj_workspace);
+brahms_status brahms_adjoint_backward(brahms_plan plan, void* const* grad, double* grad_dk);
+
 /* Thread-local message for the last failing call (empty if none). */
 const char* brahms_last_error(void);
 

@@ -80,6 +80,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "brahms_plan_destroy": [vp],
         "brahms_plan_set_schedule": [vp, ctypes.POINTER(ScheduleC)],
         "brahms_plan_get_schedule": [vp, ctypes.POINTER(ScheduleC)],
+        "brahms_adjoint_workspace_size": [vp, i, i, ctypes.POINTER(ctypes.c_size_t)],
+        "brahms_adjoint_forward": [vp, i, i, vp],
+        "brahms_adjoint_backward": [vp, ctypes.POINTER(vp), ctypes.POINTER(d)],
         "brahms_timing_enable": [vp, i],
         "brahms_timing_read": [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)],
     }
@@ -223,6 +226,41 @@ class Plan:
         _check(self._lib.brahms_plan_get_schedule(self._h, ctypes.byref(sc)),
                "brahms_plan_get_schedule")
         return {"pass_order": sc.pass_order}
+
+    # --- adjoint (reverse-mode gradient of the z-loop) ---
+    def adjoint_workspace_bytes(self, nsteps: int, checkpoint_every: int) -> int:
+        out = ctypes.c_size_t()
+        _check(self._lib.brahms_adjoint_workspace_size(self._h, int(nsteps), int(checkpoint_every),
+                                                       ctypes.byref(out)),
+               "brahms_adjoint_workspace_size")
+        return int(out.value)
+
+    def adjoint_forward(self, nsteps: int, checkpoint_every: int):
+        """Advance nsteps like step(), keeping checkpoints for the backward."""
+        nbytes = self.adjoint_workspace_bytes(nsteps, checkpoint_every)
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.fields[0].device)
+        aligned = (ws.data_ptr() + 255) // 256 * 256
+        _check(self._lib.brahms_adjoint_forward(self._h, int(nsteps), int(checkpoint_every),
+                                                ctypes.c_void_p(aligned)),
+               "brahms_adjoint_forward")
+        self.adjoint_workspace = ws
+
+    def adjoint_backward(self, grads: Sequence[torch.Tensor]):
+        """grads: dJ/dA_out (complex64, field layout), overwritten with
+        dJ/dA_in.  Returns dJ/ddk as a float64 numpy array (profile length,
+        or one entry for a constant dk)."""
+        import numpy as np
+        for g in grads:
+            if (g.dtype != torch.complex64 or not g.is_cuda or not g.is_contiguous()
+                    or tuple(g.shape) != (self.nt, self.ny, self.nx)):
+                raise ValueError("grads must be contiguous complex64 CUDA tensors in field layout")
+        n_dk = len(self.params.dk) if self.params.dk is not None else 1
+        out = np.zeros(n_dk, dtype=np.float64)
+        arr = (ctypes.c_void_p * self.nf)(*[g.data_ptr() for g in grads])
+        _check(self._lib.brahms_adjoint_backward(
+            self._h, arr, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+            "brahms_adjoint_backward")
+        return out
 
     def timing_enable(self, enable: bool = True):
         _check(self._lib.brahms_timing_enable(self._h, 1 if enable else 0), "brahms_timing_enable")

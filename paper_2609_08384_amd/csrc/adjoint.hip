@@ -1,0 +1,312 @@
+// Adjoint of the z-loop behind the C ABI (brahms_adjoint_*; see
+// include/brahms.h and adjoint.hpp).
+//
+// Forward: the plain z-loop, with the state copied to a checkpoint every K
+// steps.  Backward, one K-step segment at a time from the last: recompute the
+// segment out of place from its checkpoint, keeping every step's input and
+// the input of its second RK4 half-step; then for each step in reverse apply
+// the adjoint passes (reverse second half-step + conj-propagator transforms
+// along the last axis, conj-propagator transforms along y, conj-propagator
+// transforms along the first axis + reverse first half-step).  dJ/dPhi at the
+// six stage positions of every step is reduced on the device in a fixed
+// order and turned into dJ/ddk_n on the host: with Phi(z) = Phi_n +
+// dk_n (z - z_n) and Phi_n = dz sum_{m<n} dk_m,
+//   dJ/ddk_n = sum_stages (z_s - z_n) dJ/dPhi(z_s) [stages of step n]
+//            + dz sum_{m>n} sum_stages dJ/dPhi(z_s) [stages of later steps].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/brahms.h"
+#include "adjoint.hpp"
+#include "plan.hpp"
+
+using namespace brahms;
+using brahms::detail::align_up;
+using brahms::detail::check_plan;
+using brahms::detail::fail;
+using brahms::detail::kChunk;
+
+namespace {
+
+struct AdjLayout {
+  size_t ckpt = 0, seg = 0, pre = 0, parts = 0, dphi = 0, total = 0;
+  int nckpt = 0, every = 0, nsteps = 0;
+  size_t field_bytes = 0;
+  int max_blocks = 0;
+};
+
+template <int N1, int N2>
+int blocks_of(int axis, const brahms_plan_s& p) {
+  using G = LineGeom<N1, N2>;
+  const long lines = axis == AX_X ? long(p.ny) * p.nt : long(p.nx) * p.ny;
+  return int((lines + G::LPB - 1) / G::LPB);
+}
+
+int pass_blocks(int axis, const brahms_plan_s& p) {
+  const int n = axis == AX_X ? p.nx : p.nt;
+  switch (n) {
+    case 1: return blocks_of<1, 1>(axis, p);
+    case 2: return blocks_of<2, 1>(axis, p);
+    case 4: return blocks_of<4, 1>(axis, p);
+    case 8: return blocks_of<4, 2>(axis, p);
+    case 16: return blocks_of<4, 4>(axis, p);
+    case 32: return blocks_of<8, 4>(axis, p);
+    case 64: return blocks_of<8, 8>(axis, p);
+    case 96: return blocks_of<24, 4>(axis, p);
+    case 128: return blocks_of<16, 8>(axis, p);
+    default: return blocks_of<16, 16>(axis, p);
+  }
+}
+
+AdjLayout adj_layout(const brahms_plan_s& p, int nsteps, int every) {
+  AdjLayout L;
+  L.every = every;
+  L.nsteps = nsteps;
+  L.nckpt = (nsteps + every - 1) / every;
+  L.field_bytes = sizeof(float2) * size_t(p.nx) * p.ny * p.nt;
+  const size_t state = align_up(L.field_bytes) * p.nf;
+  L.max_blocks = std::max(pass_blocks(AX_X, p), pass_blocks(AX_T, p));
+  size_t off = 0;
+  L.ckpt = off;
+  off += state * L.nckpt;
+  L.seg = off;
+  off += state * (every + 1);
+  L.pre = off;
+  off += state * every;
+  L.parts = off;
+  off = align_up(off + sizeof(double) * 3 * L.max_blocks);
+  L.dphi = off;
+  off = align_up(off + sizeof(double) * 6 * nsteps);
+  L.total = off;
+  return L;
+}
+
+float2* state_field(char* base, const AdjLayout& L, const brahms_plan_s& p, int slot, int j) {
+  return reinterpret_cast<float2*>(base + (size_t(slot) * p.nf + j) * align_up(L.field_bytes));
+}
+
+template <int N1, int N2, int AX, int NF, int AT>
+void launch_adj(const brahms_plan_s& p, const AdjArgs& a) {
+  using G = LineGeom<N1, N2>;
+  const long lines = AX == AX_X ? long(p.ny) * p.nt : long(p.nx) * p.ny;
+  const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
+  AdjArgs b = a;
+  b.tile_mul = AX == AX_T ? brahms::detail::tile_multiplier(grid.x) : 1u;
+  if (lines % G::LPB == 0)
+    hipLaunchKernelGGL((adjoint_pass<N1, N2, AX, NF, AT, true>), grid, dim3(kBlock), 0, p.stream, b);
+  else
+    hipLaunchKernelGGL((adjoint_pass<N1, N2, AX, NF, AT, false>), grid, dim3(kBlock), 0, p.stream, b);
+}
+
+template <int N1, int N2>
+void launch_adj_axis(int axis, int at, const brahms_plan_s& p, const AdjArgs& a) {
+  if (axis == AX_X) {
+    if (p.nf == 3) {
+      if (at == VJP_FIRST) launch_adj<N1, N2, AX_X, 3, VJP_FIRST>(p, a);
+      else launch_adj<N1, N2, AX_X, 3, VJP_LAST>(p, a);
+    } else {
+      if (at == VJP_FIRST) launch_adj<N1, N2, AX_X, 2, VJP_FIRST>(p, a);
+      else launch_adj<N1, N2, AX_X, 2, VJP_LAST>(p, a);
+    }
+  } else {
+    if (p.nf == 3) {
+      if (at == VJP_FIRST) launch_adj<N1, N2, AX_T, 3, VJP_FIRST>(p, a);
+      else launch_adj<N1, N2, AX_T, 3, VJP_LAST>(p, a);
+    } else {
+      if (at == VJP_FIRST) launch_adj<N1, N2, AX_T, 2, VJP_FIRST>(p, a);
+      else launch_adj<N1, N2, AX_T, 2, VJP_LAST>(p, a);
+    }
+  }
+}
+
+hipError_t dispatch_adj(int axis, int at, const brahms_plan_s& p, const AdjArgs& a) {
+  const int n = axis == AX_X ? p.nx : p.nt;
+  switch (n) {
+    case 1: launch_adj_axis<1, 1>(axis, at, p, a); break;
+    case 2: launch_adj_axis<2, 1>(axis, at, p, a); break;
+    case 4: launch_adj_axis<4, 1>(axis, at, p, a); break;
+    case 8: launch_adj_axis<4, 2>(axis, at, p, a); break;
+    case 16: launch_adj_axis<4, 4>(axis, at, p, a); break;
+    case 32: launch_adj_axis<8, 4>(axis, at, p, a); break;
+    case 64: launch_adj_axis<8, 8>(axis, at, p, a); break;
+    case 96: launch_adj_axis<24, 4>(axis, at, p, a); break;
+    case 128: launch_adj_axis<16, 8>(axis, at, p, a); break;
+    case 256: launch_adj_axis<16, 16>(axis, at, p, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+brahms_status copy_state(const brahms_plan_s& p, float2* const* dst, float2* const* src) {
+  const long n = long(p.nx) * p.ny * p.nt;
+  for (int j = 0; j < p.nf; ++j)
+    hipLaunchKernelGGL(copy_field, dim3(unsigned(std::min<long>((n + 255) / 256, 4096))), dim3(256), 0,
+                       p.stream, dst[j], src[j], n);
+  HIP_TRY(hipGetLastError());
+  return BRAHMS_OK;
+}
+
+// One adjoint pass with an RK4 reverse sweep, then the fixed-order reduction
+// of its phase derivatives into dphi_acc[0..2].
+brahms_status adj_pass(brahms_plan_s& p, const AdjLayout& L, int row, int k, float2* const* g,
+                       float2* const* y, double* dphi_acc) {
+  const int ax = brahms::detail::pass_axis(p, k);
+  const int per_field = p.nx + p.ny + p.nt;
+  const float2* r = brahms::detail::table_row(p, row);
+  AdjArgs a{};
+  for (int j = 0; j < 3; ++j) {
+    a.g[j] = j < p.nf ? g[j] : nullptr;
+    a.y[j] = j < p.nf ? y[j] : nullptr;
+  }
+  a.axis_off = ax == AX_X ? 0 : p.nx + p.ny;
+  a.tw = r + p.nf * per_field + a.axis_off;
+  a.consts = reinterpret_cast<const DftConsts*>(r + (p.nf + 1) * per_field);
+  a.prop = r;
+  a.field_stride = per_field;
+  a.nl = brahms::detail::nl_coefficients(p, row, k == 0 ? 0 : 1);
+  a.nx = p.nx; a.ny = p.ny; a.nt = p.nt;
+  double* parts = reinterpret_cast<double*>(p.adj_ws + L.parts);
+  a.dphi_out = parts;
+  // exp(-i Phi) on the sum-frequency field, exp(+i Phi) on the others
+  if (p.nf == 3) {
+    a.sigma[0] = -1.f; a.sigma[1] = 1.f; a.sigma[2] = 1.f;
+  } else {
+    a.sigma[0] = 1.f; a.sigma[1] = -1.f; a.sigma[2] = 0.f;
+  }
+  HIP_TRY(dispatch_adj(ax, k == 0 ? VJP_LAST : VJP_FIRST, p, a));
+  hipLaunchKernelGGL(reduce_dphi, dim3(1), dim3(256), 0, p.stream, parts, pass_blocks(ax, p), dphi_acc);
+  HIP_TRY(hipGetLastError());
+  return BRAHMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+brahms_status brahms_adjoint_workspace_size(brahms_plan plan, int nsteps, int checkpoint_every,
+                                            size_t* bytes) {
+  if (brahms_status st = check_plan(plan)) return st;
+  if (bytes == nullptr) return fail(BRAHMS_E_INVALID_ARG, "bytes is NULL");
+  if (nsteps < 1 || checkpoint_every < 1 || checkpoint_every > kChunk)
+    return fail(BRAHMS_E_INVALID_ARG, "need nsteps >= 1 and 1 <= checkpoint_every <= 64");
+  *bytes = adj_layout(*plan, nsteps, checkpoint_every).total;
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_adjoint_forward(brahms_plan plan, int nsteps, int checkpoint_every,
+                                     void* adj_workspace) {
+  if (brahms_status st = check_plan(plan)) return st;
+  brahms_plan_s& p = *plan;
+  if (!p.bound) return fail(BRAHMS_E_STATE, "brahms_adjoint_forward before brahms_plan_bind");
+  if (adj_workspace == nullptr || reinterpret_cast<uintptr_t>(adj_workspace) % 256 != 0)
+    return fail(BRAHMS_E_INVALID_ARG, "adjoint workspace must be a 256-byte aligned device pointer");
+  if (nsteps < 1 || checkpoint_every < 1 || checkpoint_every > kChunk)
+    return fail(BRAHMS_E_INVALID_ARG, "need nsteps >= 1 and 1 <= checkpoint_every <= 64");
+  if (!p.dk.empty() && p.step + nsteps > (long long)p.dk.size())
+    return fail(BRAHMS_E_INVALID_ARG, "steps beyond the end of the dk profile");
+  p.adj_ready = false;
+  p.adj_ws = static_cast<char*>(adj_workspace);
+  const AdjLayout L = adj_layout(p, nsteps, checkpoint_every);
+  p.adj_n0 = p.step;
+  p.adj_nsteps = nsteps;
+  p.adj_every = checkpoint_every;
+  float2* fields[3] = {p.fields[0], p.fields[1], p.fields[2]};
+  for (int c = 0; c < L.nckpt; ++c) {
+    float2* ck[3] = {nullptr, nullptr, nullptr};
+    for (int j = 0; j < p.nf; ++j) ck[j] = state_field(p.adj_ws + L.ckpt, L, p, c, j);
+    if (brahms_status st = copy_state(p, ck, fields)) return st;
+    const int cnt = std::min(checkpoint_every, nsteps - c * checkpoint_every);
+    if (brahms_status st = brahms_step(plan, cnt)) return st;
+  }
+  p.adj_ready = true;
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_adjoint_backward(brahms_plan plan, void* const* grad, double* grad_dk) {
+  if (brahms_status st = check_plan(plan)) return st;
+  brahms_plan_s& p = *plan;
+  if (!p.adj_ready) return fail(BRAHMS_E_STATE, "brahms_adjoint_backward before brahms_adjoint_forward");
+  if (grad == nullptr) return fail(BRAHMS_E_INVALID_ARG, "grad is NULL");
+  for (int j = 0; j < p.nf; ++j)
+    if (grad[j] == nullptr || reinterpret_cast<uintptr_t>(grad[j]) % 8 != 0)
+      return fail(BRAHMS_E_INVALID_ARG, "grad pointers must be non-NULL and 8-byte aligned");
+  const AdjLayout L = adj_layout(p, p.adj_nsteps, p.adj_every);
+  float2* g[3] = {nullptr, nullptr, nullptr};
+  for (int j = 0; j < p.nf; ++j) g[j] = static_cast<float2*>(grad[j]);
+  double* dphi = reinterpret_cast<double*>(p.adj_ws + L.dphi);
+  hipLaunchKernelGGL(zero_doubles, dim3(64), dim3(256), 0, p.stream, dphi, long(6) * p.adj_nsteps);
+  HIP_TRY(hipGetLastError());
+  const long long saved_step = p.step;
+  for (int c = L.nckpt - 1; c >= 0; --c) {
+    const long long s0 = p.adj_n0 + (long long)c * p.adj_every;
+    const int cnt = int(std::min<long long>(p.adj_every, p.adj_n0 + p.adj_nsteps - s0));
+    if (brahms_status st = brahms::detail::refresh_tables(p, s0, cnt)) return st;
+    // recompute the segment out of place, keeping inputs and pre-RK4 states
+    float2* slot0[3] = {nullptr, nullptr, nullptr};
+    float2* ck[3] = {nullptr, nullptr, nullptr};
+    for (int j = 0; j < p.nf; ++j) {
+      slot0[j] = state_field(p.adj_ws + L.seg, L, p, 0, j);
+      ck[j] = state_field(p.adj_ws + L.ckpt, L, p, c, j);
+    }
+    if (brahms_status st = copy_state(p, slot0, ck)) return st;
+    for (int i = 0; i < cnt; ++i) {
+      brahms::detail::StepIO io{};
+      for (int j = 0; j < p.nf; ++j) {
+        io.in[j] = state_field(p.adj_ws + L.seg, L, p, i, j);
+        io.out[j] = state_field(p.adj_ws + L.seg, L, p, i + 1, j);
+        io.pre[j] = state_field(p.adj_ws + L.pre, L, p, i, j);
+      }
+      if (brahms_status st = brahms::detail::launch_step(p, i, io)) return st;
+    }
+    // reverse sweep over the segment
+    for (int i = cnt - 1; i >= 0; --i) {
+      const long long r = s0 + i - p.adj_n0;
+      float2* y2[3] = {nullptr, nullptr, nullptr};
+      float2* y0[3] = {nullptr, nullptr, nullptr};
+      for (int j = 0; j < p.nf; ++j) {
+        y2[j] = state_field(p.adj_ws + L.pre, L, p, i, j);
+        y0[j] = state_field(p.adj_ws + L.seg, L, p, i, j);
+      }
+      if (brahms_status st = adj_pass(p, L, i, 2, g, y2, dphi + 6 * r + 3)) return st;
+      if (brahms_status st = brahms::detail::launch_linear_pass(p, i, AX_Y, g, true)) return st;
+      if (brahms_status st = adj_pass(p, L, i, 0, g, y0, dphi + 6 * r)) return st;
+    }
+  }
+  p.step = saved_step;
+  if (grad_dk != nullptr) {
+    std::vector<double> G(size_t(6) * p.adj_nsteps);
+    HIP_TRY(hipMemcpyAsync(G.data(), dphi, sizeof(double) * G.size(), hipMemcpyDeviceToHost, p.stream));
+    HIP_TRY(hipStreamSynchronize(p.stream));
+    // stage offsets z - z_n of the six dJ/dPhi entries of a step
+    const double off[6] = {0.0, 0.25 * p.dz, 0.5 * p.dz, 0.5 * p.dz, 0.75 * p.dz, p.dz};
+    if (p.dk.empty()) {
+      // Phi = dk z: dJ/ddk = sum over stages of z_s dJ/dPhi(z_s)
+      double acc = 0.0;
+      for (int r = 0; r < p.adj_nsteps; ++r)
+        for (int k = 0; k < 6; ++k)
+          acc += (double(p.adj_n0 + r) * p.dz + off[k]) * G[size_t(6) * r + k];
+      grad_dk[0] = acc;
+    } else {
+      const long long ndk = (long long)p.dk.size();
+      for (long long m = 0; m < ndk; ++m) grad_dk[m] = 0.0;
+      double later = 0.0;  // sum of dJ/dPhi over stages of steps after the current one
+      for (int r = p.adj_nsteps - 1; r >= 0; --r) {
+        double own = 0.0, tot = 0.0;
+        for (int k = 0; k < 6; ++k) {
+          own += off[k] * G[size_t(6) * r + k];
+          tot += G[size_t(6) * r + k];
+        }
+        grad_dk[p.adj_n0 + r] = own + p.dz * later;
+        later += tot;
+      }
+      for (long long m = 0; m < p.adj_n0; ++m) grad_dk[m] = p.dz * later;
+    }
+  }
+  return BRAHMS_OK;
+}
+
+}  // extern "C"

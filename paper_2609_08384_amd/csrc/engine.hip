@@ -17,10 +17,16 @@
 
 #include "../../include/brahms.h"
 #include "kernels.hpp"
+#include "plan.hpp"
 
 using namespace brahms;
+using brahms::detail::fail;
+using brahms::detail::kAlign;
+using brahms::detail::kChunk;
+using brahms::detail::align_up;
 
-namespace {
+namespace brahms {
+namespace detail {
 
 thread_local std::string g_last_error;
 
@@ -29,17 +35,17 @@ brahms_status fail(brahms_status st, const std::string& msg) {
   return st;
 }
 
-#define HIP_TRY(expr)                                                                \
-  do {                                                                               \
-    hipError_t e_ = (expr);                                                          \
-    if (e_ != hipSuccess)                                                            \
-      return fail(BRAHMS_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
+brahms_status check_plan(brahms_plan p) {
+  if (p == nullptr) return fail(BRAHMS_E_INVALID_ARG, "plan is NULL");
+  return BRAHMS_OK;
+}
 
-constexpr int kChunk = 64;   // steps per table refill
-constexpr size_t kAlign = 256;
+}  // namespace detail
+}  // namespace brahms
 
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+using brahms::detail::check_plan;
+
+namespace {
 
 bool supported_length(int n) {
   switch (n) {
@@ -51,28 +57,6 @@ bool supported_length(int n) {
 }
 
 }  // namespace
-
-struct brahms_plan_s {
-  int nx = 0, ny = 0, nt = 0, nf = 0;
-  double dz = 0, dx = 1, dy = 1, dt = 1, dk_const = 0;
-  std::vector<double> dk;      // per-step profile (empty: constant)
-  std::vector<double> phi0;    // Phi_n prefix of the profile
-  brahms_field_params fp[3] = {};
-  unsigned flags = 0;
-  hipStream_t stream = nullptr;
-  float2* fields[3] = {nullptr, nullptr, nullptr};
-  char* ws = nullptr;
-  bool bound = false;
-  long long step = 0;          // z = step * dz
-  int order = 0;               // 0: x, y, tau passes; 1: tau, y, x
-  // workspace offsets (bytes)
-  size_t off_phi0 = 0, off_dk = 0, off_prop = 0, off_nl = 0, off_flag = 0, ws_size = 0;
-  // launch timing (diagnostics)
-  bool timing = false;
-  struct Timed { int kind; hipEvent_t start, stop; };
-  std::vector<Timed> timed;             // one entry per timed launch
-  std::vector<hipEvent_t> pool;         // reusable events
-};
 
 namespace {
 
@@ -86,28 +70,7 @@ void launch_pass(bool full, dim3 grid, hipStream_t st, const PassArgs& a) {
   else hipLaunchKernelGGL((axis_pass<N1, N2, AX, NF, NL, false>), grid, dim3(kBlock), 0, st, a);
 }
 
-#ifndef BRAHMS_TILE_SPREAD
-#define BRAHMS_TILE_SPREAD 1
-#endif
-
-unsigned gcd_u(unsigned a, unsigned b) {
-  while (b) {
-    const unsigned r = a % b;
-    a = b;
-    b = r;
-  }
-  return a;
-}
-
-// Multiplier of the block -> tile permutation of the tau pass: coprime with
-// the tile count (so the map is a bijection) and about tiles/64, so that
-// consecutive blocks land about 1/64 of the plane apart.
-unsigned tile_multiplier(unsigned tiles) {
-  if (!BRAHMS_TILE_SPREAD || tiles < 128) return 1;
-  unsigned m = tiles / 64 + 1;
-  while (gcd_u(m, tiles) != 1) ++m;
-  return m;
-}
+using brahms::detail::tile_multiplier;
 
 template <int N1, int N2, int AX>
 void launch_nl(int nf, int nl, bool full, dim3 grid, hipStream_t st, const PassArgs& a) {
@@ -186,11 +149,6 @@ void layout(brahms_plan_s& p) {
   p.ws_size = off;
 }
 
-brahms_status check_plan(brahms_plan p) {
-  if (p == nullptr) return fail(BRAHMS_E_INVALID_ARG, "plan is NULL");
-  return BRAHMS_OK;
-}
-
 __global__ void clear_flag(int* flag) { *flag = 0; }
 
 constexpr size_t kMaxTimed = 65536;
@@ -223,61 +181,126 @@ brahms_status timing_stop(brahms_plan_s& p) {
   return BRAHMS_OK;
 }
 
-brahms_status run_steps(brahms_plan_s& p, int nsteps) {
+}  // namespace
+
+namespace brahms {
+namespace detail {
+
+const float2* table_row(const brahms_plan_s& p, int row) {
+  return reinterpret_cast<const float2*>(p.ws + p.off_prop) +
+         size_t(row) * table_row_stride(p.nf, p.nx, p.ny, p.nt);
+}
+
+const float2* nl_coefficients(const brahms_plan_s& p, int row, int half) {
+  return reinterpret_cast<const float2*>(p.ws + p.off_nl) + (size_t(row) * 2 + half) * p.nf * kNlCoef;
+}
+
+int pass_axis(const brahms_plan_s& p, int k) {
+  if (k == 1) return AX_Y;
+  if (k == 0) return p.order == 0 ? int(AX_X) : int(AX_T);
+  return p.order == 0 ? int(AX_T) : int(AX_X);
+}
+
+brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count) {
   const int per_field = p.nx + p.ny + p.nt;
-  const int row_stride = table_row_stride(p.nf, p.nx, p.ny, p.nt);
-  float2* prop = reinterpret_cast<float2*>(p.ws + p.off_prop);
-  float2* nl = reinterpret_cast<float2*>(p.ws + p.off_nl);
+  TableArgs ta{};
+  ta.rows = reinterpret_cast<float2*>(p.ws + p.off_prop);
+  ta.row_stride = table_row_stride(p.nf, p.nx, p.ny, p.nt);
+  ta.nl = reinterpret_cast<float2*>(p.ws + p.off_nl);
+  ta.phi0 = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_phi0);
+  ta.dk = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_dk);
+  ta.n0 = n0;
+  ta.count = count;
+  ta.nx = p.nx; ta.ny = p.ny; ta.nt = p.nt; ta.nf = p.nf;
+  ta.dz = p.dz; ta.dx = p.dx; ta.dy = p.dy; ta.dt = p.dt; ta.dk_const = p.dk_const;
+  for (int j = 0; j < p.nf; ++j) {
+    const brahms_field_params& f = p.fp[j];
+    ta.fc[j] = FieldCoef{f.kappa, f.diffraction, f.tan_rho, f.delay, f.k2, f.k3, f.alpha};
+  }
+  const long total = long(count) * ((p.nf + 1) * per_field + 1) + long(count) * 2 * p.nf;
+  const bool timed = p.timing && p.timed.size() < kMaxTimed;
+  if (brahms_status st = timing_start(p, 3)) return st;
+  hipLaunchKernelGGL(step_tables, dim3(unsigned((total + 255) / 256)), dim3(256), 0, p.stream, ta);
+  HIP_TRY(hipGetLastError());
+  if (timed)
+    if (brahms_status st = timing_stop(p)) return st;
+  return BRAHMS_OK;
+}
+
+namespace {
+
+PassArgs pass_args(const brahms_plan_s& p, int row, int ax) {
+  const int per_field = p.nx + p.ny + p.nt;
+  const float2* r = table_row(p, row);
+  PassArgs a{};
+  a.axis_off = (ax == AX_X) ? 0 : (ax == AX_Y ? p.nx : p.nx + p.ny);
+  a.tw = r + p.nf * per_field + a.axis_off;
+  a.consts = reinterpret_cast<const DftConsts*>(r + (p.nf + 1) * per_field);
+  a.nx = p.nx; a.ny = p.ny; a.nt = p.nt;
+  a.prop = r;
+  a.field_stride = per_field;
+  return a;
+}
+
+brahms_status timed_dispatch(brahms_plan_s& p, int ax, int nlmode, const PassArgs& a) {
   const int n[3] = {p.nx, p.ny, p.nt};
+  const bool timed = p.timing && p.timed.size() < kMaxTimed;
+  if (brahms_status st = timing_start(p, ax)) return st;
+  HIP_TRY(dispatch_axis(n[ax], ax, nlmode, p.nf, p, a));
+  if (timed)
+    if (brahms_status st = timing_stop(p)) return st;
+  return BRAHMS_OK;
+}
+
+}  // namespace
+
+brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io) {
+  // pass order of the step: the first pass carries the first RK4 half-step,
+  // the last pass the second one (the axis operators commute)
+  for (int k = 0; k < 3; ++k) {
+    const int ax = pass_axis(p, k);
+    const int nlmode = k == 0 ? NL_BEFORE : (k == 2 ? NL_AFTER : NL_NONE);
+    PassArgs a = pass_args(p, row, ax);
+    for (int j = 0; j < 3; ++j) {
+      a.f[j] = k == 0 ? io.in[j] : io.out[j];
+      a.fo[j] = io.out[j];
+      a.pre[j] = k == 2 ? io.pre[j] : nullptr;
+    }
+    a.nl = nl_coefficients(p, row, k == 0 ? 0 : 1);
+    if (brahms_status st = timed_dispatch(p, ax, nlmode, a)) return st;
+  }
+  return BRAHMS_OK;
+}
+
+brahms_status launch_linear_pass(brahms_plan_s& p, int row, int axis, float2* const* fields,
+                                 bool conj) {
+  if (axis != AX_Y) return fail(BRAHMS_E_INVALID_ARG, "linear-only passes run along y");
+  PassArgs a = pass_args(p, row, axis);
+  for (int j = 0; j < 3; ++j) {
+    a.f[j] = fields[j];
+    a.fo[j] = fields[j];
+  }
+  a.conj = conj ? 1 : 0;
+  return timed_dispatch(p, axis, NL_NONE, a);
+}
+
+}  // namespace detail
+}  // namespace brahms
+
+namespace {
+
+brahms_status run_steps(brahms_plan_s& p, int nsteps) {
+  detail::StepIO io{};
+  for (int j = 0; j < 3; ++j) {
+    io.in[j] = p.fields[j];
+    io.out[j] = p.fields[j];
+  }
   int done = 0;
   while (done < nsteps) {
     const int count = std::min(kChunk, nsteps - done);
-    TableArgs ta{};
-    ta.rows = prop;
-    ta.row_stride = row_stride;
-    ta.nl = nl;
-    ta.phi0 = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_phi0);
-    ta.dk = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_dk);
-    ta.n0 = p.step;
-    ta.count = count;
-    ta.nx = p.nx; ta.ny = p.ny; ta.nt = p.nt; ta.nf = p.nf;
-    ta.dz = p.dz; ta.dx = p.dx; ta.dy = p.dy; ta.dt = p.dt; ta.dk_const = p.dk_const;
-    for (int j = 0; j < p.nf; ++j) {
-      const brahms_field_params& f = p.fp[j];
-      ta.fc[j] = FieldCoef{f.kappa, f.diffraction, f.tan_rho, f.delay, f.k2, f.k3, f.alpha};
-    }
-    const long total = long(count) * ((p.nf + 1) * per_field + 1) + long(count) * 2 * p.nf;
-    const bool timed_tab = p.timing && p.timed.size() < kMaxTimed;
-    if (brahms_status st = timing_start(p, 3)) return st;
-    hipLaunchKernelGGL(step_tables, dim3(unsigned((total + 255) / 256)), dim3(256), 0, p.stream, ta);
-    HIP_TRY(hipGetLastError());
-    if (timed_tab)
-      if (brahms_status st = timing_stop(p)) return st;
-    for (int s = 0; s < count; ++s) {
-      const float2* row = prop + size_t(s) * row_stride;
-      // pass order of the step: the first pass carries the first RK4
-      // half-step, the last pass the second one (the axis operators commute)
-      const int seq[3] = {p.order == 0 ? int(AX_X) : int(AX_T), int(AX_Y),
-                          p.order == 0 ? int(AX_T) : int(AX_X)};
-      for (int k = 0; k < 3; ++k) {
-        const int ax = seq[k];
-        const int nlmode = k == 0 ? NL_BEFORE : (k == 2 ? NL_AFTER : NL_NONE);
-        PassArgs a{};
-        for (int j = 0; j < 3; ++j) a.f[j] = p.fields[j];
-        a.axis_off = (ax == AX_X) ? 0 : (ax == AX_Y ? p.nx : p.nx + p.ny);
-        a.tw = row + p.nf * per_field + a.axis_off;
-        a.consts = reinterpret_cast<const DftConsts*>(row + (p.nf + 1) * per_field);
-        a.nx = p.nx; a.ny = p.ny; a.nt = p.nt;
-        a.nl = nl + (size_t(s) * 2 + (k == 0 ? 0 : 1)) * p.nf * kNlCoef;
-        a.prop = row;
-        a.field_stride = per_field;
-        const bool timed = p.timing && p.timed.size() < kMaxTimed;
-        if (brahms_status st = timing_start(p, ax)) return st;
-        HIP_TRY(dispatch_axis(n[ax], ax, nlmode, p.nf, p, a));
-        if (timed)
-          if (brahms_status st = timing_stop(p)) return st;
-      }
-    }
+    if (brahms_status st = detail::refresh_tables(p, p.step, count)) return st;
+    for (int s = 0; s < count; ++s)
+      if (brahms_status st = detail::launch_step(p, s, io)) return st;
     p.step += count;
     done += count;
   }
@@ -288,11 +311,11 @@ brahms_status run_steps(brahms_plan_s& p, int nsteps) {
 
 extern "C" {
 
-const char* brahms_last_error(void) { return g_last_error.c_str(); }
+const char* brahms_last_error(void) { return brahms::detail::g_last_error.c_str(); }
 
 brahms_status brahms_plan_create(int nx, int ny, int nt, int nfields, const brahms_params* params,
                                  void* hip_stream, brahms_plan* out) {
-  g_last_error.clear();
+  brahms::detail::g_last_error.clear();
   if (out == nullptr) return fail(BRAHMS_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (params == nullptr) return fail(BRAHMS_E_INVALID_ARG, "params is NULL");

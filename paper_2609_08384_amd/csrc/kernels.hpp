@@ -30,7 +30,11 @@ enum Axis { AX_X = 0, AX_Y = 1, AX_T = 2 };
 enum NlMode { NL_NONE = 0, NL_BEFORE = 1, NL_AFTER = 2 };
 
 struct PassArgs {
-  float2* f[3];          // field base pointers (complex64, [nt][ny][nx])
+  float2* f[3];          // fields read (complex64, [nt][ny][nx])
+  float2* fo[3];         // fields written (== f for an in-place pass)
+  float2* pre[3];        // if pre[0]: the last pass also stores its values
+                         // just before the RK4 half-step here
+  int conj;              // multiply by conj(P) (adjoint linear step)
   const float2* tw;      // this step's forward twiddles exp(-2 pi i m / N), m < N
   const float2* prop;    // this step's propagators, field j's table of this
                          // axis at prop + j * field_stride + axis_off
@@ -202,8 +206,11 @@ __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass(PassArgs 
   const int field0 = (AX == AX_Y) ? int(blockIdx.z) : 0;
   // this step's twiddles and this block's propagators, staged once
   for (int i = tid; i < N; i += kBlock) s_tw[i] = args.tw[i];
-  for (int i = tid; i < NF * N; i += kBlock)
-    s_prop[i] = args.prop[(field0 + i / N) * args.field_stride + args.axis_off + i % N];
+  for (int i = tid; i < NF * N; i += kBlock) {
+    float2 pv = args.prop[(field0 + i / N) * args.field_stride + args.axis_off + i % N];
+    if (args.conj) pv.y = -pv.y;
+    s_prop[i] = pv;
+  }
 
   int t, li;
   unsigned base, estride;
@@ -239,7 +246,7 @@ __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass(PassArgs 
 #pragma unroll
   for (int j = 0; j < NF; ++j) {
     fin[j] = args.f[field0 + j];
-    fout[j] = args.f[field0 + j];
+    fout[j] = args.fo[field0 + j];
   }
   const unsigned idx0 = base + unsigned(t) * estride;
   const unsigned estep = unsigned(N2) * estride;
@@ -287,6 +294,12 @@ __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass(PassArgs 
   }
 
   if constexpr (NL == NL_AFTER) {
+    if (args.pre[0] != nullptr && valid) {
+#pragma unroll
+      for (int j = 0; j < NF; ++j)
+#pragma unroll
+        for (int e = 0; e < N1; ++e) store_field<NT>(args.pre[j], idx0 + unsigned(e) * estep, v[j][e]);
+    }
     float2 co[NF][kNlCoef];
 #pragma unroll
     for (int j = 0; j < NF; ++j)
@@ -402,7 +415,7 @@ __device__ inline float stochastic_round(double v, unsigned bits) {
   return (u < p) ? hi : lo;
 }
 
-__global__ void step_tables(TableArgs a) {
+static __global__ void step_tables(TableArgs a) {
   const int per_field = a.nx + a.ny + a.nt;
   const int per_step = (a.nf + 1) * per_field + 1;  // + one thread for DftConsts
   const long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -504,7 +517,7 @@ __global__ void step_tables(TableArgs a) {
 
 // Set a flag when any field value is not finite (the step-size hazard of
 // Sec. 3.2: a too-large dz makes the nonlinear increment blow up).
-__global__ void finite_check(const float2* f, long n, int* flag) {
+static __global__ void finite_check(const float2* f, long n, int* flag) {
   long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
   const long stride = long(gridDim.x) * blockDim.x;
   int bad = 0;

@@ -1,0 +1,98 @@
+// Internal host-side state of a plan, shared by the engine's translation
+// units (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/brahms.h"
+
+struct brahms_plan_s {
+  int nx = 0, ny = 0, nt = 0, nf = 0;
+  double dz = 0, dx = 1, dy = 1, dt = 1, dk_const = 0;
+  std::vector<double> dk;      // per-step profile (empty: constant)
+  std::vector<double> phi0;    // Phi_n prefix of the profile
+  brahms_field_params fp[3] = {};
+  unsigned flags = 0;
+  hipStream_t stream = nullptr;
+  float2* fields[3] = {nullptr, nullptr, nullptr};
+  char* ws = nullptr;
+  bool bound = false;
+  long long step = 0;          // z = step * dz
+  int order = 0;               // 0: x, y, tau passes; 1: tau, y, x
+  // workspace offsets (bytes)
+  size_t off_phi0 = 0, off_dk = 0, off_prop = 0, off_nl = 0, off_flag = 0, ws_size = 0;
+  // launch timing (diagnostics)
+  bool timing = false;
+  struct Timed { int kind; hipEvent_t start, stop; };
+  std::vector<Timed> timed;             // one entry per timed launch
+  std::vector<hipEvent_t> pool;         // reusable events
+  // adjoint record (set by brahms_adjoint_forward)
+  bool adj_ready = false;
+  long long adj_n0 = 0;
+  int adj_nsteps = 0, adj_every = 0;
+  char* adj_ws = nullptr;
+};
+
+namespace brahms {
+namespace detail {
+
+constexpr int kChunk = 64;     // steps per table refill (rows in the workspace)
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+brahms_status fail(brahms_status st, const std::string& msg);
+
+#define HIP_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return ::brahms::detail::fail(BRAHMS_E_DEVICE,                                           \
+                                    std::string(#expr) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+brahms_status check_plan(brahms_plan p);
+
+// Multiplier of the block -> tile permutation of the tau pass: coprime with
+// the tile count (so the map is a bijection) and about tiles/64, so that
+// consecutive blocks land about 1/64 of the plane apart.
+inline unsigned tile_multiplier(unsigned tiles) {
+  if (tiles < 128) return 1;
+  unsigned m = tiles / 64 + 1;
+  for (;; ++m) {
+    unsigned a = m, b = tiles;
+    while (b) {
+      const unsigned r = a % b;
+      a = b;
+      b = r;
+    }
+    if (a == 1) return m;
+  }
+}
+
+// Where one z-step reads and writes: the first pass reads `in` and writes
+// `out`, the other two passes work in place on `out`; when `pre` is given the
+// last pass also stores the input of the second RK4 half-step there.
+struct StepIO {
+  float2* in[3];
+  float2* out[3];
+  float2* pre[3];
+};
+
+// Fill table rows 0..count-1 for steps n0..n0+count-1.
+brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count);
+// One z-step with the tables of `row`.
+brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io);
+// The axis of the k-th pass of a step (k = 0, 1, 2) under the plan's order.
+int pass_axis(const brahms_plan_s& p, int k);
+// A linear-only pass (FFT . P . IFFT, or with conj(P)) along `axis`, in place.
+brahms_status launch_linear_pass(brahms_plan_s& p, int row, int axis, float2* const* fields,
+                                 bool conj);
+const float2* table_row(const brahms_plan_s& p, int row);
+const float2* nl_coefficients(const brahms_plan_s& p, int row, int half);
+
+}  // namespace detail
+}  // namespace brahms

@@ -1,0 +1,94 @@
+"""GPU adjoint (hand-written reverse sweep behind torch.autograd) against the
+oracle's own adjoint (autograd through the FP64 loop)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint as oadj
+from oracle import ssfm
+from paper_2609_08384_amd import autograd, brahms, inputs
+from tests.util import oracle_problem, rel_l2
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _case(nf, shape, nz, seed, profile=True):
+    nx, ny, nt = shape
+    rng = np.random.default_rng(seed)
+    base = [dict(kappa=1.2, diffraction=0.9, tan_rho=0.4, delay=-0.3, k2=0.7),
+            dict(kappa=0.8, diffraction=0.5, tan_rho=-0.2, delay=0.2, k2=-0.6),
+            dict(kappa=0.6, diffraction=1.4, delay=0.5, k2=0.3)]
+    fields = [inputs.FieldSpec(**base[j]) for j in range(nf)]
+    init = inputs.random_fields(rng, nf, nx, ny, nt, scale=0.8, smooth=min(nx, ny, nt) / 2.5)
+    dk = (2.0 + 0.7 * rng.standard_normal(nz)) if profile else None
+    wl = inputs.Workload("adj", nx, ny, nt, nf, nz, 1.0 / nz, fields, dk_const=1.7, dk=dk)
+    wl.init = init
+    return wl
+
+
+def _loss(out):
+    return -(out[-1].abs() ** 2).sum()  # energy of the last field (SH or idler)
+
+
+def _gpu_grads(wl, every, order=None):
+    params = brahms.params_from_workload(wl)
+    x = [torch.from_numpy(a).to(DEV).requires_grad_(True) for a in wl.init]
+    dk = None if wl.dk is None else torch.tensor(wl.dk, dtype=torch.float64, requires_grad=True)
+    out = autograd.ssfm(x, params, wl.nz, dk=dk, checkpoint_every=every, pass_order=order)
+    loss = _loss([o.to(torch.complex128) for o in out])
+    loss.backward()
+    g = [t.grad.cpu().numpy() for t in x]
+    gdk = None if dk is None else dk.grad.numpy()
+    return float(loss), g, gdk, [o.detach().cpu().numpy() for o in out]
+
+
+def _oracle_grads(wl):
+    prob = oracle_problem(wl)
+    dk = list(wl.dk) if wl.dk is not None else [wl.dk_const] * wl.nz
+    prob.dk = dk
+    loss = lambda out, p: -(out[-1].abs() ** 2).sum()
+    j, g, gdk = oadj.gradients([torch.from_numpy(a) for a in wl.init], dk, prob, wl.nz, loss=loss)
+    return j, [x.numpy() for x in g], gdk.numpy()
+
+
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("nf,shape,nz,every", [(2, (16, 16, 8), 12, 5), (3, (8, 16, 16), 9, 4),
+                                                (2, (32, 8, 16), 7, 7)])
+def test_adjoint_matches_oracle(nf, shape, nz, every, order):
+    wl = _case(nf, shape, nz, seed=nf * 10 + nz)
+    jg, g, gdk, _ = _gpu_grads(wl, every, order)
+    jo, go, gdko = _oracle_grads(wl)
+    assert abs(jg - jo) < 1e-5 * abs(jo)
+    for j in range(nf):
+        assert rel_l2(g[j], go[j]) < 1e-4, j
+    assert rel_l2(gdk, gdko) < 1e-4
+
+
+def test_adjoint_constant_dk_is_sum_of_profile_gradient():
+    wl = _case(2, (16, 8, 8), 10, seed=3, profile=False)
+    params = brahms.params_from_workload(wl)
+    fields = [torch.from_numpy(a).to(DEV) for a in wl.init]
+    plan = brahms.Plan(wl.nx, wl.ny, wl.nt, 2, params).bind(fields)
+    plan.adjoint_forward(wl.nz, 4)
+    g = [torch.zeros_like(f) for f in fields]
+    g[1].copy_(-2 * fields[1])   # dJ/dS* convention of J = -sum |S|^2
+    gdk = plan.adjoint_backward(g)
+    _, _, gdko = _oracle_grads(wl)
+    assert gdk.shape == (1,)
+    assert abs(gdk[0] - gdko.sum()) < 1e-4 * abs(gdko.sum())
+
+
+def test_adjoint_forward_equals_plain_step():
+    wl = _case(3, (16, 16, 16), 11, seed=4)
+    params = brahms.params_from_workload(wl)
+    a = [torch.from_numpy(x).to(DEV) for x in wl.init]
+    b = [x.clone() for x in a]
+    p1 = brahms.Plan(16, 16, 16, 3, params).bind(a)
+    p1.step(wl.nz)
+    p2 = brahms.Plan(16, 16, 16, 3, params).bind(b)
+    p2.adjoint_forward(wl.nz, 4)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    assert abs(p2.z - p1.z) < 1e-15
