@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--timing-steps", type=int, default=200,
                     help="z-steps of the event-timed run used for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the adjoint and batched-sweep side measurements")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle z-steps in the CPU sample")
     ap.add_argument("--pass-order", default="auto", choices=["auto", "0", "1"],
                     help="plan schedule: autotuned (default) or a fixed pass order")
@@ -65,6 +67,97 @@ def copy_calibration():
     ms = ev0.elapsed_time(ev1) / reps
     print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "avg_ms": ms,
                       "GBps_read_plus_write": 2 * n / (ms * 1e-3) / 1e9}), flush=True)
+
+
+def adjoint_ratio(dev, reps=3):
+    """Inverse-design workload (SHG 128x128x64, 400 steps, per-step dk profile,
+    checkpoints every 20 steps): time of (forward with checkpoints + reverse
+    sweep) over the time of a plain forward solve, medians of `reps` runs."""
+    import torch
+    from paper_2609_08384_amd import brahms, inputs
+    wl = inputs.shg_adjoint()
+    params = brahms.params_from_workload(wl)
+    init = [torch.from_numpy(a).to(dev) for a in wl.init]
+
+    def run(adjoint):
+        fields = [a.clone() for a in init]
+        plan = brahms.Plan(wl.nx, wl.ny, wl.nt, wl.nf, params).bind(fields)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if adjoint:
+            plan.adjoint_forward(wl.nz, 20)
+            g = [torch.zeros_like(f) for f in fields]
+            g[1].copy_(-2 * fields[1])      # J = -sum |S(L)|^2
+            plan.adjoint_backward(g)
+        else:
+            plan.step(wl.nz)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        plan.destroy()
+        return dt
+
+    run(False)
+    run(True)
+    fwd = sorted(run(False) for _ in range(reps))[reps // 2]
+    adj = sorted(run(True) for _ in range(reps))[reps // 2]
+    return {"workload": f"{wl.name}: SHG {wl.nx}x{wl.ny}x{wl.nt}, {wl.nz} z-steps, per-step dk, "
+                        "checkpoint every 20 steps",
+            "forward_ms": fwd * 1e3, "forward_plus_adjoint_ms": adj * 1e3, "ratio": adj / fwd}
+
+
+def batch_ratio(dev):
+    """Seeded SHG sweep (64 problems over 64^3, 96x96x64, 128x128x64 and
+    128x128x256 grids, dk L in [-6, 6], xi in [0.1, 10], 200-600 steps): one
+    batched run (autotuned, hipGraph) against the same 64 problems propagated
+    one after another with plain plans (tuned pass order)."""
+    import torch
+    from paper_2609_08384_amd import autotune, brahms, inputs
+    wls = inputs.shg_sweep(seed=4, count=64)
+    probs = [(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls]
+    init = [[torch.from_numpy(a).to(dev) for a in w.init] for w in wls]
+    fields = [[a.clone() for a in fs] for fs in init]
+
+    def reset():
+        for fs, gs in zip(fields, init):
+            for f, g in zip(fs, gs):
+                f.copy_(g)
+        torch.cuda.synchronize()
+
+    batch = brahms.Batch(probs)
+    tuned = autotune.tune_batch(batch, dev)
+    batch.bind(fields)
+    batch.run()                      # builds the graph
+    reset()
+    t0 = time.perf_counter()
+    batch.run()
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    groups = batch.groups()
+    batch.destroy()
+
+    plans = []
+    for w, fs, o in zip(wls, fields, tuned["pass_orders"]):
+        pl = brahms.Plan(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w))
+        pl.set_schedule(o)
+        plans.append(pl.bind(fs))
+    for pl in plans:                 # first launches of every kernel variant
+        pl.step(2)
+        pl.set_z(0.0)
+    reset()
+    t0 = time.perf_counter()
+    for pl, w in zip(plans, wls):
+        pl.propagate(w.nz * w.dz)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    for pl in plans:
+        pl.destroy()
+    work = sum(w.points * w.nz for w in wls)
+    return {"workload": "SHG sweep: 64 problems, grids 64^3 / 96x96x64 / 128x128x64 / 128x128x256, "
+                        "200-600 steps (seed 4)",
+            "grid_point_steps": work, "batched_ms": t_batch * 1e3, "sequential_ms": t_seq * 1e3,
+            "speedup": t_seq / t_batch, "batched_rate": work / t_batch,
+            "sequential_rate": work / t_seq, "launch_groups": groups,
+            "group_max": tuned["group_max"]}
 
 
 def make_workload(name):
@@ -172,6 +265,11 @@ def main():
     step_bytes = 3 * bytes_per_launch
     plan.destroy()
 
+    extras = {}
+    if not args.no_extras:
+        extras["adjoint"] = adjoint_ratio(dev)
+        extras["batch"] = batch_ratio(dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         del fields, init
@@ -201,6 +299,9 @@ def main():
         "event_ms_per_step": ev_ms / steps,
         "per_kernel": per_kernel,
         "fields_finite": finite,
+        "adjoint_over_forward": extras.get("adjoint", {}).get("ratio"),
+        "batched_over_sequential": extras.get("batch", {}).get("speedup"),
+        "extras": extras,
     }
     print(json.dumps(out), flush=True)
 

@@ -180,6 +180,37 @@ brahms_status brahms_adjoint_forward(brahms_plan plan, int nsteps, int checkpoin
                                      void* adj_workspace);
 brahms_status brahms_adjoint_backward(brahms_plan plan, void* const* grad, double* grad_dk);
 
+/* Batched sweeps: many independent problems (each its own grid, fields and
+ * parameters, e.g. a scan of dk or of the focusing, as the parameter-sweep
+ * tab of Sec. 4.4 runs them one after another) propagated together.
+ * Problems of equal shape, field count and pass order share launches, in
+ * groups of at most group_max problems (0 = sized so that a group's fields
+ * fit a 160 MB cache budget); the whole run is captured once into a hipGraph
+ * on the batch's own stream and replayed, ordered after work already queued
+ * on the caller's stream and before work queued there afterwards.
+ *
+ * brahms_batch_create: n problems; shapes holds n x 4 ints (nx, ny, nt, nf),
+ *   params n brahms_params, nsteps n step counts (each problem is propagated
+ *   nsteps[i] steps from z = 0 by every run).  Per-problem errors as for
+ *   brahms_plan_create.
+ * brahms_batch_set_schedule: launch-group size and (optional, n entries)
+ *   pass orders; invalidates the binding (bind again).
+ * brahms_batch_bind: fields holds sum(nf_i) device pointers, problem-major,
+ *   each in the field layout of brahms_plan_bind; workspace as for plans.
+ * brahms_batch_run: propagate every problem nsteps[i] steps from z = 0
+ *   (asynchronous; the first run also builds the graph).
+ * brahms_batch_groups: number of launch groups and their sizes (members may
+ *   be NULL or hold one int per group). */
+typedef struct brahms_batch_s* brahms_batch;
+brahms_status brahms_batch_create(int n, const int* shapes, const brahms_params* params,
+                                  const int* nsteps, void* hip_stream, brahms_batch* out);
+brahms_status brahms_batch_set_schedule(brahms_batch batch, int group_max, const int* pass_order);
+brahms_status brahms_batch_workspace_size(brahms_batch batch, size_t* bytes);
+brahms_status brahms_batch_bind(brahms_batch batch, void* const* fields, void* workspace);
+brahms_status brahms_batch_run(brahms_batch batch);
+brahms_status brahms_batch_groups(brahms_batch batch, int* ngroups, int* members);
+brahms_status brahms_batch_destroy(brahms_batch batch);
+
 /* Thread-local message for the last failing call (empty if none). */
 const char* brahms_last_error(void);
 

@@ -109,3 +109,37 @@ def apply(plan: brahms.Plan, device="cuda:0") -> dict:
     sched = tune(plan.nx, plan.ny, plan.nt, plan.nf, plan.params, device)
     plan.set_schedule(**sched)
     return sched
+
+
+GROUP_CANDIDATES = (0, 1 << 30)   # cache-budget groups, or every same-shape problem at once
+
+
+def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64) -> dict:
+    """Pick pass orders (per shape, via tune) and the launch-group size of a
+    batch by timing a copy of it on scratch fields with at most max_steps
+    steps per problem; applies the choice to `batch`."""
+    orders = []
+    for (nx, ny, nt, nf, prm, _) in batch.problems:
+        orders.append(tune(nx, ny, nt, nf, prm, device)["pass_order"])
+    probe = brahms.Batch([(nx, ny, nt, nf, prm, min(ns, max_steps))
+                          for (nx, ny, nt, nf, prm, ns) in batch.problems])
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    fields = [[(0.1 * torch.randn(nt, ny, nx, dtype=torch.complex64, generator=gen)).to(device)
+               for _ in range(nf)] for (nx, ny, nt, nf, _, _) in batch.problems]
+    times = []
+    for gm in GROUP_CANDIDATES:
+        probe.set_schedule(gm, orders)
+        probe.bind(fields)
+        probe.run()
+        torch.cuda.synchronize(device)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        probe.run()
+        ev1.record()
+        torch.cuda.synchronize(device)
+        times.append((ev0.elapsed_time(ev1), gm))
+    probe.destroy()
+    best_ms, best = min(times)
+    batch.set_schedule(best, orders)
+    return {"group_max": best, "pass_orders": orders,
+            "probe_ms": {str(g): t for t, g in times}}

@@ -83,6 +83,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "brahms_adjoint_workspace_size": [vp, i, i, ctypes.POINTER(ctypes.c_size_t)],
         "brahms_adjoint_forward": [vp, i, i, vp],
         "brahms_adjoint_backward": [vp, ctypes.POINTER(vp), ctypes.POINTER(d)],
+        "brahms_batch_create": [i, ctypes.POINTER(i), ctypes.POINTER(ParamsC), ctypes.POINTER(i), vp,
+                                ctypes.POINTER(vp)],
+        "brahms_batch_set_schedule": [vp, i, ctypes.POINTER(i)],
+        "brahms_batch_workspace_size": [vp, ctypes.POINTER(ctypes.c_size_t)],
+        "brahms_batch_bind": [vp, ctypes.POINTER(vp), vp],
+        "brahms_batch_run": [vp],
+        "brahms_batch_groups": [vp, ctypes.POINTER(i), ctypes.POINTER(i)],
+        "brahms_batch_destroy": [vp],
         "brahms_timing_enable": [vp, i],
         "brahms_timing_read": [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)],
     }
@@ -299,3 +307,91 @@ def run_workload(wl, nsteps: Optional[int] = None, device: str = "cuda:0",
     torch.cuda.synchronize()
     plan.destroy()
     return fields
+
+
+class Batch:
+    """brahms_batch: many independent problems propagated together.
+
+    problems: sequence of (nx, ny, nt, nf, Params, nsteps).  Every run
+    propagates problem i nsteps[i] steps from z = 0.
+    """
+
+    def __init__(self, problems, stream: Optional[torch.cuda.Stream] = None):
+        self._lib = load_library()
+        self.problems = list(problems)
+        n = len(self.problems)
+        shapes = (ctypes.c_int * (4 * n))()
+        params = (ParamsC * n)()
+        steps = (ctypes.c_int * n)()
+        self._keep = []
+        for k, (nx, ny, nt, nf, prm, ns) in enumerate(self.problems):
+            shapes[4 * k: 4 * k + 4] = [nx, ny, nt, nf]
+            c, keep = _params_c(prm, nf)
+            params[k] = c
+            self._keep.append(keep)
+            steps[k] = int(ns)
+        handle = ctypes.c_void_p()
+        sptr = ctypes.c_void_p(stream.cuda_stream if stream is not None else
+                               (torch.cuda.current_stream().cuda_stream
+                                if torch.cuda.is_available() else 0))
+        _check(self._lib.brahms_batch_create(n, shapes, params, steps, sptr, ctypes.byref(handle)),
+               "brahms_batch_create")
+        self._h = handle
+        self.workspace = None
+        self.fields = None
+
+    def set_schedule(self, group_max: int = 0, pass_orders: Optional[Sequence[int]] = None):
+        arr = None
+        if pass_orders is not None:
+            arr = (ctypes.c_int * len(self.problems))(*[int(v) for v in pass_orders])
+        _check(self._lib.brahms_batch_set_schedule(self._h, int(group_max), arr),
+               "brahms_batch_set_schedule")
+        if self.fields is not None:
+            self.bind(self.fields)
+
+    def workspace_bytes(self) -> int:
+        out = ctypes.c_size_t()
+        _check(self._lib.brahms_batch_workspace_size(self._h, ctypes.byref(out)),
+               "brahms_batch_workspace_size")
+        return int(out.value)
+
+    def bind(self, fields):
+        """fields: one list of nf complex64 CUDA tensors [nt, ny, nx] per problem."""
+        ptrs = []
+        for (nx, ny, nt, nf, _, _), fs in zip(self.problems, fields):
+            if len(fs) != nf:
+                raise ValueError("wrong number of fields for a problem")
+            for f in fs:
+                if (f.dtype != torch.complex64 or not f.is_cuda or not f.is_contiguous()
+                        or tuple(f.shape) != (nt, ny, nx)):
+                    raise ValueError("fields must be contiguous complex64 CUDA tensors [nt, ny, nx]")
+                ptrs.append(f.data_ptr())
+        nbytes = self.workspace_bytes()
+        if self.workspace is None or self.workspace.numel() < nbytes + 256:
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=fields[0][0].device)
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
+        _check(self._lib.brahms_batch_bind(self._h, arr, ctypes.c_void_p(aligned)), "brahms_batch_bind")
+        self.fields = [list(fs) for fs in fields]
+        return self
+
+    def run(self):
+        _check(self._lib.brahms_batch_run(self._h), "brahms_batch_run")
+
+    def groups(self):
+        n = ctypes.c_int()
+        _check(self._lib.brahms_batch_groups(self._h, ctypes.byref(n), None), "brahms_batch_groups")
+        arr = (ctypes.c_int * max(1, n.value))()
+        _check(self._lib.brahms_batch_groups(self._h, ctypes.byref(n), arr), "brahms_batch_groups")
+        return [arr[k] for k in range(n.value)]
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(self._lib.brahms_batch_destroy(self._h), "brahms_batch_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

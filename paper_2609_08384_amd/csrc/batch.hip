@@ -1,0 +1,436 @@
+// Batched parameter sweeps behind the C ABI (brahms_batch_*; see
+// include/brahms.h).
+//
+// A batch holds many independent problems, each with its own grid, fields
+// and parameters.  Problems of the same shape, field count and pass order
+// form launch groups of at most `group_max` problems; one launch of a pass
+// covers every problem of a group (the problem index is a grid dimension and
+// each block reads its problem's pass arguments from a descriptor array), so
+// small grids fill the GPU.  Groups run one after the other, which keeps a
+// group's fields resident in the last-level cache while it is propagated.
+// Problems with fewer steps than the longest in their group leave their
+// blocks at once.  The whole run (tables and passes of every group) is
+// captured once into a hipGraph and replayed by brahms_batch_run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "../../include/brahms.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace brahms;
+using brahms::detail::align_up;
+using brahms::detail::fail;
+using brahms::detail::kChunk;
+
+struct brahms_batch_s {
+  int n = 0;
+  std::vector<brahms_plan> plans;
+  std::vector<int> nsteps;
+  hipStream_t caller = nullptr;
+  hipStream_t stream = nullptr;        // the batch's own stream (graph capture)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  char* ws = nullptr;
+  bool bound = false;
+  std::vector<size_t> plan_off;        // per problem: offset of its plan workspace
+  size_t off_desc = 0, off_targs = 0, ws_size = 0;
+  int group_max = 0;                   // 0: choose from the cache budget
+  // launch groups and descriptor placement (rebuilt when the schedule changes)
+  struct Group {
+    std::vector<int> members;
+    int axis_len[3];
+    int nf, order, max_steps;
+    size_t desc_off;                   // [3 passes][kChunk slots][members] PassArgs
+    size_t targs_off;                  // [chunks][members] TableArgs
+  };
+  std::vector<Group> groups;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+};
+
+namespace {
+
+constexpr size_t kCacheBudget = size_t(160) << 20;  // bytes of field state per group
+
+size_t state_bytes(const brahms_plan_s& p) {
+  return sizeof(float2) * size_t(p.nx) * p.ny * p.nt * p.nf;
+}
+
+void make_groups(brahms_batch_s& b) {
+  b.groups.clear();
+  std::map<std::tuple<int, int, int, int, int>, std::vector<int>> by_key;
+  for (int i = 0; i < b.n; ++i) {
+    const brahms_plan_s& p = *b.plans[i];
+    by_key[{p.nx, p.ny, p.nt, p.nf, p.order}].push_back(i);
+  }
+  for (auto& kv : by_key) {
+    const std::vector<int>& ids = kv.second;
+    const brahms_plan_s& p0 = *b.plans[ids[0]];
+    int gmax = b.group_max;
+    if (gmax <= 0) gmax = int(std::max<size_t>(1, kCacheBudget / state_bytes(p0)));
+    for (size_t s = 0; s < ids.size(); s += size_t(gmax)) {
+      brahms_batch_s::Group g{};
+      g.members.assign(ids.begin() + long(s), ids.begin() + long(std::min(ids.size(), s + size_t(gmax))));
+      g.axis_len[0] = p0.nx;
+      g.axis_len[1] = p0.ny;
+      g.axis_len[2] = p0.nt;
+      g.nf = p0.nf;
+      g.order = p0.order;
+      g.max_steps = 0;
+      for (int m : g.members) g.max_steps = std::max(g.max_steps, b.nsteps[m]);
+      b.groups.push_back(g);
+    }
+  }
+}
+
+size_t descriptor_bytes(brahms_batch_s& b) {
+  size_t off = 0;
+  for (auto& g : b.groups) {
+    g.desc_off = off;
+    off = align_up(off + sizeof(PassArgs) * 3 * kChunk * g.members.size());
+  }
+  return off;
+}
+
+size_t table_arg_bytes(brahms_batch_s& b) {
+  size_t off = 0;
+  for (auto& g : b.groups) {
+    g.targs_off = off;
+    const int chunks = (g.max_steps + kChunk - 1) / kChunk;
+    off = align_up(off + sizeof(TableArgs) * size_t(std::max(chunks, 1)) * g.members.size());
+  }
+  return off;
+}
+
+template <int N1, int N2, int AX, int NF, int NL>
+void launch_batched(bool full, dim3 grid, hipStream_t st, const PassArgs* d, long long step, int nf) {
+  if (full)
+    hipLaunchKernelGGL((axis_pass_batched<N1, N2, AX, NF, NL, true>), grid, dim3(kBlock), 0, st, d, step, nf);
+  else
+    hipLaunchKernelGGL((axis_pass_batched<N1, N2, AX, NF, NL, false>), grid, dim3(kBlock), 0, st, d, step, nf);
+}
+
+template <int N1, int N2, int AX>
+void launch_batched_nl(int nf, int nl, bool full, dim3 grid, hipStream_t st, const PassArgs* d,
+                       long long step) {
+  if (nf == 3) {
+    if (nl == NL_BEFORE) launch_batched<N1, N2, AX, 3, NL_BEFORE>(full, grid, st, d, step, nf);
+    else launch_batched<N1, N2, AX, 3, NL_AFTER>(full, grid, st, d, step, nf);
+  } else {
+    if (nl == NL_BEFORE) launch_batched<N1, N2, AX, 2, NL_BEFORE>(full, grid, st, d, step, nf);
+    else launch_batched<N1, N2, AX, 2, NL_AFTER>(full, grid, st, d, step, nf);
+  }
+}
+
+template <int N1, int N2>
+void launch_group_pass(int axis, int nl, const brahms_batch_s::Group& g, hipStream_t st,
+                       const PassArgs* d, long long step) {
+  using G = LineGeom<N1, N2>;
+  const unsigned m = unsigned(g.members.size());
+  const int nx = g.axis_len[0], ny = g.axis_len[1], nt = g.axis_len[2];
+  if (axis == AX_X) {
+    const long lines = long(ny) * nt;
+    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), m);
+    launch_batched_nl<N1, N2, AX_X>(g.nf, nl, lines % G::LPB == 0, grid, st, d, step);
+  } else if (axis == AX_Y) {
+    const dim3 grid(unsigned((nx + G::LPB - 1) / G::LPB), unsigned(nt), unsigned(g.nf) * m);
+    launch_batched<N1, N2, AX_Y, 1, NL_NONE>(nx % G::LPB == 0, grid, st, d, step, g.nf);
+  } else {
+    const long lines = long(nx) * ny;
+    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), m);
+    launch_batched_nl<N1, N2, AX_T>(g.nf, nl, lines % G::LPB == 0, grid, st, d, step);
+  }
+}
+
+void dispatch_group_pass(int len, int axis, int nl, const brahms_batch_s::Group& g, hipStream_t st,
+                         const PassArgs* d, long long step) {
+  switch (len) {
+    case 1: launch_group_pass<1, 1>(axis, nl, g, st, d, step); break;
+    case 2: launch_group_pass<2, 1>(axis, nl, g, st, d, step); break;
+    case 4: launch_group_pass<4, 1>(axis, nl, g, st, d, step); break;
+    case 8: launch_group_pass<4, 2>(axis, nl, g, st, d, step); break;
+    case 16: launch_group_pass<4, 4>(axis, nl, g, st, d, step); break;
+    case 32: launch_group_pass<8, 4>(axis, nl, g, st, d, step); break;
+    case 64: launch_group_pass<8, 8>(axis, nl, g, st, d, step); break;
+    case 96: launch_group_pass<24, 4>(axis, nl, g, st, d, step); break;
+    case 128: launch_group_pass<16, 8>(axis, nl, g, st, d, step); break;
+    default: launch_group_pass<16, 16>(axis, nl, g, st, d, step); break;
+  }
+}
+
+int lpb_of(int len) {
+  switch (len) {
+    case 1: case 2: case 4: return kBlock;
+    case 8: return kBlock / 2;
+    case 16: case 32: case 96: return kBlock / 4;
+    case 64: case 128: return kBlock / 8;
+    default: return kBlock / 16;
+  }
+}
+
+// Host images of the descriptors (pass arguments per slot and table
+// arguments per chunk) of every group, uploaded once at bind.
+brahms_status upload_descriptors(brahms_batch_s& b) {
+  std::vector<char> desc(b.off_targs - b.off_desc), targ(b.ws_size - b.off_targs);
+  for (auto& g : b.groups) {
+    const size_t m = g.members.size();
+    for (size_t k = 0; k < m; ++k) {
+      brahms_plan_s& p = *b.plans[g.members[k]];
+      const int per_field = p.nx + p.ny + p.nt;
+      const int row_stride = table_row_stride(p.nf, p.nx, p.ny, p.nt);
+      const float2* rows = reinterpret_cast<const float2*>(p.ws + p.off_prop);
+      const float2* nls = reinterpret_cast<const float2*>(p.ws + p.off_nl);
+      for (int pass = 0; pass < 3; ++pass) {
+        const int ax = brahms::detail::pass_axis(p, pass);
+        const int len = ax == AX_X ? p.nx : (ax == AX_Y ? p.ny : p.nt);
+        for (int s = 0; s < kChunk; ++s) {
+          PassArgs a{};
+          const float2* r = rows + size_t(s) * row_stride;
+          a.axis_off = (ax == AX_X) ? 0 : (ax == AX_Y ? p.nx : p.nx + p.ny);
+          a.tw = r + p.nf * per_field + a.axis_off;
+          a.consts = reinterpret_cast<const DftConsts*>(r + (p.nf + 1) * per_field);
+          a.prop = r;
+          a.field_stride = per_field;
+          a.nl = nls + (size_t(s) * 2 + (pass == 0 ? 0 : 1)) * p.nf * kNlCoef;
+          a.nx = p.nx; a.ny = p.ny; a.nt = p.nt;
+          for (int j = 0; j < 3; ++j) {
+            a.f[j] = p.fields[j];
+            a.fo[j] = p.fields[j];
+          }
+          a.tile_mul = 1;
+          a.tiles = 1;
+          if (ax == AX_T) {
+            const long lines = long(p.nx) * p.ny;
+            const int lpb = lpb_of(len);
+            a.tiles = unsigned((lines + lpb - 1) / lpb);
+            a.tile_mul = brahms::detail::tile_multiplier(a.tiles);
+          }
+          a.nz = b.nsteps[g.members[k]];  // compared with the absolute step
+          std::memcpy(desc.data() + g.desc_off + ((size_t(pass) * kChunk + s) * m + k) * sizeof(PassArgs),
+                      &a, sizeof(PassArgs));
+        }
+      }
+      const int chunks = (g.max_steps + kChunk - 1) / kChunk;
+      for (int c = 0; c < chunks; ++c) {
+        TableArgs ta{};
+        ta.rows = reinterpret_cast<float2*>(p.ws + p.off_prop);
+        ta.row_stride = row_stride;
+        ta.nl = reinterpret_cast<float2*>(p.ws + p.off_nl);
+        ta.phi0 = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_phi0);
+        ta.dk = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_dk);
+        ta.n0 = (long long)c * kChunk;
+        ta.count = std::max(0, std::min(kChunk, b.nsteps[g.members[k]] - c * kChunk));
+        ta.nx = p.nx; ta.ny = p.ny; ta.nt = p.nt; ta.nf = p.nf;
+        ta.dz = p.dz; ta.dx = p.dx; ta.dy = p.dy; ta.dt = p.dt; ta.dk_const = p.dk_const;
+        for (int j = 0; j < p.nf; ++j) {
+          const brahms_field_params& f = p.fp[j];
+          ta.fc[j] = FieldCoef{f.kappa, f.diffraction, f.tan_rho, f.delay, f.k2, f.k3, f.alpha};
+        }
+        std::memcpy(targ.data() + g.targs_off + (size_t(c) * m + k) * sizeof(TableArgs), &ta,
+                    sizeof(TableArgs));
+      }
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(b.ws + b.off_desc, desc.data(), desc.size(), hipMemcpyHostToDevice, b.stream));
+  HIP_TRY(hipMemcpyAsync(b.ws + b.off_targs, targ.data(), targ.size(), hipMemcpyHostToDevice, b.stream));
+  HIP_TRY(hipStreamSynchronize(b.stream));
+  return BRAHMS_OK;
+}
+
+// The whole run on b.stream: per group, per 64-step chunk, one batched table
+// launch and then three batched pass launches per step.
+brahms_status enqueue_run(brahms_batch_s& b) {
+  for (auto& g : b.groups) {
+    const brahms_plan_s& p0 = *b.plans[g.members[0]];
+    const int per_field = p0.nx + p0.ny + p0.nt;
+    const unsigned m = unsigned(g.members.size());
+    const int chunks = (g.max_steps + kChunk - 1) / kChunk;
+    for (int c = 0; c < chunks; ++c) {
+      const long total = long(kChunk) * ((g.nf + 1) * per_field + 1) + long(kChunk) * 2 * g.nf;
+      const TableArgs* targs =
+          reinterpret_cast<const TableArgs*>(b.ws + b.off_targs + g.targs_off) + size_t(c) * m;
+      hipLaunchKernelGGL(step_tables_batched, dim3(unsigned((total + 255) / 256), m), dim3(256), 0,
+                         b.stream, targs);
+      HIP_TRY(hipGetLastError());
+      const int cnt = std::min(kChunk, g.max_steps - c * kChunk);
+      for (int s = 0; s < cnt; ++s) {
+        const long long step = (long long)c * kChunk + s;
+        for (int pass = 0; pass < 3; ++pass) {
+          const int ax = brahms::detail::pass_axis(p0, pass);
+          const int nl = pass == 0 ? NL_BEFORE : (pass == 2 ? NL_AFTER : NL_NONE);
+          const PassArgs* d = reinterpret_cast<const PassArgs*>(b.ws + b.off_desc + g.desc_off) +
+                              (size_t(pass) * kChunk + s) * m;
+          dispatch_group_pass(g.axis_len[ax], ax, nl, g, b.stream, d, step);
+          HIP_TRY(hipGetLastError());
+        }
+      }
+    }
+  }
+  return BRAHMS_OK;
+}
+
+void drop_graph(brahms_batch_s& b) {
+  if (b.exec) (void)hipGraphExecDestroy(b.exec);
+  if (b.graph) (void)hipGraphDestroy(b.graph);
+  b.exec = nullptr;
+  b.graph = nullptr;
+}
+
+brahms_status check_batch(brahms_batch b) {
+  if (b == nullptr) return fail(BRAHMS_E_INVALID_ARG, "batch is NULL");
+  return BRAHMS_OK;
+}
+
+void layout_batch(brahms_batch_s& b) {
+  size_t off = 0;
+  b.plan_off.resize(b.n);
+  for (int i = 0; i < b.n; ++i) {
+    b.plan_off[i] = off;
+    off = align_up(off + b.plans[i]->ws_size);
+  }
+  make_groups(b);
+  b.off_desc = off;
+  off += descriptor_bytes(b);
+  b.off_targs = off;
+  off += table_arg_bytes(b);
+  b.ws_size = align_up(off);
+}
+
+}  // namespace
+
+extern "C" {
+
+brahms_status brahms_batch_create(int n, const int* shapes, const brahms_params* params,
+                                  const int* nsteps, void* hip_stream, brahms_batch* out) {
+  if (out == nullptr) return fail(BRAHMS_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || shapes == nullptr || params == nullptr || nsteps == nullptr)
+    return fail(BRAHMS_E_INVALID_ARG, "need n >= 1 and non-NULL shapes, params, nsteps");
+  auto* b = new brahms_batch_s();
+  b->n = n;
+  b->caller = reinterpret_cast<hipStream_t>(hip_stream);
+  for (int i = 0; i < n; ++i) {
+    brahms_plan p = nullptr;
+    if (nsteps[i] < 0) {
+      brahms_batch_destroy(b);
+      return fail(BRAHMS_E_INVALID_ARG, "negative step count");
+    }
+    if (brahms_status st = brahms_plan_create(shapes[4 * i], shapes[4 * i + 1], shapes[4 * i + 2],
+                                              shapes[4 * i + 3], &params[i], nullptr, &p)) {
+      brahms_batch_destroy(b);
+      return st;
+    }
+    if (!p->dk.empty() && nsteps[i] > (int)p->dk.size()) {
+      brahms_plan_destroy(p);
+      brahms_batch_destroy(b);
+      return fail(BRAHMS_E_INVALID_ARG, "steps beyond the end of a dk profile");
+    }
+    b->plans.push_back(p);
+    b->nsteps.push_back(nsteps[i]);
+  }
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+    brahms_batch_destroy(b);
+    return fail(BRAHMS_E_DEVICE, "could not create the batch stream or events");
+  }
+  for (brahms_plan p : b->plans) p->stream = b->stream;
+  layout_batch(*b);
+  *out = b;
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_batch_set_schedule(brahms_batch b, int group_max, const int* pass_order) {
+  if (brahms_status st = check_batch(b)) return st;
+  if (group_max < 0) return fail(BRAHMS_E_INVALID_ARG, "group_max < 0");
+  if (pass_order != nullptr)
+    for (int i = 0; i < b->n; ++i)
+      if (pass_order[i] != 0 && pass_order[i] != 1)
+        return fail(BRAHMS_E_INVALID_ARG, "pass_order entries must be 0 or 1");
+  b->group_max = group_max;
+  if (pass_order != nullptr)
+    for (int i = 0; i < b->n; ++i) b->plans[i]->order = pass_order[i];
+  drop_graph(*b);
+  b->bound = false;
+  layout_batch(*b);
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_batch_workspace_size(brahms_batch b, size_t* bytes) {
+  if (brahms_status st = check_batch(b)) return st;
+  if (bytes == nullptr) return fail(BRAHMS_E_INVALID_ARG, "bytes is NULL");
+  *bytes = b->ws_size;
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_batch_bind(brahms_batch b, void* const* fields, void* workspace) {
+  if (brahms_status st = check_batch(b)) return st;
+  if (fields == nullptr || workspace == nullptr ||
+      reinterpret_cast<uintptr_t>(workspace) % detail::kAlign != 0)
+    return fail(BRAHMS_E_INVALID_ARG, "fields NULL or workspace not 256-byte aligned");
+  drop_graph(*b);
+  b->bound = false;
+  b->ws = static_cast<char*>(workspace);
+  size_t f = 0;
+  for (int i = 0; i < b->n; ++i) {
+    brahms_plan p = b->plans[i];
+    if (brahms_status st = brahms_plan_bind(p, fields + f, b->ws + b->plan_off[i])) return st;
+    f += size_t(p->nf);
+  }
+  if (brahms_status st = upload_descriptors(*b)) return st;
+  b->bound = true;
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_batch_run(brahms_batch b) {
+  if (brahms_status st = check_batch(b)) return st;
+  if (!b->bound) return fail(BRAHMS_E_STATE, "brahms_batch_run before brahms_batch_bind");
+  HIP_TRY(hipEventRecord(b->ev_in, b->caller));
+  HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_in, 0));
+  if (b->exec == nullptr) {
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    const brahms_status st = enqueue_run(*b);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->stream, &graph);
+    if (st != BRAHMS_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    HIP_TRY(e);
+    b->graph = graph;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+  HIP_TRY(hipEventRecord(b->ev_out, b->stream));
+  HIP_TRY(hipStreamWaitEvent(b->caller, b->ev_out, 0));
+  for (int i = 0; i < b->n; ++i) b->plans[i]->step = b->nsteps[i];
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_batch_groups(brahms_batch b, int* ngroups, int* members) {
+  if (brahms_status st = check_batch(b)) return st;
+  if (ngroups == nullptr) return fail(BRAHMS_E_INVALID_ARG, "ngroups is NULL");
+  *ngroups = int(b->groups.size());
+  if (members != nullptr)
+    for (size_t g = 0; g < b->groups.size(); ++g) members[g] = int(b->groups[g].members.size());
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_batch_destroy(brahms_batch b) {
+  if (b == nullptr) return fail(BRAHMS_E_INVALID_ARG, "batch is NULL");
+  drop_graph(*b);
+  for (brahms_plan p : b->plans) brahms_plan_destroy(p);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+  return BRAHMS_OK;
+}
+
+}  // extern "C"

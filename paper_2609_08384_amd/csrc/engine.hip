@@ -89,6 +89,7 @@ template <int N1, int N2>
 hipError_t launch_axis(int axis, int nl, int nf, const brahms_plan_s& p, PassArgs a) {
   using G = LineGeom<N1, N2>;
   a.tile_mul = 1;
+  a.tiles = 1;
   if (axis == AX_X) {
     const long lines = long(p.ny) * p.nt;
     const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
@@ -100,6 +101,7 @@ hipError_t launch_axis(int axis, int nl, int nf, const brahms_plan_s& p, PassArg
     const long lines = long(p.nx) * p.ny;
     const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
     a.tile_mul = tile_multiplier(grid.x);
+    a.tiles = grid.x;
     launch_nl<N1, N2, AX_T>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
   }
   return hipGetLastError();

@@ -43,6 +43,8 @@ struct PassArgs {
   int nx, ny, nt;
   int axis_off, field_stride;
   unsigned tile_mul;     // block -> tile map: tile = (block * tile_mul) mod tiles
+  unsigned tiles;        // number of tiles (blocks along x of the launch)
+  long long nz;          // batched launches: the instance is done once step >= nz
 };
 
 // ---------------------------------------------------------------------------
@@ -193,8 +195,11 @@ __device__ inline void store_field(float2* base, unsigned idx, float2 v) {
 // NF is the number of fields held by one thread (Y: 1, one field per block).
 // FULL: every line of every block exists (no bounds masks).
 // ---------------------------------------------------------------------------
+// bx: tile index along the launch's x dimension; by: tau slice (y pass);
+// field0: first field handled (y pass: the block's field).
 template <int N1, int N2, int AX, int NF, int NL, bool FULL>
-__global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass(PassArgs args) {
+__device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx, unsigned by,
+                                               int field0) {
   using G = LineGeom<N1, N2>;
   constexpr int N = G::N;
   constexpr bool NT = (AX == AX_X) ? bool(BRAHMS_NT_X) : bool(BRAHMS_NT_YT);
@@ -203,7 +208,6 @@ __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass(PassArgs 
   __shared__ float2 s_prop[NF * N];
 
   const int tid = threadIdx.x;
-  const int field0 = (AX == AX_Y) ? int(blockIdx.z) : 0;
   // this step's twiddles and this block's propagators, staged once
   for (int i = tid; i < N; i += kBlock) s_tw[i] = args.tw[i];
   for (int i = tid; i < NF * N; i += kBlock) {
@@ -220,16 +224,16 @@ __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass(PassArgs 
   if constexpr (AX == AX_X) {
     t = tid % N2;
     li = tid / N2;
-    const unsigned line = blockIdx.x * unsigned(G::LPB) + li;
+    const unsigned line = bx * unsigned(G::LPB) + li;
     if constexpr (!FULL) valid = line < unsigned(args.ny) * unsigned(args.nt);
     base = line * unsigned(args.nx);
     estride = 1;
   } else if constexpr (AX == AX_Y) {
     li = tid % G::LPB;
     t = tid / G::LPB;
-    const unsigned col = blockIdx.x * unsigned(G::LPB) + li;
+    const unsigned col = bx * unsigned(G::LPB) + li;
     if constexpr (!FULL) valid = col < unsigned(args.nx);
-    base = col + unsigned(args.nx) * unsigned(args.ny) * blockIdx.y;
+    base = col + unsigned(args.nx) * unsigned(args.ny) * by;
     estride = args.nx;
   } else {
     li = tid % G::LPB;
@@ -237,7 +241,7 @@ __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass(PassArgs 
     // tiles of consecutive (x, y) columns; concurrently running blocks are
     // spread over the whole plane so that their strided rows fall into many
     // memory channels rather than one narrow address window
-    const unsigned tile = unsigned((unsigned long long)blockIdx.x * args.tile_mul % gridDim.x);
+    const unsigned tile = unsigned((unsigned long long)bx * args.tile_mul % args.tiles);
     const unsigned q = tile * unsigned(G::LPB) + li;
     if constexpr (!FULL) valid = q < unsigned(args.nx) * unsigned(args.ny);
     base = q;
@@ -321,6 +325,27 @@ __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass(PassArgs 
         for (int e = 0; e < N1; ++e) store_field<NT>(fout[j], idx0 + unsigned(e) * estep, v[j][e]);
     }
   }
+}
+
+// One pass of one problem.
+template <int N1, int N2, int AX, int NF, int NL, bool FULL>
+__global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass(PassArgs args) {
+  axis_pass_body<N1, N2, AX, NF, NL, FULL>(args, blockIdx.x, blockIdx.y,
+                                           AX == AX_Y ? int(blockIdx.z) : 0);
+}
+
+// One pass over a group of problems of the same shape (a batch): descs[i]
+// describes problem i at this step; x/tau passes take the problem from
+// blockIdx.y, the y pass from blockIdx.z / nf.  Problems whose own step count
+// is reached (step >= nz) leave at once.
+template <int N1, int N2, int AX, int NF, int NL, bool FULL>
+__global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass_batched(
+    const PassArgs* descs, long long step, int nf) {
+  const unsigned inst = AX == AX_Y ? blockIdx.z / unsigned(nf) : blockIdx.y;
+  const PassArgs& a = descs[inst];
+  if (step >= a.nz) return;
+  axis_pass_body<N1, N2, AX, NF, NL, FULL>(a, blockIdx.x, blockIdx.y,
+                                           AX == AX_Y ? int(blockIdx.z % unsigned(nf)) : 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -415,10 +440,9 @@ __device__ inline float stochastic_round(double v, unsigned bits) {
   return (u < p) ? hi : lo;
 }
 
-static __global__ void step_tables(TableArgs a) {
+__device__ __forceinline__ void step_tables_body(const TableArgs& a, long gid) {
   const int per_field = a.nx + a.ny + a.nt;
   const int per_step = (a.nf + 1) * per_field + 1;  // + one thread for DftConsts
-  const long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
   const long nrow = long(a.count) * per_step;
   if (gid < nrow) {
     const int s = int(gid / per_step);
@@ -513,6 +537,15 @@ static __global__ void step_tables(TableArgs a) {
     out[k] = make_float2(stochastic_round(w[k] * c[which[k]].x, entry_bits(n, slot)),
                          stochastic_round(w[k] * c[which[k]].y, entry_bits(n, slot + 1)));
   }
+}
+
+static __global__ void step_tables(TableArgs a) {
+  step_tables_body(a, long(blockIdx.x) * blockDim.x + threadIdx.x);
+}
+
+// Tables of several problems: problem blockIdx.y uses targs[blockIdx.y].
+static __global__ void step_tables_batched(const TableArgs* targs) {
+  step_tables_body(targs[blockIdx.y], long(blockIdx.x) * blockDim.x + threadIdx.x);
 }
 
 // Set a flag when any field value is not finite (the step-size hazard of
