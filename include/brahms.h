@@ -171,7 +171,8 @@ brahms_status brahms_timing_read(brahms_plan plan, double* ms, long long* launch
  *   receives dJ/ddk: n_dk entries (entries past the window are zero) when a
  *   per-step profile was given at create, else one entry dJ/d(dk_const).
  *   The z counter is left at z_end.  Synchronises the plan's stream when
- *   grad_dk is not NULL.
+ *   grad_dk is not NULL.  brahms_step, brahms_set_z or brahms_plan_bind
+ *   between the two calls discard the forward record (BRAHMS_E_STATE).
  * Errors: BRAHMS_E_STATE (not bound / no forward record), BRAHMS_E_INVALID_ARG
  * (sizes, pointers, steps beyond the dk profile), BRAHMS_E_DEVICE. */
 brahms_status brahms_adjoint_workspace_size(brahms_plan plan, int nsteps, int checkpoint_every,

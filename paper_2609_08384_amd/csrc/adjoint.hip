@@ -78,7 +78,7 @@ AdjLayout adj_layout(const brahms_plan_s& p, int nsteps, int every) {
   L.pre = off;
   off += state * every;
   L.parts = off;
-  off = align_up(off + sizeof(double) * 3 * L.max_blocks);
+  off = align_up(off + sizeof(double) * 3 * L.max_blocks * 2 * every);
   L.dphi = off;
   off = align_up(off + sizeof(double) * 6 * nsteps);
   L.total = off;
@@ -150,10 +150,10 @@ brahms_status copy_state(const brahms_plan_s& p, float2* const* dst, float2* con
   return BRAHMS_OK;
 }
 
-// One adjoint pass with an RK4 reverse sweep, then the fixed-order reduction
-// of its phase derivatives into dphi_acc[0..2].
+// One adjoint pass with an RK4 reverse sweep; its per-block phase
+// derivatives go to slot (row, k == 0 ? 0 : 1) of the segment's partials.
 brahms_status adj_pass(brahms_plan_s& p, const AdjLayout& L, int row, int k, float2* const* g,
-                       float2* const* y, double* dphi_acc) {
+                       float2* const* y) {
   const int ax = brahms::detail::pass_axis(p, k);
   const int per_field = p.nx + p.ny + p.nt;
   const float2* r = brahms::detail::table_row(p, row);
@@ -170,7 +170,7 @@ brahms_status adj_pass(brahms_plan_s& p, const AdjLayout& L, int row, int k, flo
   a.nl = brahms::detail::nl_coefficients(p, row, k == 0 ? 0 : 1);
   a.nx = p.nx; a.ny = p.ny; a.nt = p.nt;
   double* parts = reinterpret_cast<double*>(p.adj_ws + L.parts);
-  a.dphi_out = parts;
+  a.dphi_out = parts + (size_t(row) * 2 + (k == 0 ? 0 : 1)) * size_t(L.max_blocks) * 3;
   // exp(-i Phi) on the sum-frequency field, exp(+i Phi) on the others
   if (p.nf == 3) {
     a.sigma[0] = -1.f; a.sigma[1] = 1.f; a.sigma[2] = 1.f;
@@ -178,8 +178,23 @@ brahms_status adj_pass(brahms_plan_s& p, const AdjLayout& L, int row, int k, flo
     a.sigma[0] = 1.f; a.sigma[1] = -1.f; a.sigma[2] = 0.f;
   }
   HIP_TRY(dispatch_adj(ax, k == 0 ? VJP_LAST : VJP_FIRST, p, a));
-  hipLaunchKernelGGL(reduce_dphi, dim3(1), dim3(256), 0, p.stream, parts, pass_blocks(ax, p), dphi_acc);
-  HIP_TRY(hipGetLastError());
+  return BRAHMS_OK;
+}
+
+// Run steps s0 .. s0+cnt-1 (table rows 0..cnt-1) out of place through the
+// segment slots, keeping every step's input (slot i) and the input of its
+// second RK4 half-step; the last step writes `last_out` when given.
+brahms_status record_segment(brahms_plan_s& p, const AdjLayout& L, int cnt, float2* const* last_out) {
+  for (int i = 0; i < cnt; ++i) {
+    brahms::detail::StepIO io{};
+    for (int j = 0; j < p.nf; ++j) {
+      io.in[j] = state_field(p.adj_ws + L.seg, L, p, i, j);
+      io.out[j] = (i == cnt - 1 && last_out != nullptr) ? last_out[j]
+                                                        : state_field(p.adj_ws + L.seg, L, p, i + 1, j);
+      io.pre[j] = state_field(p.adj_ws + L.pre, L, p, i, j);
+    }
+    if (brahms_status st = brahms::detail::launch_step(p, i, io)) return st;
+  }
   return BRAHMS_OK;
 }
 
@@ -215,13 +230,22 @@ brahms_status brahms_adjoint_forward(brahms_plan plan, int nsteps, int checkpoin
   p.adj_nsteps = nsteps;
   p.adj_every = checkpoint_every;
   float2* fields[3] = {p.fields[0], p.fields[1], p.fields[2]};
-  for (int c = 0; c < L.nckpt; ++c) {
+  for (int c = 0; c < L.nckpt - 1; ++c) {
     float2* ck[3] = {nullptr, nullptr, nullptr};
     for (int j = 0; j < p.nf; ++j) ck[j] = state_field(p.adj_ws + L.ckpt, L, p, c, j);
     if (brahms_status st = copy_state(p, ck, fields)) return st;
-    const int cnt = std::min(checkpoint_every, nsteps - c * checkpoint_every);
-    if (brahms_status st = brahms_step(plan, cnt)) return st;
+    if (brahms_status st = brahms_step(plan, checkpoint_every)) return st;
   }
+  // the last segment is recorded as the backward sweep needs it, so that
+  // sweep starts without recomputing it
+  const int cnt = nsteps - (L.nckpt - 1) * checkpoint_every;
+  float2* slot0[3] = {nullptr, nullptr, nullptr};
+  for (int j = 0; j < p.nf; ++j) slot0[j] = state_field(p.adj_ws + L.seg, L, p, 0, j);
+  if (brahms_status st = copy_state(p, slot0, fields)) return st;
+  if (brahms_status st = brahms::detail::refresh_tables(p, p.step, cnt)) return st;
+  if (brahms_status st = record_segment(p, L, cnt, fields)) return st;
+  p.step += cnt;
+  p.adj_last_recorded = true;
   p.adj_ready = true;
   return BRAHMS_OK;
 }
@@ -244,23 +268,17 @@ brahms_status brahms_adjoint_backward(brahms_plan plan, void* const* grad, doubl
   for (int c = L.nckpt - 1; c >= 0; --c) {
     const long long s0 = p.adj_n0 + (long long)c * p.adj_every;
     const int cnt = int(std::min<long long>(p.adj_every, p.adj_n0 + p.adj_nsteps - s0));
-    if (brahms_status st = brahms::detail::refresh_tables(p, s0, cnt)) return st;
-    // recompute the segment out of place, keeping inputs and pre-RK4 states
-    float2* slot0[3] = {nullptr, nullptr, nullptr};
-    float2* ck[3] = {nullptr, nullptr, nullptr};
-    for (int j = 0; j < p.nf; ++j) {
-      slot0[j] = state_field(p.adj_ws + L.seg, L, p, 0, j);
-      ck[j] = state_field(p.adj_ws + L.ckpt, L, p, c, j);
-    }
-    if (brahms_status st = copy_state(p, slot0, ck)) return st;
-    for (int i = 0; i < cnt; ++i) {
-      brahms::detail::StepIO io{};
+    if (c != L.nckpt - 1 || !p.adj_last_recorded) {
+      // recompute the segment out of place, keeping inputs and pre-RK4 states
+      if (brahms_status st = brahms::detail::refresh_tables(p, s0, cnt)) return st;
+      float2* slot0[3] = {nullptr, nullptr, nullptr};
+      float2* ck[3] = {nullptr, nullptr, nullptr};
       for (int j = 0; j < p.nf; ++j) {
-        io.in[j] = state_field(p.adj_ws + L.seg, L, p, i, j);
-        io.out[j] = state_field(p.adj_ws + L.seg, L, p, i + 1, j);
-        io.pre[j] = state_field(p.adj_ws + L.pre, L, p, i, j);
+        slot0[j] = state_field(p.adj_ws + L.seg, L, p, 0, j);
+        ck[j] = state_field(p.adj_ws + L.ckpt, L, p, c, j);
       }
-      if (brahms_status st = brahms::detail::launch_step(p, i, io)) return st;
+      if (brahms_status st = copy_state(p, slot0, ck)) return st;
+      if (brahms_status st = record_segment(p, L, cnt, nullptr)) return st;
     }
     // reverse sweep over the segment
     for (int i = cnt - 1; i >= 0; --i) {
@@ -271,11 +289,20 @@ brahms_status brahms_adjoint_backward(brahms_plan plan, void* const* grad, doubl
         y2[j] = state_field(p.adj_ws + L.pre, L, p, i, j);
         y0[j] = state_field(p.adj_ws + L.seg, L, p, i, j);
       }
-      if (brahms_status st = adj_pass(p, L, i, 2, g, y2, dphi + 6 * r + 3)) return st;
+      if (brahms_status st = adj_pass(p, L, i, 2, g, y2)) return st;
       if (brahms_status st = brahms::detail::launch_linear_pass(p, i, AX_Y, g, true)) return st;
-      if (brahms_status st = adj_pass(p, L, i, 0, g, y0, dphi + 6 * r)) return st;
+      if (brahms_status st = adj_pass(p, L, i, 0, g, y0)) return st;
+      (void)r;
     }
+    // dJ/dPhi of the segment's steps, in a fixed order
+    const int nb_first = pass_blocks(brahms::detail::pass_axis(p, 0), p);
+    const int nb_last = pass_blocks(brahms::detail::pass_axis(p, 2), p);
+    hipLaunchKernelGGL(reduce_dphi_segment, dim3(unsigned(cnt), 2), dim3(256), 0, p.stream,
+                       reinterpret_cast<const double*>(p.adj_ws + L.parts), nb_first, nb_last,
+                       L.max_blocks, dphi + 6 * (s0 - p.adj_n0));
+    HIP_TRY(hipGetLastError());
   }
+  p.adj_last_recorded = false;
   p.step = saved_step;
   if (grad_dk != nullptr) {
     std::vector<double> G(size_t(6) * p.adj_nsteps);

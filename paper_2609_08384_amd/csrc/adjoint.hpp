@@ -200,6 +200,13 @@ __global__ __launch_bounds__(kBlock) void adjoint_pass(AdjArgs args) {
         yy[j] = valid ? args.y[j][idx0 + unsigned(e) * estep] : make_float2(0.f, 0.f);
         gg[j] = v[j][e];
       }
+      // One point at a time: tie this point's inputs to the phase sums of the
+      // previous points (an empty asm, no instructions), so the compiler
+      // cannot interleave all points and run out of registers.
+#pragma unroll
+      for (int j = 0; j < NF; ++j)
+        asm volatile("" : "+v"(yy[j].x), "+v"(yy[j].y), "+v"(gg[j].x), "+v"(gg[j].y), "+v"(dphi[0]),
+                          "+v"(dphi[1]), "+v"(dphi[2]));
       rk4_vjp_point<NF>(yy, gg, co, sigma, dphi);
 #pragma unroll
       for (int j = 0; j < NF; ++j) v[j][e] = gg[j];
@@ -236,20 +243,27 @@ __global__ __launch_bounds__(kBlock) void adjoint_pass(AdjArgs args) {
   }
 }
 
-// Sum the per-block phase derivatives of one launch (fixed order):
-// out[k] += sum_b parts[b * 3 + k], k < 3.
-static __global__ void reduce_dphi(const double* parts, int nblocks, double* out) {
+// Sum the per-block phase derivatives of a segment's adjoint passes (fixed
+// order).  Block (i, w) handles step i of the segment and pass w (0: the
+// reverse first half-step, 1: the reverse second half-step), whose launch had
+// nblocks[w] blocks and wrote parts[((i * 2 + w) * stride + b) * 3 + k];
+// out[6 i + 3 w + k] receives the sum over b (block size 256).
+static __global__ void reduce_dphi_segment(const double* parts, int nblocks0, int nblocks1,
+                                           int stride, double* out) {
   __shared__ double s[256];
+  const int i = blockIdx.x, w = blockIdx.y;
+  const int nb = w == 0 ? nblocks0 : nblocks1;
+  const double* src = parts + (size_t(i) * 2 + w) * size_t(stride) * 3;
   for (int k = 0; k < 3; ++k) {
     double acc = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) acc += parts[b * 3 + k];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += src[b * 3 + k];
     s[threadIdx.x] = acc;
     __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+      if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
       __syncthreads();
     }
-    if (threadIdx.x == 0) out[k] += s[0];
+    if (threadIdx.x == 0) out[6 * i + 3 * w + k] = s[0];
     __syncthreads();
   }
 }

@@ -10,7 +10,10 @@
 // group's fields resident in the last-level cache while it is propagated.
 // Problems with fewer steps than the longest in their group leave their
 // blocks at once.  The whole run (tables and passes of every group) is
-// captured once into a hipGraph and replayed by brahms_batch_run.
+// captured once into a hipGraph and replayed by brahms_batch_run; launch
+// groups are independent branches of that graph (up to four side streams),
+// so a bandwidth-bound group of large grids and latency-bound groups of
+// small grids can execute at the same time.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,6 +55,11 @@ struct brahms_batch_s {
   std::vector<Group> groups;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
+  // side streams and events of the capture: launch groups are independent,
+  // so they become parallel branches of the graph
+  static constexpr int kBranches = 4;
+  hipStream_t side[kBranches] = {};
+  hipEvent_t fork = nullptr, join[kBranches] = {};
 };
 
 namespace {
@@ -243,10 +251,10 @@ brahms_status upload_descriptors(brahms_batch_s& b) {
   return BRAHMS_OK;
 }
 
-// The whole run on b.stream: per group, per 64-step chunk, one batched table
-// launch and then three batched pass launches per step.
-brahms_status enqueue_run(brahms_batch_s& b) {
-  for (auto& g : b.groups) {
+// One launch group on stream st: per 64-step chunk, one batched table launch
+// and then three batched pass launches per step.
+brahms_status enqueue_group(brahms_batch_s& b, const brahms_batch_s::Group& g, hipStream_t st) {
+  {
     const brahms_plan_s& p0 = *b.plans[g.members[0]];
     const int per_field = p0.nx + p0.ny + p0.nt;
     const unsigned m = unsigned(g.members.size());
@@ -256,7 +264,7 @@ brahms_status enqueue_run(brahms_batch_s& b) {
       const TableArgs* targs =
           reinterpret_cast<const TableArgs*>(b.ws + b.off_targs + g.targs_off) + size_t(c) * m;
       hipLaunchKernelGGL(step_tables_batched, dim3(unsigned((total + 255) / 256), m), dim3(256), 0,
-                         b.stream, targs);
+                         st, targs);
       HIP_TRY(hipGetLastError());
       const int cnt = std::min(kChunk, g.max_steps - c * kChunk);
       for (int s = 0; s < cnt; ++s) {
@@ -266,11 +274,33 @@ brahms_status enqueue_run(brahms_batch_s& b) {
           const int nl = pass == 0 ? NL_BEFORE : (pass == 2 ? NL_AFTER : NL_NONE);
           const PassArgs* d = reinterpret_cast<const PassArgs*>(b.ws + b.off_desc + g.desc_off) +
                               (size_t(pass) * kChunk + s) * m;
-          dispatch_group_pass(g.axis_len[ax], ax, nl, g, b.stream, d, step);
+          dispatch_group_pass(g.axis_len[ax], ax, nl, g, st, d, step);
           HIP_TRY(hipGetLastError());
         }
       }
     }
+  }
+  return BRAHMS_OK;
+}
+
+// The whole run: forks from b.stream into the side streams (launch groups
+// dealt round-robin, largest first), and joins back.
+brahms_status enqueue_run(brahms_batch_s& b) {
+  std::vector<size_t> order(b.groups.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+  auto work = [&](size_t k) {
+    const auto& g = b.groups[k];
+    return double(g.axis_len[0]) * g.axis_len[1] * g.axis_len[2] * g.members.size() * g.max_steps;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) { return work(a) > work(c); });
+  const int nb = std::min<int>(brahms_batch_s::kBranches, int(order.size()));
+  HIP_TRY(hipEventRecord(b.fork, b.stream));
+  for (int k = 0; k < nb; ++k) HIP_TRY(hipStreamWaitEvent(b.side[k], b.fork, 0));
+  for (size_t k = 0; k < order.size(); ++k)
+    if (brahms_status st = enqueue_group(b, b.groups[order[k]], b.side[k % nb])) return st;
+  for (int k = 0; k < nb; ++k) {
+    HIP_TRY(hipEventRecord(b.join[k], b.side[k]));
+    HIP_TRY(hipStreamWaitEvent(b.stream, b.join[k], 0));
   }
   return BRAHMS_OK;
 }
@@ -334,11 +364,16 @@ brahms_status brahms_batch_create(int n, const int* shapes, const brahms_params*
     b->plans.push_back(p);
     b->nsteps.push_back(nsteps[i]);
   }
-  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+  bool ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+  for (int k = 0; ok && k < brahms_batch_s::kBranches; ++k)
+    ok = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
     brahms_batch_destroy(b);
-    return fail(BRAHMS_E_DEVICE, "could not create the batch stream or events");
+    return fail(BRAHMS_E_DEVICE, "could not create the batch streams or events");
   }
   for (brahms_plan p : b->plans) p->stream = b->stream;
   layout_batch(*b);
@@ -428,6 +463,11 @@ brahms_status brahms_batch_destroy(brahms_batch b) {
   for (brahms_plan p : b->plans) brahms_plan_destroy(p);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (int k = 0; k < brahms_batch_s::kBranches; ++k) {
+    if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+    if (b->side[k]) (void)hipStreamDestroy(b->side[k]);
+  }
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return BRAHMS_OK;

@@ -377,6 +377,7 @@ brahms_status brahms_plan_bind(brahms_plan plan, void* const* fields, void* work
       return fail(BRAHMS_E_INVALID_ARG, "field pointer must be 8-byte aligned");
   }
   plan->bound = false;
+  plan->adj_ready = false;
   for (int j = 0; j < 3; ++j) plan->fields[j] = j < plan->nf ? static_cast<float2*>(fields[j]) : nullptr;
   plan->ws = static_cast<char*>(workspace);
   if (!plan->dk.empty()) {
@@ -395,6 +396,7 @@ brahms_status brahms_step(brahms_plan plan, int nsteps) {
   if (!plan->bound) return fail(BRAHMS_E_STATE, "brahms_step before brahms_plan_bind");
   if (nsteps < 0) return fail(BRAHMS_E_INVALID_ARG, "nsteps < 0");
   if (nsteps == 0) return BRAHMS_OK;
+  plan->adj_ready = false;  // a recorded adjoint forward no longer matches
   if (!plan->dk.empty() && plan->step + nsteps > (long long)plan->dk.size())
     return fail(BRAHMS_E_INVALID_ARG, "steps beyond the end of the dk profile");
   if (brahms_status st = run_steps(*plan, nsteps)) return st;
@@ -447,6 +449,7 @@ brahms_status brahms_set_z(brahms_plan plan, double z) {
   if (!std::isfinite(z) || z < 0.0 || !steps_to(0.0, z, plan->dz, &n))
     return fail(BRAHMS_E_INVALID_ARG, "z must be a non-negative multiple of dz");
   plan->step = n;
+  plan->adj_ready = false;
   return BRAHMS_OK;
 }
 

@@ -165,6 +165,16 @@ __device__ inline void line_fft(float2 (&v)[N1], int t, float2* lbuf, const floa
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
+// Tie a point's RK4 inputs to the previous point's results with an empty asm
+// (no instructions): the points of a thread are then updated one after the
+// other instead of all interleaved, which would run out of registers.
+template <int NF, int N1>
+__device__ __forceinline__ void point_link(float2* y, float2 (&v)[NF][N1], int prev) {
+#pragma unroll
+  for (int j = 0; j < NF; ++j)
+    asm volatile("" : "+v"(y[j].x), "+v"(y[j].y), "+v"(v[j][prev].x), "+v"(v[j][prev].y));
+}
+
 template <bool NT>
 __device__ inline float2 load_field(const float2* base, unsigned idx) {
   if constexpr (NT) {
@@ -277,6 +287,7 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
       float2 y[NF];
 #pragma unroll
       for (int j = 0; j < NF; ++j) y[j] = v[j][e];
+      if (e > 0) point_link<NF>(y, v, e - 1);
       rk4_point<NF>(y, co);
 #pragma unroll
       for (int j = 0; j < NF; ++j) v[j][e] = y[j];
@@ -314,6 +325,9 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
       float2 y[NF];
 #pragma unroll
       for (int j = 0; j < NF; ++j) y[j] = v[j][e];
+      // (after the transforms a schedule barrier between points keeps
+      // fewer registers live than the link above)
+      __builtin_amdgcn_sched_barrier(0);
       rk4_point<NF>(y, co);
 #pragma unroll
       for (int j = 0; j < NF; ++j) v[j][e] = y[j];

@@ -33,6 +33,7 @@ struct brahms_plan_s {
   bool adj_ready = false;
   long long adj_n0 = 0;
   int adj_nsteps = 0, adj_every = 0;
+  bool adj_last_recorded = false;   // segment slots hold the last segment
   char* adj_ws = nullptr;
 };
 
