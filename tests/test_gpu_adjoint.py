@@ -92,3 +92,26 @@ def test_adjoint_forward_equals_plain_step():
     for x, y in zip(a, b):
         assert torch.equal(x, y)
     assert abs(p2.z - p1.z) < 1e-15
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_inverse_design_workload_vs_oracle(order):
+    """SHG 128x128x64, 400 steps, per-step dk = 2/L + N(0, 0.1/L), checkpoints
+    every 20 steps, J = -sum |S(L)|^2: the loss, dJ/ddk (all 400 entries) and
+    sampled dJ/dF_in against the oracle's adjoint (tests/golden)."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "shg_adjoint_grad.npz"))
+    wl = inputs.shg_adjoint()
+    params = brahms.params_from_workload(wl)
+    x = [torch.from_numpy(a).to(DEV).requires_grad_(True) for a in wl.init]
+    dk = torch.tensor(wl.dk, dtype=torch.float64, requires_grad=True)
+    out = autograd.ssfm(x, params, wl.nz, dk=dk, checkpoint_every=20, pass_order=order)
+    loss = -(out[1].to(torch.complex128).abs() ** 2).sum()
+    loss.backward()
+    assert abs(float(loss) - float(g["J"])) < 2e-5 * abs(float(g["J"]))
+    assert rel_l2(dk.grad.numpy(), g["grad_dk"]) < 1e-4
+    gf = x[0].grad.cpu().numpy().reshape(-1)
+    assert rel_l2(gf[g["uniform_idx"]], g["gF_uniform"]) < 1e-4
+    assert rel_l2(gf[g["top_idx"]], g["gF_top"]) < 1e-4
+    power = (np.abs(x[0].grad.cpu().numpy().astype(np.complex128)) ** 2).sum(axis=(1, 2))
+    assert rel_l2(power, g["gF_power"]) < 2e-4
