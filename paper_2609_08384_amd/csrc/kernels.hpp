@@ -74,6 +74,12 @@ __device__ inline float2 cfma(float2 acc, float2 c, float2 q) {  // acc + c q
                      fmaf(c.x, q.y, fmaf(c.y, q.x, acc.y)));
 }
 
+// A value that is the same in every lane, moved into scalar registers.
+__device__ inline float2 wave_uniform(float2 v) {
+  return make_float2(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v.x))),
+                     __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v.y))));
+}
+
 template <int NF>
 __device__ inline void rk4_point(float2* y, const float2 (*co)[kNlCoef]) {
   float2 q[NF], acc[NF], ys[NF];
@@ -218,6 +224,15 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
   __shared__ float2 s_prop[NF * N];
 
   const int tid = threadIdx.x;
+  // RK4 coefficients of the half-step: the same for every thread, read
+  // before any store and kept in scalar registers
+  float2 co[NF][kNlCoef];
+  if constexpr (NL != NL_NONE) {
+#pragma unroll
+    for (int j = 0; j < NF; ++j)
+#pragma unroll
+      for (int c = 0; c < kNlCoef; ++c) co[j][c] = wave_uniform(args.nl[j * kNlCoef + c]);
+  }
   // this step's twiddles and this block's propagators, staged once
   for (int i = tid; i < N; i += kBlock) s_tw[i] = args.tw[i];
   for (int i = tid; i < NF * N; i += kBlock) {
@@ -277,11 +292,6 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
   __syncthreads();  // s_tw, s_prop staged
 
   if constexpr (NL == NL_BEFORE) {
-    float2 co[NF][kNlCoef];
-#pragma unroll
-    for (int j = 0; j < NF; ++j)
-#pragma unroll
-      for (int c = 0; c < kNlCoef; ++c) co[j][c] = args.nl[j * kNlCoef + c];
 #pragma unroll
     for (int e = 0; e < N1; ++e) {
       float2 y[NF];
@@ -315,11 +325,6 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
 #pragma unroll
         for (int e = 0; e < N1; ++e) store_field<NT>(args.pre[j], idx0 + unsigned(e) * estep, v[j][e]);
     }
-    float2 co[NF][kNlCoef];
-#pragma unroll
-    for (int j = 0; j < NF; ++j)
-#pragma unroll
-      for (int c = 0; c < kNlCoef; ++c) co[j][c] = args.nl[j * kNlCoef + c];
 #pragma unroll
     for (int e = 0; e < N1; ++e) {
       float2 y[NF];
