@@ -6,14 +6,15 @@
 // form launch groups of at most `group_max` problems; one launch of a pass
 // covers every problem of a group (the problem index is a grid dimension and
 // each block reads its problem's pass arguments from a descriptor array), so
-// small grids fill the GPU.  Groups run one after the other, which keeps a
-// group's fields resident in the last-level cache while it is propagated.
-// Problems with fewer steps than the longest in their group leave their
-// blocks at once.  The whole run (tables and passes of every group) is
-// captured once into a hipGraph and replayed by brahms_batch_run; launch
-// groups are independent branches of that graph (up to four side streams),
-// so a bandwidth-bound group of large grids and latency-bound groups of
-// small grids can execute at the same time.
+// small grids fill the GPU.  Problems with fewer steps than the longest in
+// their group leave their blocks at once.  The whole run (tables and passes
+// of every group) is captured once into a hipGraph and replayed by
+// brahms_batch_run.  Launch groups are independent branches of that graph
+// (up to four side streams, groups dealt out largest first), so a
+// bandwidth-bound group of large grids and latency-bound groups of small
+// grids execute at the same time; within a branch groups run one after the
+// other, and the default group size (a state of at most 160 MB) keeps a
+// group's fields in the last-level cache while it is propagated.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
