@@ -160,6 +160,44 @@ def batch_ratio(dev):
             "group_max": tuned["group_max"]}
 
 
+# Sources that define the pass kernels and their launch configuration: the
+# HBM byte counts recorded under profiles/ hold only for the digest of these.
+KERNEL_SOURCES = ("paper_2609_08384_amd/csrc/kernels.hpp", "paper_2609_08384_amd/csrc/dft.hpp",
+                  "paper_2609_08384_amd/csrc/engine.hip")
+NL_OF_PASS = {0: {"x_pass": "before", "y_pass": "none", "t_pass": "after"},
+              1: {"t_pass": "before", "y_pass": "none", "x_pass": "after"}}
+
+
+def kernel_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, pass_name: str, pass_order: int):
+    """HBM bytes per launch of one pass kernel from the hardware-counter
+    summary profiles/hbm_traffic_<workload>.json (FETCH_SIZE and WRITE_SIZE
+    per dispatch, each scaled by what the counter reads for a plain copy of
+    known size), or None when there is no summary for this kernel or the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_digest") != kernel_digest():
+        return None
+    key = f"{pass_name}:{NL_OF_PASS[pass_order][pass_name]}"
+    k = rec.get("kernels", {}).get(key)
+    if k is None:
+        return None
+    return int(round(k["fetch_kib"] * 1024 * rec["fetch_factor"] + k["write_kib"] * 1024 * rec["write_factor"]))
+
+
 def make_workload(name):
     from paper_2609_08384_amd import inputs
     return {"opg256": inputs.opg256, "sfg128": inputs.sfg128, "shg32": inputs.shg32}[name]()
@@ -257,7 +295,8 @@ def main():
     bytes_per_launch = 2 * 8 * wl.nf * wl.points
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(wl.name, dom, int(schedule["pass_order"])), "kernel": dom,
                 "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": bytes_per_launch}
     per_kernel = {k: {"avg_ms": round(v[0] / max(v[1], 1), 5), "launches": v[1],
                       "GBps": (round(bytes_per_launch / (v[0] / v[1] * 1e-3) / 1e9, 1)
