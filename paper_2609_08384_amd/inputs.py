@@ -232,3 +232,51 @@ def random_fields(rng: np.random.Generator, nf: int, nx: int, ny: int, nt: int,
             a = a * np.exp(-(x ** 2 + y ** 2 + t ** 2) / smooth ** 2)
         out.append(to_c64(a))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Reduced-dimension workloads (CW beams with nt = 1, plane-wave pulses with
+# nx = ny = 1), run as batches.
+# ---------------------------------------------------------------------------
+BK_DIFFRACTION = 36.0   # D_F of the CW focusing sweep (cells^2 / L)
+BK_XI = tuple(round(2.0 + 0.2 * k, 3) for k in range(11))       # 2.0 .. 4.0
+BK_DKL = tuple(round(-4.0 + 0.2 * k, 3) for k in range(9))      # -4.0 .. -2.4
+
+
+def bk_cw_instance(xi: float, dkl: float, n: int = 128, nz: int = 200) -> Workload:
+    """Undepleted CW SHG of a beam focused at L/2 (the focusing study of
+    Sec. 5.2): nt = 1, kappa_F = 0, kappa_S = 1, D_S = D_F / 2, no walk-off;
+    w0 from xi = L / (2 z_R) with z_R = w0^2 / (4 D_F)."""
+    w0 = math.sqrt(2.0 * BK_DIFFRACTION / xi)
+    fs = [FieldSpec(kappa=0.0, diffraction=BK_DIFFRACTION),
+          FieldSpec(kappa=1.0, diffraction=BK_DIFFRACTION / 2.0)]
+    wl = Workload(f"bk_xi{xi}_dk{dkl}", n, n, 1, 2, nz, 1.0 / nz, fs, dk_const=dkl)
+    wl.init = [to_c64(focused_pulse(n, n, 1, w0, None, xi)), np.zeros((1, n, n), np.complex64)]
+    return wl
+
+
+def bk_sweep(n: int = 128, nz: int = 200) -> List[Workload]:
+    """The focusing-parameter x phase-mismatch grid BK_XI x BK_DKL (99 CW
+    problems), xi-major."""
+    return [bk_cw_instance(xi, dkl, n, nz) for xi in BK_XI for dkl in BK_DKL]
+
+
+def plane_wave_pulse_sweep(seed: int = 6, count: int = 16, nt: int = 256) -> List[Workload]:
+    """Pulsed plane-wave SHG (nx = ny = 1): Gaussian F pulse of FWHM nt/8,
+    group-velocity mismatch delta_S in U[-nt/8, nt/8] cells/L, GVD k''_F =
+    +tau0^2/2 and k''_S = -tau0^2/2 (dispersion length L), dk L in U[-6, 6],
+    kappa = 1 with peak amplitude in U[0.5, 2] (pump depletion), 100-300
+    steps."""
+    rng = np.random.default_rng(seed)
+    tau0 = fwhm_to_tau0(nt / 8.0)
+    out = []
+    for k in range(count):
+        amp = float(rng.uniform(0.5, 2.0))
+        fs = [FieldSpec(kappa=1.0, k2=tau0 ** 2 / 2.0),
+              FieldSpec(kappa=1.0, delay=float(rng.uniform(-nt / 8.0, nt / 8.0)), k2=-tau0 ** 2 / 2.0)]
+        nzk = int(rng.integers(100, 301))
+        wl = Workload(f"pw{k}", 1, 1, nt, 2, nzk, 1.0 / nzk, fs, dk_const=float(rng.uniform(-6.0, 6.0)))
+        wl.init = [to_c64(focused_pulse(1, 1, nt, 1.0, tau0, 0.0, amp)),
+                   np.zeros((nt, 1, 1), np.complex64)]
+        out.append(wl)
+    return out

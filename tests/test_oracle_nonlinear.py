@@ -8,10 +8,9 @@ import os
 import numpy as np
 import pytest
 import torch
-from scipy import integrate
 
 from oracle import ssfm
-from tests.util import rel_l2
+from tests.util import bk_efficiency, bk_integral, rel_l2
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -153,14 +152,6 @@ def test_global_second_order_convergence():
     assert 3.6 < r < 4.4
 
 
-def _bk_integral(sigma, xi):
-    re = integrate.quad(lambda u: (math.cos(sigma * u) + u * math.sin(sigma * u)) / (1 + u * u), -xi, xi,
-                        epsabs=1e-13, epsrel=1e-11, limit=400)[0]
-    im = integrate.quad(lambda u: (math.sin(sigma * u) - u * math.cos(sigma * u)) / (1 + u * u), -xi, xi,
-                        epsabs=1e-13, epsrel=1e-11, limit=400)[0]
-    return complex(re, im)
-
-
 def _bk_run(xi, dkl, n=128, nz=200, w_focus=None):
     """Undepleted CW SHG of a beam focused at L/2 (Sec. 5.2 set-up):
     returns (SSFM efficiency E_S/P_F^2, closed form kS^2 L |I|^2/(8 pi D_F xi))."""
@@ -175,9 +166,7 @@ def _bk_run(xi, dkl, n=128, nz=200, w_focus=None):
     f, s = ssfm.propagate([torch.from_numpy(f0), torch.zeros(1, n, n, dtype=torch.complex128)], prob, nz)
     pf = float((np.abs(f0) ** 2).sum())
     es = float((s.abs() ** 2).sum())
-    sigma = -dkl * (1.0 / (2 * xi))
-    closed = ks ** 2 * abs(_bk_integral(sigma, xi)) ** 2 / (8 * math.pi * dfun * xi)
-    return es / pf ** 2, closed
+    return es / pf ** 2, bk_efficiency(xi, dkl, dfun, ks)
 
 
 def test_boyd_kleinman_optimum():
@@ -195,6 +184,6 @@ def test_boyd_kleinman_optimum():
     assert effs[1] > effs[0] and effs[1] > effs[2]
     # the closed form itself peaks there too (BK's h_m ~ 1.068)
     grid = np.linspace(2.0, 4.0, 201)
-    h = [abs(_bk_integral(-g["dk_L"] / (2 * x), x)) ** 2 / (4 * x) for x in grid]
+    h = [abs(bk_integral(-g["dk_L"] / (2 * x), x)) ** 2 / (4 * x) for x in grid]
     assert abs(grid[int(np.argmax(h))] - g["xi_opt"]) < 0.05
     assert abs(max(h) - 1.068) < 2e-3

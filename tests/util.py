@@ -24,3 +24,23 @@ def rel_l2(a, b) -> float:
     b = np.asarray(b, dtype=np.complex128)
     nb = np.linalg.norm(b.ravel())
     return float(np.linalg.norm((a - b).ravel()) / (nb if nb > 0 else 1.0))
+
+
+def bk_integral(sigma: float, xi: float) -> complex:
+    """Boyd-Kleinman focusing integral int_{-xi}^{xi} exp(i sigma u)/(1 + i u) du
+    by FP64 quadrature (real and imaginary parts separately)."""
+    import math
+    from scipy import integrate
+    re = integrate.quad(lambda u: (math.cos(sigma * u) + u * math.sin(sigma * u)) / (1 + u * u), -xi, xi,
+                        epsabs=1e-13, epsrel=1e-11, limit=400)[0]
+    im = integrate.quad(lambda u: (math.sin(sigma * u) - u * math.cos(sigma * u)) / (1 + u * u), -xi, xi,
+                        epsabs=1e-13, epsrel=1e-11, limit=400)[0]
+    return complex(re, im)
+
+
+def bk_efficiency(xi: float, dkl: float, diffraction: float, kappa_s: float = 1.0) -> float:
+    """Closed-form undepleted CW SHG efficiency E_S / P_F^2 of a Gaussian beam
+    focused at L/2 (grid cells of unit area): kappa_S^2 L |I|^2 / (8 pi D_F xi)
+    with sigma = -dk z_R = -dk L / (2 xi)."""
+    import math
+    return kappa_s ** 2 * abs(bk_integral(-dkl / (2 * xi), xi)) ** 2 / (8 * math.pi * diffraction * xi)
