@@ -153,6 +153,43 @@ brahms_status brahms_plan_get_schedule(brahms_plan plan, brahms_schedule* sched)
 brahms_status brahms_timing_enable(brahms_plan plan, int enable);
 brahms_status brahms_timing_read(brahms_plan plan, double* ms, long long* launches);
 
+/* Diagnostics: the output quantities of Sec. 6 (pulse power per time slice,
+ * field energies) and the Manley-Rowe combinations of the coupled equations
+ * (Sec. 2), taken on the device from the bound fields.
+ *
+ * A record is brahms_record_size() doubles describing the fields at step
+ * index n (z = n dz):
+ *   [0]                      n
+ *   [1, 1 + nf nt)           P_j(tau) = sum_{x,y} |A_j|^2 dx dy, field-major
+ *   [1 + nf nt, + nf)        E_j = sum_tau P_j(tau) dtau
+ *   [1 + nf (nt + 1), + 3)   nf = 3: E_p/k_p + E_s/k_s, E_p/k_p + E_i/k_i,
+ *                            E_s/k_s - E_i/k_i (kappa_j of the plan);
+ *                            nf = 2: E_F/k_F + E_S/k_S, NaN, NaN;
+ *                            NaN wherever a kappa is 0.
+ * Sums run in FP64 in a fixed order: records are reproducible bit for bit.
+ * Records and snapshot buffers are caller-owned device memory; the calls
+ * below only store the pointers, which must stay valid while the plan steps.
+ *
+ * brahms_record_size: doubles per record.
+ * brahms_diagnose: one record of the fields as they are now (asynchronous
+ *   on the plan's stream).  Errors: BRAHMS_E_STATE before bind.
+ * brahms_set_monitor: from now on, whenever brahms_step completes a step
+ *   whose index is a multiple of `every`, append a record to `records`
+ *   (room for `capacity` records; later ones are dropped).  every = 0
+ *   switches the monitor off.  Resets the record count.
+ * brahms_get_monitor_count: records written since brahms_set_monitor.
+ * brahms_set_snapshots: n snapshots; when brahms_step completes step index
+ *   steps[i] (>= 1) it copies field j to buffers[i * nf + j] (field layout of
+ *   brahms_plan_bind).  n = 0 removes them.  Replaces earlier snapshots.
+ * Errors: BRAHMS_E_INVALID_ARG for NULL pointers, negative sizes or steps
+ * below 1. */
+brahms_status brahms_record_size(brahms_plan plan, int* ndoubles);
+brahms_status brahms_diagnose(brahms_plan plan, double* record);
+brahms_status brahms_set_monitor(brahms_plan plan, int every, double* records, int capacity);
+brahms_status brahms_get_monitor_count(brahms_plan plan, int* count);
+brahms_status brahms_set_snapshots(brahms_plan plan, int n, const long long* steps,
+                                   void* const* buffers);
+
 /* Adjoint (reverse-mode gradient) of the z-loop, for inverse design.  Not in
  * the paper; it differentiates exactly the discrete map that brahms_step
  * computes (Sec. 3.1: RK4 half-steps and the Fourier-space linear step).

@@ -256,6 +256,12 @@ def propagate(fields, prob: Problem, nsteps: int, n0: int = 0):
 # Manley-Rowe combinations that the lossless equations conserve
 # ---------------------------------------------------------------------------
 
+def power_traces(a: List[torch.Tensor], prob: Problem) -> List[torch.Tensor]:
+    """P_j(tau) = sum over x, y of |A_j|^2 dx dy: the pulse power per time
+    slice, the output quantity plotted in Sec. 6 (fields are [nt, ny, nx])."""
+    return [(x.abs() ** 2).sum(dim=(1, 2)) * (prob.dx * prob.dy) for x in a]
+
+
 def energies(a: List[torch.Tensor], prob: Problem) -> List[float]:
     cell = prob.dx * prob.dy * prob.dt
     return [float((x.abs() ** 2).sum()) * cell for x in a]

@@ -93,6 +93,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "brahms_batch_destroy": [vp],
         "brahms_timing_enable": [vp, i],
         "brahms_timing_read": [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)],
+        "brahms_record_size": [vp, ctypes.POINTER(i)],
+        "brahms_diagnose": [vp, vp],
+        "brahms_set_monitor": [vp, i, vp, i],
+        "brahms_get_monitor_count": [vp, ctypes.POINTER(i)],
+        "brahms_set_snapshots": [vp, i, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(vp)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -187,6 +192,8 @@ class Plan:
         self.workspace_bytes = int(size.value)
         self.workspace = None
         self.fields: List[torch.Tensor] = []
+        self._monitor: Optional[torch.Tensor] = None
+        self._snapshots: List[List[torch.Tensor]] = []
 
     def bind(self, fields: Sequence[torch.Tensor], workspace: Optional[torch.Tensor] = None):
         if len(fields) != self.nf:
@@ -279,6 +286,59 @@ class Plan:
         cnt = (ctypes.c_longlong * TIMING_KINDS)()
         _check(self._lib.brahms_timing_read(self._h, ms, cnt), "brahms_timing_read")
         return {name: (ms[k], int(cnt[k])) for k, name in enumerate(TIMING_NAMES)}
+
+    # -- diagnostics (Sec. 6 outputs) ------------------------------------
+    def record_size(self) -> int:
+        n = ctypes.c_int()
+        _check(self._lib.brahms_record_size(self._h, ctypes.byref(n)), "brahms_record_size")
+        return int(n.value)
+
+    def split_records(self, rec: torch.Tensor) -> dict:
+        """Split [k, record_size] float64 records into their parts (a view of
+        the layout documented at brahms_record_size in include/brahms.h)."""
+        rec = rec.reshape(-1, self.record_size()).cpu()
+        nf, nt = self.nf, self.nt
+        return {"step": rec[:, 0].to(torch.int64),
+                "power": rec[:, 1:1 + nf * nt].reshape(-1, nf, nt),
+                "energy": rec[:, 1 + nf * nt:1 + nf * (nt + 1)],
+                "manley_rowe": rec[:, 1 + nf * (nt + 1):1 + nf * (nt + 1) + (3 if nf == 3 else 1)]}
+
+    def diagnose(self) -> dict:
+        """Power traces, energies and Manley-Rowe values of the fields now."""
+        rec = torch.empty(self.record_size(), dtype=torch.float64, device=self.fields[0].device)
+        _check(self._lib.brahms_diagnose(self._h, ctypes.c_void_p(rec.data_ptr())), "brahms_diagnose")
+        return {k: v[0] for k, v in self.split_records(rec).items()}
+
+    def set_monitor(self, every: int, capacity: int = 0):
+        """Record diagnostics whenever a completed step index is a multiple of
+        `every` (at most `capacity` records); every = 0 switches it off."""
+        if every > 0:
+            self._monitor = torch.zeros(capacity, self.record_size(), dtype=torch.float64,
+                                        device=self.fields[0].device)
+            ptr = ctypes.c_void_p(self._monitor.data_ptr())
+        else:
+            self._monitor, ptr, capacity = None, ctypes.c_void_p(), 0
+        _check(self._lib.brahms_set_monitor(self._h, every, ptr, capacity), "brahms_set_monitor")
+
+    def monitor_records(self) -> dict:
+        n = ctypes.c_int()
+        _check(self._lib.brahms_get_monitor_count(self._h, ctypes.byref(n)), "brahms_get_monitor_count")
+        if self._monitor is None or n.value == 0:
+            return self.split_records(torch.zeros(0, self.record_size(), dtype=torch.float64))
+        return self.split_records(self._monitor[:n.value])
+
+    def set_snapshots(self, steps: Sequence[int]) -> List[List[torch.Tensor]]:
+        """Copy the fields into new device tensors when each of `steps` (step
+        indices >= 1) is completed; returns those tensors."""
+        steps = [int(s) for s in steps]
+        dev = self.fields[0].device
+        self._snapshots = [[torch.zeros(self.nt, self.ny, self.nx, dtype=torch.complex64, device=dev)
+                            for _ in range(self.nf)] for _ in steps]
+        ptrs = (ctypes.c_void_p * max(1, len(steps) * self.nf))(
+            *[t.data_ptr() for snap in self._snapshots for t in snap])
+        arr = (ctypes.c_longlong * max(1, len(steps)))(*steps)
+        _check(self._lib.brahms_set_snapshots(self._h, len(steps), arr, ptrs), "brahms_set_snapshots")
+        return self._snapshots
 
     def destroy(self):
         if getattr(self, "_h", None) is not None and self._h.value:

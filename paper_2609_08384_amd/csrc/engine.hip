@@ -301,8 +301,12 @@ brahms_status run_steps(brahms_plan_s& p, int nsteps) {
   while (done < nsteps) {
     const int count = std::min(kChunk, nsteps - done);
     if (brahms_status st = detail::refresh_tables(p, p.step, count)) return st;
-    for (int s = 0; s < count; ++s)
+    const bool watch = p.mon_every > 0 || !p.snap_steps.empty();
+    for (int s = 0; s < count; ++s) {
       if (brahms_status st = detail::launch_step(p, s, io)) return st;
+      if (watch)
+        if (brahms_status st = detail::after_step(p, p.step + s + 1)) return st;
+    }
     p.step += count;
     done += count;
   }

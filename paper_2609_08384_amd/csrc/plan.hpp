@@ -35,6 +35,12 @@ struct brahms_plan_s {
   int adj_nsteps = 0, adj_every = 0;
   bool adj_last_recorded = false;   // segment slots hold the last segment
   char* adj_ws = nullptr;
+  // diagnostics (brahms_set_monitor / brahms_set_snapshots)
+  int mon_every = 0;                    // record when the step index is a multiple
+  double* mon_records = nullptr;        // device, capacity x record doubles
+  int mon_capacity = 0, mon_count = 0;
+  std::vector<long long> snap_steps;    // step indices of the snapshots
+  std::vector<float2*> snap_buffers;    // [snapshot * nf + field], device
 };
 
 namespace brahms {
@@ -93,6 +99,8 @@ int pass_axis(const brahms_plan_s& p, int k);
 brahms_status launch_linear_pass(brahms_plan_s& p, int row, int axis, float2* const* fields,
                                  bool conj);
 const float2* table_row(const brahms_plan_s& p, int row);
+// Monitor records and snapshots due once `step_done` steps are complete.
+brahms_status after_step(brahms_plan_s& p, long long step_done);
 const float2* nl_coefficients(const brahms_plan_s& p, int row, int half);
 
 }  // namespace detail

@@ -117,3 +117,31 @@ def test_profile_length_checked(lib):
     # propagate past the profile: checked after the bind check, so it is E_STATE first
     assert lib.brahms_step(h, 4) == brahms.BRAHMS_E_STATE
     lib.brahms_plan_destroy(h)
+
+
+def test_diagnostics_host_checks(lib):
+    c, keep = _params(nf=3)
+    st, h = _create(lib, 8, 4, 16, 3, c)
+    assert st == brahms.BRAHMS_OK
+    n = ctypes.c_int()
+    assert lib.brahms_record_size(h, ctypes.byref(n)) == brahms.BRAHMS_OK
+    assert n.value == 1 + 3 * (16 + 1) + 3
+    assert lib.brahms_record_size(h, None) == brahms.BRAHMS_E_INVALID_ARG
+    assert lib.brahms_diagnose(h, ctypes.c_void_p(0x1000)) == brahms.BRAHMS_E_STATE   # before bind
+    assert lib.brahms_set_monitor(h, 5, None, 4) == brahms.BRAHMS_E_INVALID_ARG
+    assert lib.brahms_set_monitor(h, 5, ctypes.c_void_p(0x1000), 0) == brahms.BRAHMS_E_INVALID_ARG
+    assert lib.brahms_set_monitor(h, -1, None, 0) == brahms.BRAHMS_E_INVALID_ARG
+    assert lib.brahms_set_monitor(h, 0, None, 0) == brahms.BRAHMS_OK                # off
+    assert lib.brahms_set_monitor(h, 5, ctypes.c_void_p(0x1000), 4) == brahms.BRAHMS_OK
+    assert lib.brahms_get_monitor_count(h, ctypes.byref(n)) == brahms.BRAHMS_OK and n.value == 0
+    steps = (ctypes.c_longlong * 2)(3, 0)
+    bufs = (ctypes.c_void_p * 6)(*([0x1000] * 6))
+    assert lib.brahms_set_snapshots(h, 2, steps, bufs) == brahms.BRAHMS_E_INVALID_ARG   # step 0
+    steps[1] = 9
+    bufs[4] = 0
+    assert lib.brahms_set_snapshots(h, 2, steps, bufs) == brahms.BRAHMS_E_INVALID_ARG   # NULL buffer
+    bufs[4] = 0x1000
+    assert lib.brahms_set_snapshots(h, 2, steps, bufs) == brahms.BRAHMS_OK
+    assert lib.brahms_set_snapshots(h, 0, None, None) == brahms.BRAHMS_OK
+    assert lib.brahms_set_snapshots(h, -1, None, None) == brahms.BRAHMS_E_INVALID_ARG
+    lib.brahms_plan_destroy(h)

@@ -184,3 +184,22 @@ def test_two_stage_linear_step_equals_3d_multiply():
     one = ssfm.linear_step(a, ssfm.linear_symbol(fp, prob), 0.9).numpy()
     two = ssfm.linear_step_two_stage(a, fp, prob, 0.9).numpy()
     assert rel_l2(two, one) < 1e-14
+
+
+def test_power_trace_of_gaussian_pulse_and_energy():
+    """P(tau) of a sampled Gaussian beam-pulse exp(-r^2/w^2 - tau^2/tau0^2):
+    the transverse sum of exp(-2 r^2/w^2) over unit cells is pi w^2 / 2 to
+    exponential accuracy for w >> 1 cell (Poisson summation), so P(tau) =
+    (pi w^2 / 2) exp(-2 tau^2 / tau0^2); and sum_tau P dtau is the energy."""
+    n, nt, w, tau0 = 64, 32, 6.0, 5.0
+    x = ssfm.axis_coords(n)
+    t = ssfm.axis_coords(nt)
+    a = torch.exp(-(x[None, None, :] ** 2 + x[None, :, None] ** 2) / w ** 2
+                  - t[:, None, None] ** 2 / tau0 ** 2).to(torch.complex128)
+    prob = ssfm.Problem(n, n, nt, 2, 0.1, [ssfm.FieldParams(), ssfm.FieldParams()])
+    p = ssfm.power_traces([a, 2 * a], prob)
+    want = math.pi * w ** 2 / 2 * torch.exp(-2 * t ** 2 / tau0 ** 2)
+    assert float((p[0] - want).abs().max()) < 1e-12 * float(want.max())
+    assert float((p[1] - 4 * want).abs().max()) < 1e-11 * float(want.max())
+    e = ssfm.energies([a, 2 * a], prob)
+    assert abs(float(p[0].sum()) * prob.dt - e[0]) < 1e-12 * e[0]
