@@ -62,6 +62,8 @@ def shg_energy_loss(out: List[torch.Tensor], prob: ssfm.Problem) -> torch.Tensor
 def gradients(fields_in: Sequence, dk: Sequence[float], prob: ssfm.Problem, nsteps: int,
               loss=shg_energy_loss) -> Tuple[float, List[torch.Tensor], torch.Tensor]:
     """(J, dJ/dA_in per field, dJ/ddk_n) by reverse-mode differentiation."""
+    if prob.dk_map is not None:
+        raise NotImplementedError("gradients with a transverse mismatch map")
     a = [torch.as_tensor(x).to(ssfm.DTYPE_C).clone().requires_grad_(True) for x in fields_in]
     d = torch.as_tensor(list(dk), dtype=ssfm.DTYPE_R).clone().requires_grad_(True)
     out = forward(a, d, prob, nsteps)

@@ -82,6 +82,9 @@ class Problem:
     dx: float = 1.0
     dy: float = 1.0
     dt: float = 1.0
+    # transverse mismatch map: dk(x, y, z) = dk_n + s_n dk_map[y, x] in step n
+    dk_map: Optional[object] = None        # [ny, nx] array (1/L), or None
+    dk_map_scale: Optional[Sequence[float]] = None   # s_n per step (None: all 1)
 
 
 # ---------------------------------------------------------------------------
@@ -159,20 +162,39 @@ def linear_step_two_stage(a: torch.Tensor, fp: FieldParams, prob: Problem,
 # mismatch phase Phi(z) = int_0^z dk(z') dz'
 # ---------------------------------------------------------------------------
 
-def phase_function(prob: Problem) -> Callable[[float], float]:
+def _piecewise_integral(values: Sequence[float], dz: float) -> Callable[[float], float]:
+    """z -> integral_0^z v(z') dz' for v piecewise constant per step (v_n on
+    [n dz, (n+1) dz))."""
+    vals = [float(v) for v in values]
+    cum = [0.0]
+    for v in vals:
+        cum.append(cum[-1] + v * dz)
+
+    def integral(z: float) -> float:
+        n = int(math.floor(z / dz + 1e-9))
+        n = min(max(n, 0), len(vals) - 1)
+        return cum[n] + vals[n] * (z - n * dz)
+    return integral
+
+
+def phase_function(prob: Problem) -> Callable:
+    """Phi(z) = int_0^z dk dz' (reading of Sec. 2's exp(-/+ i dk z) for a dk
+    that varies along z).  With a transverse map, dk(x, y, z) = dk_n +
+    s_n dk_map(x, y) and Phi(x, y, z) = Phi(z) + dk_map(x, y) Psi(z),
+    Psi(z) = int_0^z s dz' (a real [1, ny, nx] tensor for each z)."""
     if prob.dk is None:
         dk = float(prob.dk_const)
-        return lambda z: dk * z
-    dks = [float(v) for v in prob.dk]
-    cum = [0.0]
-    for v in dks:
-        cum.append(cum[-1] + v * prob.dz)
-
-    def phi(z: float) -> float:
-        n = int(math.floor(z / prob.dz + 1e-9))
-        n = min(max(n, 0), len(dks) - 1)
-        return cum[n] + dks[n] * (z - n * prob.dz)
-    return phi
+        base = lambda z: dk * z
+    else:
+        base = _piecewise_integral(prob.dk, prob.dz)
+    if prob.dk_map is None:
+        return base
+    m = torch.as_tensor(prob.dk_map, dtype=DTYPE_R).reshape(1, prob.ny, prob.nx)
+    if prob.dk_map_scale is None:
+        psi = lambda z: z
+    else:
+        psi = _piecewise_integral(prob.dk_map_scale, prob.dz)
+    return lambda z: base(z) + m * psi(z)
 
 
 # ---------------------------------------------------------------------------

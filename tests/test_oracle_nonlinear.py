@@ -187,3 +187,44 @@ def test_boyd_kleinman_optimum():
     h = [abs(bk_integral(-g["dk_L"] / (2 * x), x)) ** 2 / (4 * x) for x in grid]
     assert abs(grid[int(np.argmax(h))] - g["xi_opt"]) < 0.05
     assert abs(max(h) - 1.068) < 2e-3
+
+
+def test_uniform_transverse_map_equals_shifted_constant_mismatch():
+    """dk(x, y, z) = dk + c everywhere is the scalar case with dk + c."""
+    rng = np.random.default_rng(41)
+    a = _random_smooth(rng, 2, 8, 0.8)
+    fps = [_fp(kappa=1.1, diffraction=0.5, tan_rho=0.2, k2=0.4), _fp(kappa=0.8, diffraction=0.25, delay=0.3)]
+    nz = 12
+    plain = ssfm.propagate(a, ssfm.Problem(8, 8, 8, 2, 1.0 / nz, fps, dk_const=2.5 + 1.25), nz)
+    mapped = ssfm.propagate(a, ssfm.Problem(8, 8, 8, 2, 1.0 / nz, fps, dk_const=2.5,
+                                            dk_map=np.full((8, 8), 1.25)), nz)
+    for x, y in zip(plain, mapped):
+        assert float((x - y).abs().max()) < 1e-13 * float(x.abs().max())
+
+
+def test_transverse_map_undepleted_shg_closed_form():
+    """kappa_F = 0 and no linear terms: every (x, y) column is an independent
+    undepleted SHG problem with its own mismatch dk + s_n m(x, y), so
+    S(L) = i kS F0^2 sum_n exp(-i Phi_n) (1 - exp(-i K_n dz)) / (i K_n) with
+    K_n = dk + s_n m and Phi_n = dk z_n + m sum_{l<n} s_l dz.  The map is
+    asymmetric in x and y, so a transposed map fails."""
+    nx, ny, nt, nz = 5, 3, 2, 100
+    rng = np.random.default_rng(42)
+    m = rng.uniform(-8, 8, (ny, nx))
+    s = rng.uniform(0.2, 1.5, nz)
+    dk, ks, f0 = 1.7, 1.3, 0.9 - 0.2j
+    fps = [_fp(kappa=0.0), _fp(kappa=ks)]
+    prob = ssfm.Problem(nx, ny, nt, 2, 1.0 / nz, fps, dk_const=dk, dk_map=m, dk_map_scale=list(s))
+    a0 = [torch.full((nt, ny, nx), f0, dtype=torch.complex128), torch.zeros(nt, ny, nx, dtype=torch.complex128)]
+    out = ssfm.propagate(a0, prob, nz)
+    dz = 1.0 / nz
+    psi = np.concatenate([[0.0], np.cumsum(s * dz)])
+    want = np.zeros((ny, nx), complex)
+    for n in range(nz):
+        k = dk + s[n] * m
+        phi_n = dk * n * dz + m * psi[n]
+        want += np.exp(-1j * phi_n) * (1 - np.exp(-1j * k * dz)) / (1j * k)
+    want *= 1j * ks * f0 ** 2
+    got = out[1].numpy()
+    assert np.abs(got - want[None]).max() < 1e-9 * np.abs(want).max()
+    assert np.abs(out[0].numpy() - f0).max() < 1e-13   # F is not driven (kappa_F = 0)
