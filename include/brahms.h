@@ -82,14 +82,25 @@ typedef struct {
   double dx, dy, dt;            /* grid spacings; 0 means 1                       */
   brahms_field_params field[3]; /* first nf entries used                          */
   unsigned flags;               /* BRAHMS_CHECK_FINITE                            */
+  /* Transverse phase-mismatch map (the spatially varying dk(x, y, z) of the
+   * phase-matching module, Sec. 4.1): in step n,
+   *   dk(x, y, z) = dk_n + s_n m(x, y),
+   * so Phi(x, y, z) = Phi(z) + m(x, y) Psi(z), Psi(z) = int_0^z s dz'.
+   * dk_map: host array m[y][x] (nx * ny doubles, 1/L) or NULL (no map);
+   * dk_map_scale: host array s_n (n_dk_map_scale steps) or NULL (s = 1).
+   * Both are copied at create.  Plans only: batches and the adjoint reject a
+   * map (BRAHMS_E_UNSUPPORTED). */
+  const double* dk_map;
+  const double* dk_map_scale;
+  int n_dk_map_scale;
 } brahms_params;
 
 /* Create a plan for an nx x ny x nt grid with nfields in {2, 3}.
  * Axis lengths must be 1, 2, 4, 8, 16, 32, 64, 96, 128 or 256
  * (BRAHMS_E_UNSUPPORTED otherwise).  The parameters are copied.
  * Errors: BRAHMS_E_INVALID_ARG for a non-positive size, nf outside {2, 3},
- * NULL params/out, dz <= 0, a non-finite coefficient, or dk != NULL with
- * n_dk < 1. */
+ * NULL params/out, dz <= 0, a non-finite coefficient, dk != NULL with
+ * n_dk < 1, or dk_map_scale without dk_map or with n_dk_map_scale < 1. */
 brahms_status brahms_plan_create(int nx, int ny, int nt, int nfields,
                                  const brahms_params* params, void* hip_stream,
                                  brahms_plan* out);

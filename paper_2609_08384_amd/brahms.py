@@ -12,6 +12,7 @@ import os
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
+import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -53,7 +54,9 @@ class ParamsC(ctypes.Structure):
     _fields_ = [("dz", ctypes.c_double), ("dk_const", ctypes.c_double),
                 ("dk", ctypes.POINTER(ctypes.c_double)), ("n_dk", ctypes.c_int),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dt", ctypes.c_double),
-                ("field", FieldParamsC * 3), ("flags", ctypes.c_uint)]
+                ("field", FieldParamsC * 3), ("flags", ctypes.c_uint),
+                ("dk_map", ctypes.POINTER(ctypes.c_double)),
+                ("dk_map_scale", ctypes.POINTER(ctypes.c_double)), ("n_dk_map_scale", ctypes.c_int)]
 
 
 _lib = None
@@ -136,27 +139,43 @@ class Params:
     dy: float = 1.0
     dt: float = 1.0
     check_finite: bool = False
+    dk_map: Optional[object] = None                # [ny, nx] array: m(x, y)
+    dk_map_scale: Optional[Sequence[float]] = None  # s_n per step (None: 1)
 
 
 def params_from_workload(wl) -> Params:
     fs = [FieldParams(f.kappa, f.diffraction, f.tan_rho, f.delay, f.k2, f.k3, f.alpha)
           for f in wl.fields]
     dk = None if wl.dk is None else [float(v) for v in wl.dk]
-    return Params(dz=wl.dz, fields=fs, dk_const=wl.dk_const, dk=dk)
+    return Params(dz=wl.dz, fields=fs, dk_const=wl.dk_const, dk=dk,
+                  dk_map=getattr(wl, "dk_map", None), dk_map_scale=getattr(wl, "dk_map_scale", None))
+
+
+def _doubles(values):
+    arr = (ctypes.c_double * len(values))(*[float(v) for v in values])
+    return arr, ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
 
 
 def _params_c(p: Params, nf: int):
     c = ParamsC()
     c.dz = p.dz
     c.dk_const = p.dk_const
-    keep = None
+    keep = []
     if p.dk is not None:
-        keep = (ctypes.c_double * len(p.dk))(*[float(v) for v in p.dk])
-        c.dk = ctypes.cast(keep, ctypes.POINTER(ctypes.c_double))
+        arr, c.dk = _doubles(p.dk)
+        keep.append(arr)
         c.n_dk = len(p.dk)
     else:
         c.dk = None
         c.n_dk = 0
+    c.dk_map, c.dk_map_scale, c.n_dk_map_scale = None, None, 0
+    if p.dk_map is not None:
+        arr, c.dk_map = _doubles(np.asarray(p.dk_map, dtype=np.float64).reshape(-1))
+        keep.append(arr)
+        if p.dk_map_scale is not None:
+            arr, c.dk_map_scale = _doubles(p.dk_map_scale)
+            keep.append(arr)
+            c.n_dk_map_scale = len(p.dk_map_scale)
     c.dx, c.dy, c.dt = p.dx, p.dy, p.dt
     for j, f in enumerate(p.fields[:3]):
         c.field[j] = FieldParamsC(f.kappa, f.diffraction, f.tan_rho, f.delay, f.k2, f.k3, f.alpha)

@@ -72,15 +72,20 @@ void launch_pass(bool full, dim3 grid, hipStream_t st, const PassArgs& a) {
 
 using brahms::detail::tile_multiplier;
 
+template <int N1, int N2, int AX, int NF>
+void launch_nl_nf(int nl, bool full, dim3 grid, hipStream_t st, const PassArgs& a) {
+  switch (nl) {
+    case NL_BEFORE: launch_pass<N1, N2, AX, NF, NL_BEFORE>(full, grid, st, a); break;
+    case NL_AFTER: launch_pass<N1, N2, AX, NF, NL_AFTER>(full, grid, st, a); break;
+    case NL_BEFORE | NL_MAP: launch_pass<N1, N2, AX, NF, NL_BEFORE | NL_MAP>(full, grid, st, a); break;
+    default: launch_pass<N1, N2, AX, NF, NL_AFTER | NL_MAP>(full, grid, st, a); break;
+  }
+}
+
 template <int N1, int N2, int AX>
 void launch_nl(int nf, int nl, bool full, dim3 grid, hipStream_t st, const PassArgs& a) {
-  if (nf == 3) {
-    if (nl == NL_BEFORE) launch_pass<N1, N2, AX, 3, NL_BEFORE>(full, grid, st, a);
-    else launch_pass<N1, N2, AX, 3, NL_AFTER>(full, grid, st, a);
-  } else {
-    if (nl == NL_BEFORE) launch_pass<N1, N2, AX, 2, NL_BEFORE>(full, grid, st, a);
-    else launch_pass<N1, N2, AX, 2, NL_AFTER>(full, grid, st, a);
-  }
+  if (nf == 3) launch_nl_nf<N1, N2, AX, 3>(nl, full, grid, st, a);
+  else launch_nl_nf<N1, N2, AX, 2>(nl, full, grid, st, a);
 }
 
 // One pass along `axis`; nl says where the RK4 half-step goes (NL_NONE only
@@ -148,6 +153,12 @@ void layout(brahms_plan_s& p) {
   off = align_up(off + sizeof(float2) * size_t(kChunk) * 2 * p.nf * kNlCoef);
   p.off_flag = off;
   off = align_up(off + sizeof(int));
+  if (!p.dk_map.empty()) {
+    p.off_map = off;
+    off = align_up(off + sizeof(double) * p.dk_map.size());
+    p.off_maptab = off;
+    off = align_up(off + sizeof(float2) * 5 * p.dk_map.size());
+  }
   p.ws_size = off;
 }
 
@@ -213,6 +224,7 @@ brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count) {
   ta.dk = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_dk);
   ta.n0 = n0;
   ta.count = count;
+  p.table_n0 = n0;
   ta.nx = p.nx; ta.ny = p.ny; ta.nt = p.nt; ta.nf = p.nf;
   ta.dz = p.dz; ta.dx = p.dx; ta.dy = p.dy; ta.dt = p.dt; ta.dk_const = p.dk_const;
   for (int j = 0; j < p.nf; ++j) {
@@ -254,15 +266,37 @@ brahms_status timed_dispatch(brahms_plan_s& p, int ax, int nlmode, const PassArg
   return BRAHMS_OK;
 }
 
+// The transverse phase factors of step n at its five stage offsets.
+brahms_status map_table(brahms_plan_s& p, long long n) {
+  MapArgs m{};
+  m.map = reinterpret_cast<const double*>(p.ws + p.off_map);
+  m.out = reinterpret_cast<float2*>(p.ws + p.off_maptab);
+  m.plane = unsigned(p.dk_map.size());
+  const double psi_n = p.map_scale.empty() ? double(n) * p.dz : p.psi0[size_t(n)];
+  const double s_n = p.map_scale.empty() ? 1.0 : p.map_scale[size_t(n)];
+  for (int k = 0; k < 5; ++k) m.psi[k] = psi_n + s_n * (0.25 * k) * p.dz;
+  hipLaunchKernelGGL(map_phase_table, dim3((m.plane + 255) / 256), dim3(256), 0, p.stream, m);
+  HIP_TRY(hipGetLastError());
+  return BRAHMS_OK;
+}
+
 }  // namespace
 
 brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io) {
+  const bool map = !p.dk_map.empty();
+  if (map)
+    if (brahms_status st = map_table(p, p.table_n0 + row)) return st;
   // pass order of the step: the first pass carries the first RK4 half-step,
   // the last pass the second one (the axis operators commute)
   for (int k = 0; k < 3; ++k) {
     const int ax = pass_axis(p, k);
-    const int nlmode = k == 0 ? NL_BEFORE : (k == 2 ? NL_AFTER : NL_NONE);
+    int nlmode = k == 0 ? NL_BEFORE : (k == 2 ? NL_AFTER : NL_NONE);
     PassArgs a = pass_args(p, row, ax);
+    if (map && nlmode != NL_NONE) {
+      nlmode |= NL_MAP;
+      a.map = reinterpret_cast<const float2*>(p.ws + p.off_maptab) +
+              (k == 0 ? 0 : 2) * p.dk_map.size();
+    }
     for (int j = 0; j < 3; ++j) {
       a.f[j] = k == 0 ? io.in[j] : io.out[j];
       a.fo[j] = io.out[j];
@@ -333,6 +367,8 @@ brahms_status brahms_plan_create(int nx, int ny, int nt, int nfields, const brah
     return fail(BRAHMS_E_INVALID_ARG, "negative grid spacing");
   if (params->dk != nullptr && params->n_dk < 1)
     return fail(BRAHMS_E_INVALID_ARG, "dk profile given with n_dk < 1");
+  if (params->dk_map_scale != nullptr && (params->dk_map == nullptr || params->n_dk_map_scale < 1))
+    return fail(BRAHMS_E_INVALID_ARG, "dk_map_scale needs dk_map and n_dk_map_scale >= 1");
   if (!supported_length(nx) || !supported_length(ny) || !supported_length(nt))
     return fail(BRAHMS_E_UNSUPPORTED,
                 "axis lengths must be one of 1, 2, 4, 8, 16, 32, 64, 96, 128, 256");
@@ -353,6 +389,22 @@ brahms_status brahms_plan_create(int nx, int ny, int nt, int nfields, const brah
     p->phi0.resize(p->dk.size() + 1);
     p->phi0[0] = 0.0;
     for (size_t k = 0; k < p->dk.size(); ++k) p->phi0[k + 1] = p->phi0[k] + p->dk[k] * p->dz;
+  }
+  if (params->dk_map != nullptr) {
+    p->dk_map.assign(params->dk_map, params->dk_map + size_t(nx) * ny);
+    bool ok = true;
+    for (double v : p->dk_map) ok = ok && std::isfinite(v);
+    if (params->dk_map_scale != nullptr) {
+      p->map_scale.assign(params->dk_map_scale, params->dk_map_scale + params->n_dk_map_scale);
+      for (double v : p->map_scale) ok = ok && std::isfinite(v);
+      p->psi0.resize(p->map_scale.size() + 1);
+      p->psi0[0] = 0.0;
+      for (size_t k = 0; k < p->map_scale.size(); ++k) p->psi0[k + 1] = p->psi0[k] + p->map_scale[k] * p->dz;
+    }
+    if (!ok) {
+      delete p;
+      return fail(BRAHMS_E_INVALID_ARG, "non-finite dk_map or dk_map_scale entry");
+    }
   }
   for (int j = 0; j < nfields; ++j) p->fp[j] = params->field[j];
   p->flags = params->flags;
@@ -391,6 +443,11 @@ brahms_status brahms_plan_bind(brahms_plan plan, void* const* fields, void* work
                            hipMemcpyHostToDevice, plan->stream));
     HIP_TRY(hipStreamSynchronize(plan->stream));
   }
+  if (!plan->dk_map.empty()) {
+    HIP_TRY(hipMemcpyAsync(plan->ws + plan->off_map, plan->dk_map.data(),
+                           sizeof(double) * plan->dk_map.size(), hipMemcpyHostToDevice, plan->stream));
+    HIP_TRY(hipStreamSynchronize(plan->stream));
+  }
   plan->bound = true;
   return BRAHMS_OK;
 }
@@ -403,6 +460,8 @@ brahms_status brahms_step(brahms_plan plan, int nsteps) {
   plan->adj_ready = false;  // a recorded adjoint forward no longer matches
   if (!plan->dk.empty() && plan->step + nsteps > (long long)plan->dk.size())
     return fail(BRAHMS_E_INVALID_ARG, "steps beyond the end of the dk profile");
+  if (!plan->map_scale.empty() && plan->step + nsteps > (long long)plan->map_scale.size())
+    return fail(BRAHMS_E_INVALID_ARG, "steps beyond the end of the dk_map_scale profile");
   if (brahms_status st = run_steps(*plan, nsteps)) return st;
   if (plan->flags & BRAHMS_CHECK_FINITE) {
     int* flag = reinterpret_cast<int*>(plan->ws + plan->off_flag);

@@ -28,6 +28,9 @@ constexpr int kNlCoef = 6;         // RK4 coefficients per field per half-step
 
 enum Axis { AX_X = 0, AX_Y = 1, AX_T = 2 };
 enum NlMode { NL_NONE = 0, NL_BEFORE = 1, NL_AFTER = 2 };
+// Added to NL_BEFORE / NL_AFTER: the mismatch phase also has a transverse
+// part (a per-(x, y) table of exp(i m(x, y) Psi(z)) for each RK4 stage).
+constexpr int NL_MAP = 4;
 
 struct PassArgs {
   float2* f[3];          // fields read (complex64, [nt][ny][nx])
@@ -45,6 +48,8 @@ struct PassArgs {
   unsigned tile_mul;     // block -> tile map: tile = (block * tile_mul) mod tiles
   unsigned tiles;        // number of tiles (blocks along x of the launch)
   long long nz;          // batched launches: the instance is done once step >= nz
+  const float2* map;     // NL_MAP: exp(i m(x,y) Psi) at this half-step's three
+                         // stage positions, [3][ny][nx]
 };
 
 // ---------------------------------------------------------------------------
@@ -80,28 +85,44 @@ __device__ inline float2 wave_uniform(float2 v) {
                      __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v.y))));
 }
 
+// Transverse part of the mismatch phase at one stage: Q_j times
+// exp(i sigma_j m Psi) = w (sigma = +1) or conj(w) (sigma = -1, the
+// sum-frequency field: p of three fields, S of SHG).
 template <int NF>
-__device__ inline void rk4_point(float2* y, const float2 (*co)[kNlCoef]) {
+__device__ inline void rotate_products(float2* q, float2 w) {
+  constexpr int neg = NF == 3 ? 0 : 1;
+#pragma unroll
+  for (int j = 0; j < NF; ++j) q[j] = j == neg ? cmulc(q[j], w) : cmul(q[j], w);
+}
+
+// MAP: w[0], w[1], w[2] are the transverse phase factors at z_a, z_a + h/2
+// and z_a + h (unused otherwise).
+template <int NF, bool MAP = false>
+__device__ inline void rk4_point(float2* y, const float2 (*co)[kNlCoef], const float2* w = nullptr) {
   float2 q[NF], acc[NF], ys[NF];
   chi2_products<NF>(y, q);
+  if constexpr (MAP) rotate_products<NF>(q, w[0]);
 #pragma unroll
   for (int j = 0; j < NF; ++j) {
     acc[j] = cfma(y[j], co[j][3], q[j]);
     ys[j] = cfma(y[j], co[j][0], q[j]);
   }
   chi2_products<NF>(ys, q);
+  if constexpr (MAP) rotate_products<NF>(q, w[1]);
 #pragma unroll
   for (int j = 0; j < NF; ++j) {
     acc[j] = cfma(acc[j], co[j][4], q[j]);
     ys[j] = cfma(y[j], co[j][1], q[j]);
   }
   chi2_products<NF>(ys, q);
+  if constexpr (MAP) rotate_products<NF>(q, w[1]);
 #pragma unroll
   for (int j = 0; j < NF; ++j) {
     acc[j] = cfma(acc[j], co[j][4], q[j]);
     ys[j] = cfma(y[j], co[j][2], q[j]);
   }
   chi2_products<NF>(ys, q);
+  if constexpr (MAP) rotate_products<NF>(q, w[2]);
 #pragma unroll
   for (int j = 0; j < NF; ++j) y[j] = cfma(acc[j], co[j][5], q[j]);
 }
@@ -203,6 +224,21 @@ __device__ inline void store_field(float2* base, unsigned idx, float2 v) {
   }
 }
 
+// Transverse phase factors of slot e at the half-step's three stage
+// positions: read per slot along x, the column's values along tau.
+template <int AX, int N2>
+__device__ __forceinline__ void map_factors(const float2* map, unsigned plane, unsigned xy0, int e,
+                                            const float2* wt, float2* w) {
+  if constexpr (AX == AX_T) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w[k] = wt[k];
+  } else {
+    const unsigned xy = xy0 + unsigned(N2 * e);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w[k] = map[k * plane + xy];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // The fused axis pass.  AX selects the line family:
 //   X: line = (y, tau), element stride 1, lanes t-fastest (contiguous loads)
@@ -218,6 +254,8 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
                                                int field0) {
   using G = LineGeom<N1, N2>;
   constexpr int N = G::N;
+  constexpr int NLM = NL & 3;                  // where the RK4 half-step goes
+  constexpr bool MAP = (NL & NL_MAP) != 0;     // transverse mismatch map
   constexpr bool NT = (AX == AX_X) ? bool(BRAHMS_NT_X) : bool(BRAHMS_NT_YT);
   __shared__ float2 lds[G::LDS_ELEMS];
   __shared__ float2 s_tw[N];
@@ -227,7 +265,7 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
   // RK4 coefficients of the half-step: the same for every thread, read
   // before any store and kept in scalar registers
   float2 co[NF][kNlCoef];
-  if constexpr (NL != NL_NONE) {
+  if constexpr (NLM != NL_NONE) {
 #pragma unroll
     for (int j = 0; j < NF; ++j)
 #pragma unroll
@@ -279,6 +317,18 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
   }
   const unsigned idx0 = base + unsigned(t) * estride;
   const unsigned estep = unsigned(N2) * estride;
+  // transverse-map index of slot 0 (x pass: slot e adds N2 e; tau pass: the
+  // same column for every slot, so its three factors are read once here)
+  unsigned plane = 0, xy0 = 0;
+  float2 wt[3];
+  if constexpr (MAP) {
+    plane = unsigned(args.nx) * unsigned(args.ny);
+    xy0 = idx0 % plane;
+    if constexpr (AX == AX_T) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) wt[k] = args.map[k * plane + xy0];
+    }
+  }
   float2* lbuf = lds + li * G::LSTRIDE;
   const DftConsts K = *args.consts;
 
@@ -291,14 +341,20 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
   }
   __syncthreads();  // s_tw, s_prop staged
 
-  if constexpr (NL == NL_BEFORE) {
+  if constexpr (NLM == NL_BEFORE) {
 #pragma unroll
     for (int e = 0; e < N1; ++e) {
       float2 y[NF];
 #pragma unroll
       for (int j = 0; j < NF; ++j) y[j] = v[j][e];
       if (e > 0) point_link<NF>(y, v, e - 1);
-      rk4_point<NF>(y, co);
+      if constexpr (MAP) {
+        float2 w[3];
+        map_factors<AX, N2>(args.map, plane, xy0, e, wt, w);
+        rk4_point<NF, true>(y, co, w);
+      } else {
+        rk4_point<NF>(y, co);
+      }
 #pragma unroll
       for (int j = 0; j < NF; ++j) v[j][e] = y[j];
     }
@@ -310,7 +366,7 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
 #pragma unroll
     for (int e = 0; e < N1; ++e) v[j][e] = cmul(v[j][e], s_prop[j * N + t + N2 * e]);
     line_fft<N1, N2, true>(v[j], t, lbuf, s_tw, K);
-    if constexpr (NL != NL_AFTER) {
+    if constexpr (NLM != NL_AFTER) {
       if (valid) {
 #pragma unroll
         for (int e = 0; e < N1; ++e) store_field<NT>(fout[j], idx0 + unsigned(e) * estep, v[j][e]);
@@ -318,7 +374,7 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
     }
   }
 
-  if constexpr (NL == NL_AFTER) {
+  if constexpr (NLM == NL_AFTER) {
     if (args.pre[0] != nullptr && valid) {
 #pragma unroll
       for (int j = 0; j < NF; ++j)
@@ -333,7 +389,13 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
       // (after the transforms a schedule barrier between points keeps
       // fewer registers live than the link above)
       __builtin_amdgcn_sched_barrier(0);
-      rk4_point<NF>(y, co);
+      if constexpr (MAP) {
+        float2 w[3];
+        map_factors<AX, N2>(args.map, plane, xy0, e, wt, w);
+        rk4_point<NF, true>(y, co, w);
+      } else {
+        rk4_point<NF>(y, co);
+      }
 #pragma unroll
       for (int j = 0; j < NF; ++j) v[j][e] = y[j];
     }
@@ -569,6 +631,27 @@ static __global__ void step_tables_batched(const TableArgs* targs) {
 
 // Set a flag when any field value is not finite (the step-size hazard of
 // Sec. 3.2: a too-large dz makes the nonlinear increment blow up).
+// exp(i m(x, y) Psi(z_n + o dz)) for the five distinct stage offsets
+// o = 0, 1/4, 1/2, 3/4, 1 of one step (the first half-step uses 0..2, the
+// second 2..4), from the FP64 map and Psi reduced mod 2 pi in FP64.
+struct MapArgs {
+  const double* map;   // [ny][nx]
+  float2* out;         // [5][ny][nx]
+  unsigned plane;
+  double psi[5];
+};
+
+static __global__ void map_phase_table(MapArgs a) {
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.plane) return;
+  const double m = a.map[i];
+  for (int k = 0; k < 5; ++k) {
+    double sn, cs;
+    sincos(reduce_2pi(m * a.psi[k]), &sn, &cs);
+    a.out[k * a.plane + i] = make_float2(float(cs), float(sn));
+  }
+}
+
 static __global__ void finite_check(const float2* f, long n, int* flag) {
   long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
   const long stride = long(gridDim.x) * blockDim.x;

@@ -14,6 +14,10 @@ struct brahms_plan_s {
   double dz = 0, dx = 1, dy = 1, dt = 1, dk_const = 0;
   std::vector<double> dk;      // per-step profile (empty: constant)
   std::vector<double> phi0;    // Phi_n prefix of the profile
+  std::vector<double> dk_map;     // transverse mismatch map m(x, y), [ny][nx] (empty: none)
+  std::vector<double> map_scale;  // s_n per step (empty: all 1)
+  std::vector<double> psi0;       // Psi_n = dz sum_{l<n} s_l (when map_scale is given)
+  long long table_n0 = 0;         // step index of table row 0
   brahms_field_params fp[3] = {};
   unsigned flags = 0;
   hipStream_t stream = nullptr;
@@ -24,6 +28,7 @@ struct brahms_plan_s {
   int order = 0;               // 0: x, y, tau passes; 1: tau, y, x
   // workspace offsets (bytes)
   size_t off_phi0 = 0, off_dk = 0, off_prop = 0, off_nl = 0, off_flag = 0, ws_size = 0;
+  size_t off_map = 0, off_maptab = 0;   // map (FP64) and its per-step phase table
   // launch timing (diagnostics)
   bool timing = false;
   struct Timed { int kind; hipEvent_t start, stop; };

@@ -80,6 +80,9 @@ class Workload:
     dk_const: float = 0.0
     dk: Optional[np.ndarray] = None
     init: List[np.ndarray] = field(default_factory=list)  # complex64 arrays
+    # transverse mismatch map: dk(x, y, z) = dk_n + s_n dk_map[y, x] in step n
+    dk_map: Optional[np.ndarray] = None
+    dk_map_scale: Optional[np.ndarray] = None
 
     @property
     def points(self) -> int:
@@ -280,3 +283,28 @@ def plane_wave_pulse_sweep(seed: int = 6, count: int = 16, nt: int = 256) -> Lis
                    np.zeros((nt, 1, 1), np.complex64)]
         out.append(wl)
     return out
+
+
+def shg_thermal(seed: int = 7, with_fields: bool = True) -> Workload:
+    """SHG through a crystal with a transverse mismatch map (thermal dephasing
+    plus poling nonuniformity): 128 x 128 x 64, 200 steps, w0 = 16, FWHM 8,
+    xi = 1, dk_0 = 1/L; m(x, y) = -3 exp(-2 r^2 / (2 w0)^2) + U[-0.25, 0.25]
+    per transverse cell (seeded); s_n = 1 - z_n / 2 (the heat load decays
+    along the crystal)."""
+    nx, ny, nt, nz = 128, 128, 64, 200
+    w0, tau0, xi = 16.0, fwhm_to_tau0(8.0), 1.0
+    d_f = xi * w0 ** 2 / 2.0
+    k2 = tau0 ** 2 / 2.0
+    fs = [FieldSpec(kappa=1.0, diffraction=d_f, k2=+k2),
+          FieldSpec(kappa=1.0, diffraction=d_f / 2.0, k2=-k2)]
+    rng = np.random.default_rng(seed)
+    x = centred(nx)[None, :]
+    y = centred(ny)[:, None]
+    m = -3.0 * np.exp(-2.0 * (x ** 2 + y ** 2) / (2.0 * w0) ** 2) + rng.uniform(-0.25, 0.25, (ny, nx))
+    dz = 1.0 / nz
+    scale = 1.0 - 0.5 * dz * np.arange(nz)
+    wl = Workload("shg_thermal", nx, ny, nt, 2, nz, dz, fs, dk_const=1.0, dk_map=m, dk_map_scale=scale)
+    if with_fields:
+        f = focused_pulse(nx, ny, nt, w0, tau0, xi)
+        wl.init = [to_c64(f), np.zeros((nt, ny, nx), np.complex64)]
+    return wl

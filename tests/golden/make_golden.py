@@ -28,7 +28,7 @@ from paper_2609_08384_amd import inputs  # noqa: E402
 from tests.util import oracle_problem, to_torch  # noqa: E402
 
 WORKLOADS = {"sfg128": inputs.sfg128, "opg256": inputs.opg256, "shg_adjoint": inputs.shg_adjoint,
-             "shg32": inputs.shg32}
+             "shg32": inputs.shg32, "shg_thermal": inputs.shg_thermal}
 NSAMPLE = 4096
 
 

@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 from paper_2609_08384_amd import brahms
@@ -145,3 +147,28 @@ def test_diagnostics_host_checks(lib):
     assert lib.brahms_set_snapshots(h, 0, None, None) == brahms.BRAHMS_OK
     assert lib.brahms_set_snapshots(h, -1, None, None) == brahms.BRAHMS_E_INVALID_ARG
     lib.brahms_plan_destroy(h)
+
+
+def test_dk_map_host_checks(lib):
+    p = brahms.Params(dz=0.1, fields=[brahms.FieldParams(kappa=1.0)] * 2, dk_map=np.zeros((4, 8)),
+                      dk_map_scale=[1.0] * 5)
+    c, keep = brahms._params_c(p, 2)
+    st, h = _create(lib, 8, 4, 8, 2, c)
+    assert st == brahms.BRAHMS_OK
+    size = ctypes.c_size_t()
+    assert lib.brahms_adjoint_workspace_size(h, 10, 5, ctypes.byref(size)) == brahms.BRAHMS_E_UNSUPPORTED
+    lib.brahms_plan_destroy(h)
+    # a scale profile needs a map; non-finite map entries are refused
+    c.dk_map = None
+    assert _create(lib, 8, 4, 8, 2, c)[0] == brahms.BRAHMS_E_INVALID_ARG
+    p.dk_map = np.full((4, 8), np.nan)
+    c, keep = brahms._params_c(p, 2)
+    assert _create(lib, 8, 4, 8, 2, c)[0] == brahms.BRAHMS_E_INVALID_ARG
+    # batches refuse maps
+    p.dk_map = np.zeros((4, 8))
+    c, keep = brahms._params_c(p, 2)
+    shapes = (ctypes.c_int * 4)(8, 4, 8, 2)
+    params = (brahms.ParamsC * 1)(c)
+    steps = (ctypes.c_int * 1)(3)
+    hb = ctypes.c_void_p()
+    assert lib.brahms_batch_create(1, shapes, params, steps, None, ctypes.byref(hb)) == brahms.BRAHMS_E_UNSUPPORTED

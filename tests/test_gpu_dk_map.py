@@ -1,0 +1,99 @@
+"""Transverse phase-mismatch map dk(x, y, z) = dk_n + s_n m(x, y) (the
+spatially varying phase matching of Sec. 4.1) against the oracle, in both
+pass orders, with two and three fields, ragged tiles, per-step profiles."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ssfm
+from paper_2609_08384_amd import brahms, inputs
+from tests.util import oracle_problem, rel_l2, to_torch
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _case(nf, shape, nz, seed, profile, scale):
+    rng = np.random.default_rng(seed)
+    nx, ny, nt = shape
+    fs = [inputs.FieldSpec(kappa=1.5 - 0.3 * j, diffraction=float(rng.uniform(0.3, 1.5)),
+                           tan_rho=float(rng.uniform(-0.4, 0.4)), delay=float(rng.uniform(-0.8, 0.8)),
+                           k2=float(rng.uniform(-1.5, 1.5))) for j in range(nf)]
+    dk = (2.0 + rng.standard_normal(nz)) if profile else None
+    wl = inputs.Workload("map", nx, ny, nt, nf, nz, 1.0 / nz, fs, dk_const=-1.5, dk=dk,
+                         dk_map=rng.uniform(-12.0, 12.0, (ny, nx)),
+                         dk_map_scale=rng.uniform(0.3, 1.7, nz) if scale else None)
+    wl.init = inputs.random_fields(rng, nf, nx, ny, nt, scale=0.8, smooth=min(nx, ny, nt) / 2.0)
+    return wl
+
+
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("nf,shape,profile,scale", [
+    (2, (32, 16, 8), False, False), (3, (32, 16, 8), True, True), (2, (16, 32, 32), True, False),
+    (3, (64, 8, 16), False, True), (2, (96, 4, 4), False, True), (3, (8, 96, 32), True, True)])
+def test_map_matches_oracle(nf, shape, profile, scale, order):
+    wl = _case(nf, shape, 14, sum(shape) + nf, profile, scale)
+    out = brahms.run_workload(wl, device=DEV, pass_order=order)
+    ref = ssfm.propagate([to_torch(a) for a in wl.init], oracle_problem(wl), wl.nz)
+    for a, r in zip(out, ref):
+        assert rel_l2(a.cpu().numpy(), r.numpy()) < 1e-5
+
+
+def test_map_resumes_across_calls():
+    """The per-step phase tables follow the absolute step index: 5 + 9 steps
+    equal 14 steps bit for bit."""
+    wl = _case(2, (32, 16, 8), 14, 3, True, True)
+    whole = brahms.run_workload(wl, device=DEV)
+    fields = [torch.from_numpy(a).to(DEV) for a in wl.init]
+    plan = brahms.Plan(wl.nx, wl.ny, wl.nt, wl.nf, brahms.params_from_workload(wl)).bind(fields)
+    plan.step(5)
+    plan.step(9)
+    torch.cuda.synchronize()
+    for a, b in zip(fields, whole):
+        assert torch.equal(a, b)
+    plan.destroy()
+
+
+def test_columns_decouple_without_linear_terms():
+    """kappa_F = 0 and no linear terms: each (x, y) column is undepleted SHG
+    with its own mismatch, S(L) in closed form (as pinned for the oracle)."""
+    nx, ny, nt, nz = 8, 4, 2, 100
+    rng = np.random.default_rng(5)
+    m = rng.uniform(-8, 8, (ny, nx))
+    s = rng.uniform(0.2, 1.5, nz)
+    dk, ks, f0 = 1.7, 1.3, 0.9 - 0.2j
+    wl = inputs.Workload("cols", nx, ny, nt, 2, nz, 1.0 / nz,
+                         [inputs.FieldSpec(kappa=0.0), inputs.FieldSpec(kappa=ks)],
+                         dk_const=dk, dk_map=m, dk_map_scale=s)
+    wl.init = [np.full((nt, ny, nx), f0, np.complex64), np.zeros((nt, ny, nx), np.complex64)]
+    out = brahms.run_workload(wl, device=DEV)
+    f0 = complex(wl.init[0].reshape(-1)[0])
+    dz = 1.0 / nz
+    psi = np.concatenate([[0.0], np.cumsum(s * dz)])
+    want = np.zeros((ny, nx), complex)
+    for n in range(nz):
+        k = dk + s[n] * m
+        want += np.exp(-1j * (dk * n * dz + m * psi[n])) * (1 - np.exp(-1j * k * dz)) / (1j * k)
+    want *= 1j * ks * f0 ** 2
+    got = out[1].cpu().numpy().astype(np.complex128)
+    # FP32 accumulation of nz increments of the stored state (coherent bound)
+    bound = nz * 2.0 ** -24 * np.sqrt(2) * np.abs(want).max() * 2
+    assert np.abs(got - want[None]).max() < bound
+
+
+def test_thermal_workload_vs_oracle():
+    """SHG 128 x 128 x 64 with a thermal/poling mismatch map, 200 steps,
+    against the oracle's reference data: <= 2e-5 per field."""
+    path = os.path.join(GOLDEN, "shg_thermal_200.npz")
+    if not os.path.exists(path):
+        pytest.skip("reference data not generated")
+    g = np.load(path)
+    wl = inputs.shg_thermal()
+    out = [f.cpu().numpy().reshape(-1) for f in brahms.run_workload(wl, device=DEV)]
+    idx = g["uniform_idx"]
+    for j in range(2):
+        assert rel_l2(out[j][idx], g[f"f{j}_uniform"]) < 2e-5, j
+        assert rel_l2(out[j][g[f"f{j}_top_idx"]], g[f"f{j}_top"]) < 2e-5, j

@@ -11,8 +11,9 @@ def oracle_problem(wl: inputs.Workload) -> ssfm.Problem:
                                tan_rho=f.tan_rho, delay=f.delay, k2=f.k2,
                                k3=f.k3, alpha=f.alpha) for f in wl.fields]
     dk = None if wl.dk is None else [float(v) for v in wl.dk]
+    scale = None if wl.dk_map_scale is None else [float(v) for v in wl.dk_map_scale]
     return ssfm.Problem(wl.nx, wl.ny, wl.nt, wl.nf, wl.dz, fields,
-                        dk_const=wl.dk_const, dk=dk)
+                        dk_const=wl.dk_const, dk=dk, dk_map=wl.dk_map, dk_map_scale=scale)
 
 
 def to_torch(a) -> torch.Tensor:
