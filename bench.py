@@ -105,6 +105,115 @@ def adjoint_ratio(dev, reps=3):
             "forward_ms": fwd * 1e3, "forward_plus_adjoint_ms": adj * 1e3, "ratio": adj / fwd}
 
 
+def _median_time(fn, reps=3):
+    fn()
+    return sorted(fn() for _ in range(reps))[reps // 2]
+
+
+def reduced_dims(dev):
+    """Focusing sweep of 99 CW problems (128 x 128 x 1, 200 steps each; the
+    Boyd-Kleinman study of Sec. 5.2) as one batch, against the same problems
+    propagated one after another with plain plans."""
+    import torch
+    from paper_2609_08384_amd import brahms, inputs
+    wls = inputs.bk_sweep()
+    init = [[torch.from_numpy(a).to(dev) for a in w.init] for w in wls]
+    fields = [[a.clone() for a in fs] for fs in init]
+    batch = brahms.Batch([(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls])
+    batch.bind(fields)
+
+    def run_batch():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.run()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+    t_batch = _median_time(run_batch)
+    batch.destroy()
+    plans = [brahms.Plan(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w)).bind(fs)
+             for w, fs in zip(wls, fields)]
+
+    def run_seq():
+        for pl in plans:
+            pl.set_z(0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for pl, w in zip(plans, wls):
+            pl.step(w.nz)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+    t_seq = _median_time(run_seq)
+    for pl in plans:
+        pl.destroy()
+    work = sum(w.points * w.nz for w in wls)
+    return {"workload": "99 CW SHG problems 128x128x1 (xi 2..4 x dk L -4..-2.4), 200 steps",
+            "batched_ms": t_batch * 1e3, "sequential_ms": t_seq * 1e3, "speedup": t_seq / t_batch,
+            "batched_rate": work / t_batch}
+
+
+def diagnostics_cost(dev, wl, steps=100, every=10):
+    """One diagnostics record of the benchmark grid (event-timed, bytes read
+    = 8 nf per point) and the cost of recording every `every` steps."""
+    import torch
+    from paper_2609_08384_amd import brahms
+    fields = [torch.from_numpy(a).to(dev) for a in wl.init]
+    plan = brahms.Plan(wl.nx, wl.ny, wl.nt, wl.nf, brahms.params_from_workload(wl)).bind(fields)
+    rec = torch.empty(plan.record_size(), dtype=torch.float64, device=dev)
+    plan.diagnose_into(rec)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        plan.diagnose_into(rec)
+    ev1.record()
+    torch.cuda.synchronize()
+    rec_ms = ev0.elapsed_time(ev1) / 10
+
+    def run(monitor):
+        plan.set_z(0.0)
+        plan.set_monitor(every if monitor else 0, steps // every)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.step(steps)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+    plain = _median_time(lambda: run(False))
+    mon = _median_time(lambda: run(True))
+    plan.destroy()
+    nbytes = 8 * wl.nf * wl.points
+    return {"record_ms": rec_ms, "record_GBps": nbytes / (rec_ms * 1e-3) / 1e9,
+            "steps": steps, "every": every, "plain_ms": plain * 1e3, "monitored_ms": mon * 1e3,
+            "overhead": mon / plain - 1.0}
+
+
+def dk_map_cost(dev):
+    """SHG 128 x 128 x 64 with a transverse mismatch map (200 steps) against
+    the same problem without the map."""
+    import torch
+    from paper_2609_08384_amd import brahms, inputs
+    wl = inputs.shg_thermal()
+    out = {}
+    for name, with_map in (("with_map_ms", True), ("without_map_ms", False)):
+        prm = brahms.params_from_workload(wl)
+        if not with_map:
+            prm.dk_map, prm.dk_map_scale = None, None
+        fields = [torch.from_numpy(a).to(dev) for a in wl.init]
+        plan = brahms.Plan(wl.nx, wl.ny, wl.nt, wl.nf, prm).bind(fields)
+
+        def run():
+            plan.set_z(0.0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.step(wl.nz)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0
+        out[name] = _median_time(run) * 1e3
+        plan.destroy()
+    out["workload"] = "shg_thermal: SHG 128x128x64, 200 steps, transverse dk map"
+    out["overhead"] = out["with_map_ms"] / out["without_map_ms"] - 1.0
+    return out
+
+
 def batch_ratio(dev):
     """Seeded SHG sweep (64 problems over 64^3, 96x96x64, 128x128x64 and
     128x128x256 grids, dk L in [-6, 6], xi in [0.1, 10], 200-600 steps): one
@@ -308,6 +417,9 @@ def main():
     if not args.no_extras:
         extras["adjoint"] = adjoint_ratio(dev)
         extras["batch"] = batch_ratio(dev)
+        extras["reduced_dims"] = reduced_dims(dev)
+        extras["diagnostics"] = diagnostics_cost(dev, wl)
+        extras["dk_map"] = dk_map_cost(dev)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -322,10 +322,17 @@ class Plan:
                 "energy": rec[:, 1 + nf * nt:1 + nf * (nt + 1)],
                 "manley_rowe": rec[:, 1 + nf * (nt + 1):1 + nf * (nt + 1) + (3 if nf == 3 else 1)]}
 
+    def diagnose_into(self, rec: torch.Tensor):
+        """Write one record of the fields now into the float64 device tensor
+        `rec` (record_size() entries), asynchronously."""
+        if rec.dtype != torch.float64 or not rec.is_cuda or rec.numel() < self.record_size():
+            raise ValueError("rec must be a float64 CUDA tensor of record_size() entries")
+        _check(self._lib.brahms_diagnose(self._h, ctypes.c_void_p(rec.data_ptr())), "brahms_diagnose")
+
     def diagnose(self) -> dict:
         """Power traces, energies and Manley-Rowe values of the fields now."""
         rec = torch.empty(self.record_size(), dtype=torch.float64, device=self.fields[0].device)
-        _check(self._lib.brahms_diagnose(self._h, ctypes.c_void_p(rec.data_ptr())), "brahms_diagnose")
+        self.diagnose_into(rec)
         return {k: v[0] for k, v in self.split_records(rec).items()}
 
     def set_monitor(self, every: int, capacity: int = 0):

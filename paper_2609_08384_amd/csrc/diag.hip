@@ -12,10 +12,13 @@
 //                            then NaN, NaN (NaN wherever a kappa is 0)
 // Every sum runs in FP64 in a fixed order, so records are reproducible bit
 // for bit.  Reading the fields costs 8 nf bytes per grid point per record.
+// The slice sums are split into fixed chunks (partials in the plan
+// workspace) so that the reduction fills the chip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <vector>
 
 #include "../../include/brahms.h"
@@ -32,27 +35,62 @@ struct FieldPtrs {
   const float2* f[3];
 };
 
-// One block per (tau slice, field): the slice's |A|^2 summed by a fixed
-// thread -> element assignment and a fixed tree.
-__global__ __launch_bounds__(kDiagBlock) void power_traces(FieldPtrs fp, int nx, int ny, int nt,
-                                                           double cell_xy, double* rec) {
-  const int tau = blockIdx.x;
-  const int j = blockIdx.y;
-  const long plane = long(nx) * ny;
+// Partial sums of |A|^2: block (c, tau, j) sums chunk c of the (tau, j)
+// slice with a fixed thread -> element assignment (two values per 16-byte
+// load, four independent accumulators) and a fixed tree; part[(j nt + tau)
+// nchunk + c] receives the block's sum.
+__global__ __launch_bounds__(kDiagBlock) void power_partials(FieldPtrs fp, long plane, int nt,
+                                                             long chunk, int nchunk, int pairs,
+                                                             double* part) {
+  const int c = blockIdx.x;
+  const int tau = blockIdx.y;
+  const int j = blockIdx.z;
   const float2* s = fp.f[j] + long(tau) * plane;
-  double acc = 0.0;
-  for (long i = threadIdx.x; i < plane; i += kDiagBlock) {
-    const float2 v = s[i];
-    acc = fma(double(v.x), double(v.x), fma(double(v.y), double(v.y), acc));
+  const long lo = long(c) * chunk;
+  const long hi = lo + chunk < plane ? lo + chunk : plane;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  long i = lo + 2 * long(threadIdx.x);
+  if (pairs) {
+    // pairs of values per 16-byte load (plane and chunk even, fields 16-byte
+    // aligned); 2 * kDiagBlock values per sweep
+    const float4* s4 = reinterpret_cast<const float4*>(s);
+    for (; i + 6 * kDiagBlock + 1 < hi; i += 8 * kDiagBlock) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float4 v = s4[(i + 2 * u * kDiagBlock) / 2];
+        acc[u] = fma(double(v.x), double(v.x), fma(double(v.y), double(v.y), acc[u]));
+        acc[u] = fma(double(v.z), double(v.z), fma(double(v.w), double(v.w), acc[u]));
+      }
+    }
+    for (; i + 1 < hi; i += 2 * kDiagBlock) {
+      const float4 v = s4[i / 2];
+      acc[0] = fma(double(v.x), double(v.x), fma(double(v.y), double(v.y), acc[0]));
+      acc[0] = fma(double(v.z), double(v.z), fma(double(v.w), double(v.w), acc[0]));
+    }
+  } else {
+    for (i = lo + threadIdx.x; i < hi; i += kDiagBlock) {
+      const float2 v = s[i];
+      acc[0] = fma(double(v.x), double(v.x), fma(double(v.y), double(v.y), acc[0]));
+    }
   }
   __shared__ double red[kDiagBlock];
-  red[threadIdx.x] = acc;
+  red[threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   __syncthreads();
   for (int w = kDiagBlock / 2; w > 0; w >>= 1) {
     if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) rec[1 + long(j) * nt + tau] = red[0] * cell_xy;
+  if (threadIdx.x == 0) part[(long(j) * nt + tau) * nchunk + c] = red[0];
+}
+
+// P_j(tau) from the partial sums, in chunk order.
+__global__ void power_traces(const double* part, int nf, int nt, int nchunk, double cell_xy,
+                             double* rec) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nf * nt) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[long(k) * nchunk + c];
+  rec[1 + k] = s * cell_xy;
 }
 
 struct Kappas {
@@ -90,11 +128,33 @@ __global__ void copy_state(float2* dst, const float2* src, long n) {
     dst[i] = src[i];
 }
 
+// Chunks per slice: about 4096 blocks in all, at most kDiagChunks (the
+// partial sums live in the plan workspace).
+int chunks_for(const brahms_plan_s& p) {
+  const long plane = long(p.nx) * p.ny;
+  const long slices = long(p.nt) * p.nf;
+  long want = (4096 + slices - 1) / slices;              // about 4096 blocks in all
+  want = std::min<long>(want, std::max<long>(1, plane / (8 * kDiagBlock)));
+  return int(std::max<long>(1, std::min<long>(want, brahms::detail::kDiagChunks)));
+}
+
 brahms_status write_record(brahms_plan_s& p, long long step, double* rec) {
   FieldPtrs fp{};
   for (int j = 0; j < 3; ++j) fp.f[j] = p.fields[j];
-  hipLaunchKernelGGL(power_traces, dim3(unsigned(p.nt), unsigned(p.nf)), dim3(kDiagBlock), 0,
-                     p.stream, fp, p.nx, p.ny, p.nt, p.dx * p.dy, rec);
+  const long plane = long(p.nx) * p.ny;
+  const int nchunk = chunks_for(p);
+  long chunk = (plane + nchunk - 1) / nchunk;
+  chunk += chunk & 1;                                    // keep chunks on 16-byte boundaries
+  double* part = reinterpret_cast<double*>(p.ws + p.off_diag);
+  int pairs = (plane % 2 == 0) ? 1 : 0;
+  for (int j = 0; j < p.nf; ++j)
+    if (reinterpret_cast<uintptr_t>(p.fields[j]) % 16 != 0) pairs = 0;
+  hipLaunchKernelGGL(power_partials, dim3(unsigned(nchunk), unsigned(p.nt), unsigned(p.nf)),
+                     dim3(kDiagBlock), 0, p.stream, fp, plane, p.nt, chunk, nchunk, pairs, part);
+  HIP_TRY(hipGetLastError());
+  const int nk = p.nf * p.nt;
+  hipLaunchKernelGGL(power_traces, dim3(unsigned((nk + 255) / 256)), dim3(256), 0, p.stream, part,
+                     p.nf, p.nt, nchunk, p.dx * p.dy, rec);
   HIP_TRY(hipGetLastError());
   Kappas ka{};
   for (int j = 0; j < p.nf; ++j) ka.k[j] = p.fp[j].kappa;

@@ -23,6 +23,7 @@ using namespace brahms;
 using brahms::detail::fail;
 using brahms::detail::kAlign;
 using brahms::detail::kChunk;
+using brahms::detail::kDiagChunks;
 using brahms::detail::align_up;
 
 namespace brahms {
@@ -153,11 +154,21 @@ void layout(brahms_plan_s& p) {
   off = align_up(off + sizeof(float2) * size_t(kChunk) * 2 * p.nf * kNlCoef);
   p.off_flag = off;
   off = align_up(off + sizeof(int));
+  p.off_diag = off;
+  off = align_up(off + sizeof(double) * size_t(kDiagChunks) * p.nf * p.nt);
   if (!p.dk_map.empty()) {
+    // phase tables of a whole 64-step chunk when they take at most 64 MB,
+    // else one step at a time
+    const size_t row = sizeof(float2) * 5 * p.dk_map.size();
+    p.map_rows = row * kChunk <= (size_t(64) << 20) ? kChunk : 1;
     p.off_map = off;
     off = align_up(off + sizeof(double) * p.dk_map.size());
     p.off_maptab = off;
-    off = align_up(off + sizeof(float2) * 5 * p.dk_map.size());
+    off = align_up(off + row * size_t(p.map_rows));
+    p.off_psi0 = off;
+    off = align_up(off + sizeof(double) * (p.map_scale.size() + 1));
+    p.off_scale = off;
+    off = align_up(off + sizeof(double) * (p.map_scale.size() + 1));
   }
   p.ws_size = off;
 }
@@ -214,6 +225,10 @@ int pass_axis(const brahms_plan_s& p, int k) {
   return p.order == 0 ? int(AX_T) : int(AX_X);
 }
 
+namespace {
+brahms_status map_table(brahms_plan_s& p, long long n0, int count);
+}  // namespace
+
 brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count) {
   const int per_field = p.nx + p.ny + p.nt;
   TableArgs ta{};
@@ -236,6 +251,8 @@ brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count) {
   if (brahms_status st = timing_start(p, 3)) return st;
   hipLaunchKernelGGL(step_tables, dim3(unsigned((total + 255) / 256)), dim3(256), 0, p.stream, ta);
   HIP_TRY(hipGetLastError());
+  if (!p.dk_map.empty() && p.map_rows == kChunk)
+    if (brahms_status st = map_table(p, n0, count)) return st;
   if (timed)
     if (brahms_status st = timing_stop(p)) return st;
   return BRAHMS_OK;
@@ -266,16 +283,19 @@ brahms_status timed_dispatch(brahms_plan_s& p, int ax, int nlmode, const PassArg
   return BRAHMS_OK;
 }
 
-// The transverse phase factors of step n at its five stage offsets.
-brahms_status map_table(brahms_plan_s& p, long long n) {
+// The transverse phase factors of steps n0 .. n0 + count - 1 at their five
+// stage offsets, into table rows 0 .. count - 1.
+brahms_status map_table(brahms_plan_s& p, long long n0, int count) {
   MapArgs m{};
   m.map = reinterpret_cast<const double*>(p.ws + p.off_map);
+  m.psi0 = p.map_scale.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_psi0);
+  m.scale = p.map_scale.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_scale);
   m.out = reinterpret_cast<float2*>(p.ws + p.off_maptab);
   m.plane = unsigned(p.dk_map.size());
-  const double psi_n = p.map_scale.empty() ? double(n) * p.dz : p.psi0[size_t(n)];
-  const double s_n = p.map_scale.empty() ? 1.0 : p.map_scale[size_t(n)];
-  for (int k = 0; k < 5; ++k) m.psi[k] = psi_n + s_n * (0.25 * k) * p.dz;
-  hipLaunchKernelGGL(map_phase_table, dim3((m.plane + 255) / 256), dim3(256), 0, p.stream, m);
+  m.n0 = n0;
+  m.dz = p.dz;
+  hipLaunchKernelGGL(map_phase_table, dim3((m.plane + 255) / 256, unsigned(count)), dim3(256), 0,
+                     p.stream, m);
   HIP_TRY(hipGetLastError());
   return BRAHMS_OK;
 }
@@ -284,8 +304,9 @@ brahms_status map_table(brahms_plan_s& p, long long n) {
 
 brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io) {
   const bool map = !p.dk_map.empty();
-  if (map)
-    if (brahms_status st = map_table(p, p.table_n0 + row)) return st;
+  if (map && p.map_rows == 1)
+    if (brahms_status st = map_table(p, p.table_n0 + row, 1)) return st;
+  const size_t map_row = map ? size_t(p.map_rows == 1 ? 0 : row) * 5 * p.dk_map.size() : 0;
   // pass order of the step: the first pass carries the first RK4 half-step,
   // the last pass the second one (the axis operators commute)
   for (int k = 0; k < 3; ++k) {
@@ -294,7 +315,7 @@ brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io) {
     PassArgs a = pass_args(p, row, ax);
     if (map && nlmode != NL_NONE) {
       nlmode |= NL_MAP;
-      a.map = reinterpret_cast<const float2*>(p.ws + p.off_maptab) +
+      a.map = reinterpret_cast<const float2*>(p.ws + p.off_maptab) + map_row +
               (k == 0 ? 0 : 2) * p.dk_map.size();
     }
     for (int j = 0; j < 3; ++j) {
@@ -446,6 +467,13 @@ brahms_status brahms_plan_bind(brahms_plan plan, void* const* fields, void* work
   if (!plan->dk_map.empty()) {
     HIP_TRY(hipMemcpyAsync(plan->ws + plan->off_map, plan->dk_map.data(),
                            sizeof(double) * plan->dk_map.size(), hipMemcpyHostToDevice, plan->stream));
+    if (!plan->map_scale.empty()) {
+      HIP_TRY(hipMemcpyAsync(plan->ws + plan->off_psi0, plan->psi0.data(),
+                             sizeof(double) * plan->psi0.size(), hipMemcpyHostToDevice, plan->stream));
+      HIP_TRY(hipMemcpyAsync(plan->ws + plan->off_scale, plan->map_scale.data(),
+                             sizeof(double) * plan->map_scale.size(), hipMemcpyHostToDevice,
+                             plan->stream));
+    }
     HIP_TRY(hipStreamSynchronize(plan->stream));
   }
   plan->bound = true;

@@ -632,23 +632,32 @@ static __global__ void step_tables_batched(const TableArgs* targs) {
 // Set a flag when any field value is not finite (the step-size hazard of
 // Sec. 3.2: a too-large dz makes the nonlinear increment blow up).
 // exp(i m(x, y) Psi(z_n + o dz)) for the five distinct stage offsets
-// o = 0, 1/4, 1/2, 3/4, 1 of one step (the first half-step uses 0..2, the
-// second 2..4), from the FP64 map and Psi reduced mod 2 pi in FP64.
+// o = 0, 1/4, 1/2, 3/4, 1 of steps n0 .. n0 + count - 1 (the first half-step
+// uses offsets 0..2, the second 2..4), from the FP64 map and Psi reduced
+// mod 2 pi in FP64.  Psi(z_n + o dz) = Psi_n + s_n o dz with Psi_n = psi0[n]
+// and s_n = scale[n], or n dz and 1 without a scale profile.
 struct MapArgs {
-  const double* map;   // [ny][nx]
-  float2* out;         // [5][ny][nx]
+  const double* map;    // [ny][nx]
+  const double* psi0;   // Psi_n prefix (NULL: no scale profile)
+  const double* scale;  // s_n (NULL: no scale profile)
+  float2* out;          // [count][5][ny][nx]
   unsigned plane;
-  double psi[5];
+  long long n0;
+  double dz;
 };
 
 static __global__ void map_phase_table(MapArgs a) {
   const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.plane) return;
+  const long long n = a.n0 + blockIdx.y;
+  const double psi_n = a.psi0 != nullptr ? a.psi0[n] : double(n) * a.dz;
+  const double s_n = a.scale != nullptr ? a.scale[n] : 1.0;
   const double m = a.map[i];
+  float2* out = a.out + size_t(blockIdx.y) * 5 * a.plane;
   for (int k = 0; k < 5; ++k) {
     double sn, cs;
-    sincos(reduce_2pi(m * a.psi[k]), &sn, &cs);
-    a.out[k * a.plane + i] = make_float2(float(cs), float(sn));
+    sincos(reduce_2pi(m * (psi_n + s_n * (0.25 * k) * a.dz)), &sn, &cs);
+    out[k * a.plane + i] = make_float2(float(cs), float(sn));
   }
 }
 

@@ -28,7 +28,10 @@ struct brahms_plan_s {
   int order = 0;               // 0: x, y, tau passes; 1: tau, y, x
   // workspace offsets (bytes)
   size_t off_phi0 = 0, off_dk = 0, off_prop = 0, off_nl = 0, off_flag = 0, ws_size = 0;
-  size_t off_map = 0, off_maptab = 0;   // map (FP64) and its per-step phase table
+  size_t off_map = 0, off_maptab = 0;   // map (FP64) and its per-step phase tables
+  size_t off_psi0 = 0, off_scale = 0;   // Psi_n prefix and s_n (with a scale profile)
+  int map_rows = 0;                     // steps per phase-table fill (kChunk or 1)
+  size_t off_diag = 0;                  // partial sums of the diagnostics
   // launch timing (diagnostics)
   bool timing = false;
   struct Timed { int kind; hipEvent_t start, stop; };
@@ -53,6 +56,7 @@ namespace detail {
 
 constexpr int kChunk = 64;     // steps per table refill (rows in the workspace)
 constexpr size_t kAlign = 256;
+constexpr int kDiagChunks = 64;  // chunks per (tau, field) slice in diagnostics
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 

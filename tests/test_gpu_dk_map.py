@@ -33,7 +33,9 @@ def _case(nf, shape, nz, seed, profile, scale):
 @pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("nf,shape,profile,scale", [
     (2, (32, 16, 8), False, False), (3, (32, 16, 8), True, True), (2, (16, 32, 32), True, False),
-    (3, (64, 8, 16), False, True), (2, (96, 4, 4), False, True), (3, (8, 96, 32), True, True)])
+    (3, (64, 8, 16), False, True), (2, (96, 4, 4), False, True), (3, (8, 96, 32), True, True),
+    # a plane of 32768 cells: phase tables filled one step at a time
+    (2, (256, 128, 2), True, True)])
 def test_map_matches_oracle(nf, shape, profile, scale, order):
     wl = _case(nf, shape, 14, sum(shape) + nf, profile, scale)
     out = brahms.run_workload(wl, device=DEV, pass_order=order)
