@@ -218,7 +218,7 @@ def batch_ratio(dev):
     """Seeded SHG sweep (64 problems over 64^3, 96x96x64, 128x128x64 and
     128x128x256 grids, dk L in [-6, 6], xi in [0.1, 10], 200-600 steps): one
     batched run (autotuned, hipGraph) against the same 64 problems propagated
-    one after another with plain plans (tuned pass order)."""
+    one after another with plain plans (tuned pass order); medians of 3."""
     import torch
     from paper_2609_08384_amd import autotune, brahms, inputs
     wls = inputs.shg_sweep(seed=4, count=64)
@@ -236,28 +236,37 @@ def batch_ratio(dev):
     tuned = autotune.tune_batch(batch, dev)
     batch.bind(fields)
     batch.run()                      # builds the graph
-    reset()
-    t0 = time.perf_counter()
-    batch.run()
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
+
+    def run_batch():
+        reset()
+        t0 = time.perf_counter()
+        batch.run()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+    t_batch = sorted(run_batch() for _ in range(3))[1]
     groups = batch.groups()
     batch.destroy()
 
+    # the sequential solves each take the order that is fastest for a plain
+    # solve of their shape
     plans = []
-    for w, fs, o in zip(wls, fields, tuned["pass_orders"]):
+    for w, fs in zip(wls, fields):
         pl = brahms.Plan(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w))
-        pl.set_schedule(o)
+        autotune.apply(pl, dev)
         plans.append(pl.bind(fs))
     for pl in plans:                 # first launches of every kernel variant
         pl.step(2)
         pl.set_z(0.0)
-    reset()
-    t0 = time.perf_counter()
-    for pl, w in zip(plans, wls):
-        pl.propagate(w.nz * w.dz)
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
+    def run_seq():
+        for pl in plans:
+            pl.set_z(0.0)
+        reset()
+        t0 = time.perf_counter()
+        for pl, w in zip(plans, wls):
+            pl.propagate(w.nz * w.dz)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+    t_seq = sorted(run_seq() for _ in range(3))[1]
     for pl in plans:
         pl.destroy()
     work = sum(w.points * w.nz for w in wls)
@@ -266,7 +275,8 @@ def batch_ratio(dev):
             "grid_point_steps": work, "batched_ms": t_batch * 1e3, "sequential_ms": t_seq * 1e3,
             "speedup": t_seq / t_batch, "batched_rate": work / t_batch,
             "sequential_rate": work / t_seq, "launch_groups": groups,
-            "group_max": tuned["group_max"]}
+            "group_max": tuned["group_max"], "batch_orders": tuned["orders"],
+            "tuner_probe_ms": tuned["probe_ms"]}
 
 
 # Sources that define the pass kernels and their launch configuration: the

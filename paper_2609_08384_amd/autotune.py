@@ -115,12 +115,16 @@ GROUP_CANDIDATES = (0, 1 << 30)   # cache-budget groups, or every same-shape pro
 
 
 def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64) -> dict:
-    """Pick pass orders (per shape, via tune) and the launch-group size of a
-    batch by timing a copy of it on scratch fields with at most max_steps
-    steps per problem; applies the choice to `batch`."""
-    orders = []
-    for (nx, ny, nt, nf, prm, _) in batch.problems:
-        orders.append(tune(nx, ny, nt, nf, prm, device)["pass_order"])
+    """Pick the pass orders and the launch-group size of a batch by timing a
+    copy of it on scratch fields with at most max_steps steps per problem:
+    group sizes GROUP_CANDIDATES, each with the per-shape orders of `tune`
+    (the fastest for a plain solve) and with one order for every problem
+    (concurrent groups compete for the chip, so the best order alone need not
+    be the best order together).  Applies the choice to `batch`."""
+    tuned = [tune(nx, ny, nt, nf, prm, device)["pass_order"]
+             for (nx, ny, nt, nf, prm, _) in batch.problems]
+    n = len(batch.problems)
+    order_sets = {"per_shape": tuned, "all_0": [0] * n, "all_1": [1] * n}
     probe = brahms.Batch([(nx, ny, nt, nf, prm, min(ns, max_steps))
                           for (nx, ny, nt, nf, prm, ns) in batch.problems])
     gen = torch.Generator(device="cpu").manual_seed(7)
@@ -128,18 +132,19 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64) -> d
                for _ in range(nf)] for (nx, ny, nt, nf, _, _) in batch.problems]
     times = []
     for gm in GROUP_CANDIDATES:
-        probe.set_schedule(gm, orders)
-        probe.bind(fields)
-        probe.run()
-        torch.cuda.synchronize(device)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        probe.run()
-        ev1.record()
-        torch.cuda.synchronize(device)
-        times.append((ev0.elapsed_time(ev1), gm))
+        for name, orders in order_sets.items():
+            probe.set_schedule(gm, orders)
+            probe.bind(fields)
+            probe.run()
+            torch.cuda.synchronize(device)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            probe.run()
+            ev1.record()
+            torch.cuda.synchronize(device)
+            times.append((ev0.elapsed_time(ev1), gm, name))
     probe.destroy()
-    best_ms, best = min(times)
-    batch.set_schedule(best, orders)
-    return {"group_max": best, "pass_orders": orders,
-            "probe_ms": {str(g): t for t, g in times}}
+    best_ms, best_gm, best_name = min(times)
+    batch.set_schedule(best_gm, order_sets[best_name])
+    return {"group_max": best_gm, "pass_orders": order_sets[best_name], "orders": best_name,
+            "probe_ms": {f"{g}/{o}": t for t, g, o in times}}
