@@ -91,3 +91,38 @@ def test_sweep_instances_match_oracle():
         for a, r in zip(fs, ref):
             assert rel_l2(a.cpu().numpy(), r.numpy()) < 2e-5
     batch.destroy()
+
+
+def test_whole_sweep_matches_oracle_and_single_runs():
+    """All 64 problems of the seeded SHG sweep (the batched benchmark
+    workload) in one autotuned batch: every problem within 2e-5 of the
+    oracle's reference data (sampled values, power traces, energies), and
+    bitwise equal to the same problem propagated alone with the same pass
+    order."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "shg_sweep_64.npz")
+    if not os.path.exists(path):
+        pytest.skip("reference data not generated")
+    g = np.load(path)
+    from paper_2609_08384_amd import autotune
+    wls = inputs.shg_sweep()
+    probs = [(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls]
+    batch = brahms.Batch(probs)
+    tuned = autotune.tune_batch(batch, DEV)
+    fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
+    batch.bind(fields)
+    batch.run()
+    torch.cuda.synchronize()
+    batch.destroy()
+    for i, (w, fs, o) in enumerate(zip(wls, fields, tuned["pass_orders"])):
+        key = f"i{i:02d}_"
+        assert list(g[key + "shape"]) == [w.nx, w.ny, w.nt] and int(g[key + "nz"]) == w.nz
+        for j, f in enumerate(fs):
+            flat = f.cpu().numpy().reshape(-1)
+            assert rel_l2(flat[g[key + "uniform_idx"]], g[key + f"f{j}_uniform"]) < 2e-5, (i, j)
+            assert rel_l2(flat[g[key + f"f{j}_top_idx"]], g[key + f"f{j}_top"]) < 2e-5, (i, j)
+            p = (np.abs(f.cpu().numpy().astype(np.complex128)) ** 2).sum(axis=(1, 2))
+            assert rel_l2(p, g[key + f"f{j}_power"]) < 4e-5, (i, j)
+        alone = brahms.run_workload(w, device=DEV, pass_order=o)
+        for a, b in zip(fs, alone):
+            assert torch.equal(a, b), i
