@@ -148,8 +148,9 @@ void launch_group_pass(int axis, int nl, const brahms_batch_s::Group& g, hipStre
     const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), m);
     launch_batched_nl<N1, N2, AX_X>(g.nf, nl, lines % G::LPB == 0, grid, st, d, step);
   } else if (axis == AX_Y) {
-    const dim3 grid(unsigned((nx + G::LPB - 1) / G::LPB), unsigned(nt), unsigned(g.nf) * m);
-    launch_batched<N1, N2, AX_Y, 1, NL_NONE>(nx % G::LPB == 0, grid, st, d, step, g.nf);
+    const long lines = long(nx) * nt;
+    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(g.nf) * m);
+    launch_batched<N1, N2, AX_Y, 1, NL_NONE>(lines % G::LPB == 0, grid, st, d, step, g.nf);
   } else {
     const long lines = long(nx) * ny;
     const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), m);

@@ -97,15 +97,31 @@ struct Kappas {
   double k[3];
 };
 
-// Step index, energies and Manley-Rowe combinations of one record.
-__global__ void finish_record(double* rec, long long step, int nf, int nt, double dt, Kappas ka) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Step index, energies and Manley-Rowe combinations of one record (one
+// block of 64 threads: strided partial sums over tau, then a fixed tree).
+constexpr int kFinishThreads = 64;
+
+__global__ __launch_bounds__(kFinishThreads) void finish_record(double* rec, long long step, int nf,
+                                                                int nt, double dt, Kappas ka) {
+  __shared__ double part[3][kFinishThreads];
+  const int t = threadIdx.x;
+  for (int j = 0; j < 3; ++j) {
+    double s = 0.0;
+    if (j < nf)
+      for (int k = t; k < nt; k += kFinishThreads) s += rec[1 + long(j) * nt + k];
+    part[j][t] = s;
+  }
+  __syncthreads();
+  for (int w = kFinishThreads / 2; w > 0; w >>= 1) {
+    if (t < w)
+      for (int j = 0; j < 3; ++j) part[j][t] += part[j][t + w];
+    __syncthreads();
+  }
+  if (t != 0) return;
   rec[0] = double(step);
   double e[3] = {0.0, 0.0, 0.0};
   for (int j = 0; j < nf; ++j) {
-    double s = 0.0;
-    for (int t = 0; t < nt; ++t) s += rec[1 + long(j) * nt + t];
-    e[j] = s * dt;
+    e[j] = part[j][0] * dt;
     rec[1 + long(nf) * nt + j] = e[j];
   }
   const double qnan = __builtin_nan("");
@@ -158,7 +174,8 @@ brahms_status write_record(brahms_plan_s& p, long long step, double* rec) {
   HIP_TRY(hipGetLastError());
   Kappas ka{};
   for (int j = 0; j < p.nf; ++j) ka.k[j] = p.fp[j].kappa;
-  hipLaunchKernelGGL(finish_record, dim3(1), dim3(64), 0, p.stream, rec, step, p.nf, p.nt, p.dt, ka);
+  hipLaunchKernelGGL(finish_record, dim3(1), dim3(kFinishThreads), 0, p.stream, rec, step, p.nf, p.nt,
+                     p.dt, ka);
   HIP_TRY(hipGetLastError());
   return BRAHMS_OK;
 }

@@ -101,8 +101,9 @@ hipError_t launch_axis(int axis, int nl, int nf, const brahms_plan_s& p, PassArg
     const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
     launch_nl<N1, N2, AX_X>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
   } else if (axis == AX_Y) {
-    const dim3 grid(unsigned((p.nx + G::LPB - 1) / G::LPB), unsigned(p.nt), unsigned(nf));
-    launch_pass<N1, N2, AX_Y, 1, NL_NONE>(p.nx % G::LPB == 0, grid, p.stream, a);
+    const long lines = long(p.nx) * p.nt;
+    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(nf));
+    launch_pass<N1, N2, AX_Y, 1, NL_NONE>(lines % G::LPB == 0, grid, p.stream, a);
   } else {
     const long lines = long(p.nx) * p.ny;
     const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));

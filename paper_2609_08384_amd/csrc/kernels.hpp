@@ -247,11 +247,10 @@ __device__ __forceinline__ void map_factors(const float2* map, unsigned plane, u
 // NF is the number of fields held by one thread (Y: 1, one field per block).
 // FULL: every line of every block exists (no bounds masks).
 // ---------------------------------------------------------------------------
-// bx: tile index along the launch's x dimension; by: tau slice (y pass);
-// field0: first field handled (y pass: the block's field).
+// bx: tile index along the launch's x dimension; field0: first field
+// handled (y pass: the block's field).
 template <int N1, int N2, int AX, int NF, int NL, bool FULL>
-__device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx, unsigned by,
-                                               int field0) {
+__device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx, int field0) {
   using G = LineGeom<N1, N2>;
   constexpr int N = G::N;
   constexpr int NLM = NL & 3;                  // where the RK4 half-step goes
@@ -292,11 +291,15 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
     base = line * unsigned(args.nx);
     estride = 1;
   } else if constexpr (AX == AX_Y) {
+    // lines (x, tau) numbered x-fastest, so that a block's LPB lines are
+    // consecutive x (coalesced rows) and only the last block can be partial
     li = tid % G::LPB;
     t = tid / G::LPB;
-    const unsigned col = bx * unsigned(G::LPB) + li;
-    if constexpr (!FULL) valid = col < unsigned(args.nx);
-    base = col + unsigned(args.nx) * unsigned(args.ny) * by;
+    const unsigned line = bx * unsigned(G::LPB) + li;
+    if constexpr (!FULL) valid = line < unsigned(args.nx) * unsigned(args.nt);
+    const unsigned xx = line % unsigned(args.nx);
+    const unsigned tt = line / unsigned(args.nx);
+    base = xx + unsigned(args.nx) * unsigned(args.ny) * tt;
     estride = args.nx;
   } else {
     li = tid % G::LPB;
@@ -411,8 +414,7 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
 // One pass of one problem.
 template <int N1, int N2, int AX, int NF, int NL, bool FULL>
 __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass(PassArgs args) {
-  axis_pass_body<N1, N2, AX, NF, NL, FULL>(args, blockIdx.x, blockIdx.y,
-                                           AX == AX_Y ? int(blockIdx.z) : 0);
+  axis_pass_body<N1, N2, AX, NF, NL, FULL>(args, blockIdx.x, AX == AX_Y ? int(blockIdx.z) : 0);
 }
 
 // One pass over a group of problems of the same shape (a batch): descs[i]
@@ -425,7 +427,7 @@ __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass_batched(
   const unsigned inst = AX == AX_Y ? blockIdx.z / unsigned(nf) : blockIdx.y;
   const PassArgs& a = descs[inst];
   if (step >= a.nz) return;
-  axis_pass_body<N1, N2, AX, NF, NL, FULL>(a, blockIdx.x, blockIdx.y,
+  axis_pass_body<N1, N2, AX, NF, NL, FULL>(a, blockIdx.x,
                                            AX == AX_Y ? int(blockIdx.z % unsigned(nf)) : 0);
 }
 
