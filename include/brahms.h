@@ -144,10 +144,17 @@ brahms_status brahms_plan_destroy(brahms_plan plan);
  * pass the second one.
  *   pass_order 0: x pass, y pass, tau pass (default)
  *   pass_order 1: tau pass, y pass, x pass
+ *   graph 1: brahms_step replays whole 64-step chunks (tables and passes) from
+ *     a hipGraph captured once per binding and schedule (bitwise the same
+ *     result; removes the per-launch host cost).  Chunks that record timing,
+ *     monitors or snapshots, partial chunks, and plans whose transverse map
+ *     tables are filled per step run launch by launch.  The graph is captured
+ *     by brahms_plan_set_schedule or brahms_plan_bind, whichever comes last.
  * The autotuner in the Python package times the candidates per grid shape. */
 typedef struct {
   int pass_order;
-  int reserved[7];
+  int graph;
+  int reserved[6];
 } brahms_schedule;
 
 brahms_status brahms_plan_set_schedule(brahms_plan plan, const brahms_schedule* sched);

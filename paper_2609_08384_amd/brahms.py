@@ -41,7 +41,7 @@ class BrahmsError(RuntimeError):
 
 
 class ScheduleC(ctypes.Structure):
-    _fields_ = [("pass_order", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
+    _fields_ = [("pass_order", ctypes.c_int), ("graph", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
 
 
 class FieldParamsC(ctypes.Structure):
@@ -249,9 +249,10 @@ class Plan:
     def set_z(self, z: float):
         _check(self._lib.brahms_set_z(self._h, float(z)), "brahms_set_z")
 
-    def set_schedule(self, pass_order: int):
+    def set_schedule(self, pass_order: int, graph: int = 0):
         sc = ScheduleC()
         sc.pass_order = int(pass_order)
+        sc.graph = int(graph)
         _check(self._lib.brahms_plan_set_schedule(self._h, ctypes.byref(sc)),
                "brahms_plan_set_schedule")
 
@@ -259,7 +260,7 @@ class Plan:
         sc = ScheduleC()
         _check(self._lib.brahms_plan_get_schedule(self._h, ctypes.byref(sc)),
                "brahms_plan_get_schedule")
-        return {"pass_order": sc.pass_order}
+        return {"pass_order": sc.pass_order, "graph": sc.graph}
 
     # --- adjoint (reverse-mode gradient of the z-loop) ---
     def adjoint_workspace_bytes(self, nsteps: int, checkpoint_every: int) -> int:

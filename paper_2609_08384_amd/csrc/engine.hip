@@ -157,6 +157,8 @@ void layout(brahms_plan_s& p) {
   off = align_up(off + sizeof(int));
   p.off_diag = off;
   off = align_up(off + sizeof(double) * size_t(kDiagChunks) * p.nf * p.nt);
+  p.off_n0 = off;
+  off = align_up(off + sizeof(long long));
   if (!p.dk_map.empty()) {
     // phase tables of a whole 64-step chunk when they take at most 64 MB,
     // else one step at a time
@@ -239,6 +241,7 @@ brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count) {
   ta.phi0 = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_phi0);
   ta.dk = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_dk);
   ta.n0 = n0;
+  ta.n0_dev = p.table_n0_dev;
   ta.count = count;
   p.table_n0 = n0;
   ta.nx = p.nx; ta.ny = p.ny; ta.nt = p.nt; ta.nf = p.nf;
@@ -294,6 +297,7 @@ brahms_status map_table(brahms_plan_s& p, long long n0, int count) {
   m.out = reinterpret_cast<float2*>(p.ws + p.off_maptab);
   m.plane = unsigned(p.dk_map.size());
   m.n0 = n0;
+  m.n0_dev = p.table_n0_dev;
   m.dz = p.dz;
   hipLaunchKernelGGL(map_phase_table, dim3((m.plane + 255) / 256, unsigned(count)), dim3(256), 0,
                      p.stream, m);
@@ -347,15 +351,85 @@ brahms_status launch_linear_pass(brahms_plan_s& p, int row, int axis, float2* co
 
 namespace {
 
-brahms_status run_steps(brahms_plan_s& p, int nsteps) {
+detail::StepIO plain_io(const brahms_plan_s& p) {
   detail::StepIO io{};
   for (int j = 0; j < 3; ++j) {
     io.in[j] = p.fields[j];
     io.out[j] = p.fields[j];
   }
+  return io;
+}
+
+// A whole 64-step chunk can be replayed from the plan's graph: no per-step
+// host work (timing, monitors, snapshots, one-step map tables) is wanted.
+bool graph_chunk_ok(const brahms_plan_s& p) {
+  return p.use_graph && p.bound && !p.timing && p.mon_every == 0 && p.snap_steps.empty() &&
+         (p.dk_map.empty() || p.map_rows == kChunk);
+}
+
+void drop_chunk_graph(brahms_plan_s& p) {
+  if (p.chunk_exec) (void)hipGraphExecDestroy(p.chunk_exec);
+  if (p.chunk_graph) (void)hipGraphDestroy(p.chunk_graph);
+  p.chunk_exec = nullptr;
+  p.chunk_graph = nullptr;
+}
+
+// Capture the tables and the 64 steps of one chunk on a private stream; the
+// tables read the chunk's first step from the workspace (set before each
+// replay), everything else is the same for every chunk.
+brahms_status build_chunk_graph(brahms_plan_s& p) {
+  drop_chunk_graph(p);
+  if (!p.capture_stream) HIP_TRY(hipStreamCreateWithFlags(&p.capture_stream, hipStreamNonBlocking));
+  const hipStream_t user = p.stream;
+  const long long saved_n0 = p.table_n0;
+  p.stream = p.capture_stream;
+  p.table_n0_dev = reinterpret_cast<const long long*>(p.ws + p.off_n0);
+  brahms_status st = BRAHMS_OK;
+  hipError_t e = hipStreamBeginCapture(p.capture_stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const detail::StepIO io = plain_io(p);
+    st = detail::refresh_tables(p, 0, kChunk);
+    for (int s = 0; s < kChunk && st == BRAHMS_OK; ++s) st = detail::launch_step(p, s, io);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p.capture_stream, &g);
+    if (st == BRAHMS_OK && e == hipSuccess) {
+      p.chunk_graph = g;
+      e = hipGraphInstantiate(&p.chunk_exec, g, nullptr, nullptr, 0);
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  }
+  p.stream = user;
+  p.table_n0_dev = nullptr;
+  p.table_n0 = saved_n0;
+  if (st != BRAHMS_OK) {
+    drop_chunk_graph(p);
+    return st;
+  }
+  if (e != hipSuccess) {
+    drop_chunk_graph(p);
+    return fail(BRAHMS_E_DEVICE, std::string("chunk graph capture: ") + hipGetErrorString(e));
+  }
+  return BRAHMS_OK;
+}
+
+brahms_status run_steps(brahms_plan_s& p, int nsteps) {
+  const detail::StepIO io = plain_io(p);
   int done = 0;
   while (done < nsteps) {
     const int count = std::min(kChunk, nsteps - done);
+    if (count == kChunk && graph_chunk_ok(p)) {
+      if (!p.chunk_exec)
+        if (brahms_status st = build_chunk_graph(p)) return st;
+      hipLaunchKernelGGL(set_step_index, dim3(1), dim3(1), 0, p.stream,
+                         reinterpret_cast<long long*>(p.ws + p.off_n0), p.step);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipGraphLaunch(p.chunk_exec, p.stream));
+      p.table_n0 = p.step;
+      p.step += count;
+      done += count;
+      continue;
+    }
     if (brahms_status st = detail::refresh_tables(p, p.step, count)) return st;
     const bool watch = p.mon_every > 0 || !p.snap_steps.empty();
     for (int s = 0; s < count; ++s) {
@@ -456,6 +530,7 @@ brahms_status brahms_plan_bind(brahms_plan plan, void* const* fields, void* work
   }
   plan->bound = false;
   plan->adj_ready = false;
+  drop_chunk_graph(*plan);   // it holds the old pointers
   for (int j = 0; j < 3; ++j) plan->fields[j] = j < plan->nf ? static_cast<float2*>(fields[j]) : nullptr;
   plan->ws = static_cast<char*>(workspace);
   if (!plan->dk.empty()) {
@@ -478,6 +553,7 @@ brahms_status brahms_plan_bind(brahms_plan plan, void* const* fields, void* work
     HIP_TRY(hipStreamSynchronize(plan->stream));
   }
   plan->bound = true;
+  if (graph_chunk_ok(*plan)) return build_chunk_graph(*plan);
   return BRAHMS_OK;
 }
 
@@ -550,7 +626,12 @@ brahms_status brahms_plan_set_schedule(brahms_plan plan, const brahms_schedule* 
   if (sched == nullptr) return fail(BRAHMS_E_INVALID_ARG, "schedule is NULL");
   if (sched->pass_order != 0 && sched->pass_order != 1)
     return fail(BRAHMS_E_INVALID_ARG, "pass_order must be 0 or 1");
+  if (sched->graph != 0 && sched->graph != 1) return fail(BRAHMS_E_INVALID_ARG, "graph must be 0 or 1");
+  if (plan->order != sched->pass_order || plan->use_graph != (sched->graph != 0)) drop_chunk_graph(*plan);
   plan->order = sched->pass_order;
+  plan->use_graph = sched->graph != 0;
+  // capture now rather than in the first call that replays it
+  if (graph_chunk_ok(*plan) && !plan->chunk_exec) return build_chunk_graph(*plan);
   return BRAHMS_OK;
 }
 
@@ -559,6 +640,7 @@ brahms_status brahms_plan_get_schedule(brahms_plan plan, brahms_schedule* sched)
   if (sched == nullptr) return fail(BRAHMS_E_INVALID_ARG, "schedule is NULL");
   *sched = brahms_schedule{};
   sched->pass_order = plan->order;
+  sched->graph = plan->use_graph ? 1 : 0;
   return BRAHMS_OK;
 }
 
@@ -597,6 +679,8 @@ brahms_status brahms_plan_destroy(brahms_plan plan) {
     (void)hipEventDestroy(t.stop);
   }
   for (hipEvent_t e : plan->pool) (void)hipEventDestroy(e);
+  drop_chunk_graph(*plan);
+  if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
   delete plan;
   return BRAHMS_OK;
 }

@@ -461,13 +461,18 @@ struct TableArgs {
   float2* nl;            // [count][2][nf][6]
   const double* phi0;    // Phi_n prefix (profile) or null
   const double* dk;      // dk_n (profile) or null
-  long n0;
+  long n0;               // first step of the rows (unless n0_dev is set)
+  const long long* n0_dev;  // device copy of n0 (graph replays), or null
   int count;
   int nx, ny, nt, nf;
   int row_stride;
   double dz, dx, dy, dt, dk_const;
   FieldCoef fc[3];
 };
+
+__device__ inline long table_n0(const TableArgs& a) {
+  return a.n0_dev != nullptr ? long(*a.n0_dev) : a.n0;
+}
 
 __host__ __device__ inline int table_row_stride(int nf, int nx, int ny, int nt) {
   return (nf + 1) * (nx + ny + nt) + 4;
@@ -530,7 +535,7 @@ __device__ __forceinline__ void step_tables_body(const TableArgs& a, long gid) {
   if (gid < nrow) {
     const int s = int(gid / per_step);
     const int r = int(gid % per_step);
-    const long n = a.n0 + s;
+    const long n = table_n0(a) + s;
     float2* row = a.rows + long(s) * a.row_stride;
     if (r == per_step - 1) {
       // register-DFT constants of this step
@@ -588,7 +593,7 @@ __device__ __forceinline__ void step_tables_body(const TableArgs& a, long gid) {
   const int s = int(g2 / (2 * a.nf));
   const int half = int((g2 / a.nf) % 2);
   const int j = int(g2 % a.nf);
-  const long n = a.n0 + s;
+  const long n = table_n0(a) + s;
   double phi_n, dkn;
   if (a.dk != nullptr) {
     phi_n = a.phi0[n];
@@ -644,14 +649,15 @@ struct MapArgs {
   const double* scale;  // s_n (NULL: no scale profile)
   float2* out;          // [count][5][ny][nx]
   unsigned plane;
-  long long n0;
+  long long n0;              // first step (unless n0_dev is set)
+  const long long* n0_dev;   // device copy of n0 (graph replays), or null
   double dz;
 };
 
 static __global__ void map_phase_table(MapArgs a) {
   const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.plane) return;
-  const long long n = a.n0 + blockIdx.y;
+  const long long n = (a.n0_dev != nullptr ? *a.n0_dev : a.n0) + blockIdx.y;
   const double psi_n = a.psi0 != nullptr ? a.psi0[n] : double(n) * a.dz;
   const double s_n = a.scale != nullptr ? a.scale[n] : 1.0;
   const double m = a.map[i];
@@ -661,6 +667,11 @@ static __global__ void map_phase_table(MapArgs a) {
     sincos(reduce_2pi(m * (psi_n + s_n * (0.25 * k) * a.dz)), &sn, &cs);
     out[k * a.plane + i] = make_float2(float(cs), float(sn));
   }
+}
+
+// First step index of a chunk, for tables read by a replayed graph.
+static __global__ void set_step_index(long long* dst, long long n0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *dst = n0;
 }
 
 static __global__ void finite_check(const float2* f, long n, int* flag) {

@@ -26,12 +26,19 @@ struct brahms_plan_s {
   bool bound = false;
   long long step = 0;          // z = step * dz
   int order = 0;               // 0: x, y, tau passes; 1: tau, y, x
+  // hipGraph replay of whole 64-step chunks (schedule field `graph`)
+  bool use_graph = false;
+  hipGraph_t chunk_graph = nullptr;
+  hipGraphExec_t chunk_exec = nullptr;
+  hipStream_t capture_stream = nullptr;   // private stream the chunk is captured on
+  const long long* table_n0_dev = nullptr;  // while capturing: tables read n0 here
   // workspace offsets (bytes)
   size_t off_phi0 = 0, off_dk = 0, off_prop = 0, off_nl = 0, off_flag = 0, ws_size = 0;
   size_t off_map = 0, off_maptab = 0;   // map (FP64) and its per-step phase tables
   size_t off_psi0 = 0, off_scale = 0;   // Psi_n prefix and s_n (with a scale profile)
   int map_rows = 0;                     // steps per phase-table fill (kChunk or 1)
   size_t off_diag = 0;                  // partial sums of the diagnostics
+  size_t off_n0 = 0;                    // first step of the chunk a graph replays
   // launch timing (diagnostics)
   bool timing = false;
   struct Timed { int kind; hipEvent_t start, stop; };

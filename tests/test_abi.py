@@ -172,3 +172,17 @@ def test_dk_map_host_checks(lib):
     steps = (ctypes.c_int * 1)(3)
     hb = ctypes.c_void_p()
     assert lib.brahms_batch_create(1, shapes, params, steps, None, ctypes.byref(hb)) == brahms.BRAHMS_E_UNSUPPORTED
+
+
+def test_schedule_host_checks(lib):
+    c, keep = _params()
+    st, h = _create(lib, 8, 8, 8, 2, c)
+    sc = brahms.ScheduleC()
+    sc.pass_order, sc.graph = 1, 2
+    assert lib.brahms_plan_set_schedule(h, ctypes.byref(sc)) == brahms.BRAHMS_E_INVALID_ARG
+    sc.graph = 1
+    assert lib.brahms_plan_set_schedule(h, ctypes.byref(sc)) == brahms.BRAHMS_OK  # unbound: no capture
+    out = brahms.ScheduleC()
+    assert lib.brahms_plan_get_schedule(h, ctypes.byref(out)) == brahms.BRAHMS_OK
+    assert (out.pass_order, out.graph) == (1, 1)
+    lib.brahms_plan_destroy(h)
