@@ -358,10 +358,10 @@ brahms_status brahms_batch_create(int n, const int* shapes, const brahms_params*
       brahms_batch_destroy(b);
       return st;
     }
-    if (!p->dk_map.empty()) {
+    if (!p->dk_map.empty() || brahms::detail::long_tau(*p)) {
       brahms_plan_destroy(p);
       brahms_batch_destroy(b);
-      return fail(BRAHMS_E_UNSUPPORTED, "batches take no transverse dk map");
+      return fail(BRAHMS_E_UNSUPPORTED, "batches take no transverse dk map and no nt > 256");
     }
     if (!p->dk.empty() && nsteps[i] > (int)p->dk.size()) {
       brahms_plan_destroy(p);

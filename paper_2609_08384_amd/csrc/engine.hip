@@ -57,6 +57,10 @@ bool supported_length(int n) {
   }
 }
 
+// tau axes longer than one line transform: nt = A B, transformed in three
+// passes (b transforms, a transforms with the propagator, inverse b)
+bool supported_long_tau(int n) { return n == 512 || n == 1024 || n == 2048 || n == 4096; }
+
 }  // namespace
 
 namespace {
@@ -128,6 +132,45 @@ hipError_t dispatch_axis(int n, int axis, int nl, int nf, const brahms_plan_s& p
     case 256: return launch_axis<16, 16>(axis, nl, nf, p, a);
     default: return hipErrorInvalidValue;
   }
+}
+
+// Line length of a long-tau pass: B for the b passes, A for the a pass
+// (512 = 32 x 16, 1024 = 32 x 32, 2048 = 64 x 32, 4096 = 64 x 64).
+int long_tau_a(int nt) { return nt >= 2048 ? 64 : 32; }
+
+template <int N1, int N2, int AX>
+hipError_t launch_long(int nl, int nf, const brahms_plan_s& p, PassArgs a) {
+  using G = LineGeom<N1, N2>;
+  a.tile_mul = 1;
+  a.tiles = 1;
+  const long lines = long(p.nx) * p.ny * (p.nt / G::N);
+  const bool full = lines % G::LPB == 0;
+  if constexpr (AX == AX_TAI) {
+    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
+    launch_nl<N1, N2, AX_TAI>(nf, nl, full, grid, p.stream, a);
+  } else {
+    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(nf));
+    launch_pass<N1, N2, AX, 1, NL_NONE>(full, grid, p.stream, a);
+  }
+  return hipGetLastError();
+}
+
+template <int AX>
+hipError_t dispatch_long_len(int len, int nl, int nf, const brahms_plan_s& p, const PassArgs& a) {
+  switch (len) {
+    case 16: return launch_long<4, 4, AX>(nl, nf, p, a);
+    case 32: return launch_long<8, 4, AX>(nl, nf, p, a);
+    case 64: return launch_long<8, 8, AX>(nl, nf, p, a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t dispatch_long(int axis, int nl, int nf, const brahms_plan_s& p, const PassArgs& a) {
+  const int na = long_tau_a(p.nt);
+  const int nb = p.nt / na;
+  if (axis == AX_TAF) return dispatch_long_len<AX_TAF>(nb, nl, nf, p, a);
+  if (axis == AX_TB) return dispatch_long_len<AX_TB>(na, nl, nf, p, a);
+  return dispatch_long_len<AX_TAI>(nb, nl, nf, p, a);
 }
 
 bool finite_params(const brahms_params* pr, int nf) {
@@ -278,10 +321,14 @@ PassArgs pass_args(const brahms_plan_s& p, int row, int ax) {
 }
 
 brahms_status timed_dispatch(brahms_plan_s& p, int ax, int nlmode, const PassArgs& a) {
-  const int n[3] = {p.nx, p.ny, p.nt};
   const bool timed = p.timing && p.timed.size() < kMaxTimed;
-  if (brahms_status st = timing_start(p, ax)) return st;
-  HIP_TRY(dispatch_axis(n[ax], ax, nlmode, p.nf, p, a));
+  if (brahms_status st = timing_start(p, long_tau_kind(ax) ? int(AX_T) : ax)) return st;
+  if (long_tau_kind(ax)) {
+    HIP_TRY(dispatch_long(ax, nlmode, p.nf, p, a));
+  } else {
+    const int n[3] = {p.nx, p.ny, p.nt};
+    HIP_TRY(dispatch_axis(n[ax], ax, nlmode, p.nf, p, a));
+  }
   if (timed)
     if (brahms_status st = timing_stop(p)) return st;
   return BRAHMS_OK;
@@ -313,22 +360,27 @@ brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io) {
     if (brahms_status st = map_table(p, p.table_n0 + row, 1)) return st;
   const size_t map_row = map ? size_t(p.map_rows == 1 ? 0 : row) * 5 * p.dk_map.size() : 0;
   // pass order of the step: the first pass carries the first RK4 half-step,
-  // the last pass the second one (the axis operators commute)
-  for (int k = 0; k < 3; ++k) {
-    const int ax = pass_axis(p, k);
-    int nlmode = k == 0 ? NL_BEFORE : (k == 2 ? NL_AFTER : NL_NONE);
+  // the last pass the second one (the axis operators commute).  A long tau
+  // axis takes three passes: x, y, tau-b, tau-a, inverse tau-b.
+  const bool longt = detail::long_tau(p);
+  const int npass = longt ? 5 : 3;
+  const int long_axes[5] = {AX_X, AX_Y, AX_TAF, AX_TB, AX_TAI};
+  for (int k = 0; k < npass; ++k) {
+    const int ax = longt ? long_axes[k] : pass_axis(p, k);
+    const bool first = k == 0, last = k == npass - 1;
+    int nlmode = first ? NL_BEFORE : (last ? NL_AFTER : NL_NONE);
     PassArgs a = pass_args(p, row, ax);
     if (map && nlmode != NL_NONE) {
       nlmode |= NL_MAP;
       a.map = reinterpret_cast<const float2*>(p.ws + p.off_maptab) + map_row +
-              (k == 0 ? 0 : 2) * p.dk_map.size();
+              (first ? 0 : 2) * p.dk_map.size();
     }
     for (int j = 0; j < 3; ++j) {
-      a.f[j] = k == 0 ? io.in[j] : io.out[j];
+      a.f[j] = first ? io.in[j] : io.out[j];
       a.fo[j] = io.out[j];
-      a.pre[j] = k == 2 ? io.pre[j] : nullptr;
+      a.pre[j] = last ? io.pre[j] : nullptr;
     }
-    a.nl = nl_coefficients(p, row, k == 0 ? 0 : 1);
+    a.nl = nl_coefficients(p, row, first ? 0 : 1);
     if (brahms_status st = timed_dispatch(p, ax, nlmode, a)) return st;
   }
   return BRAHMS_OK;
@@ -465,9 +517,11 @@ brahms_status brahms_plan_create(int nx, int ny, int nt, int nfields, const brah
     return fail(BRAHMS_E_INVALID_ARG, "dk profile given with n_dk < 1");
   if (params->dk_map_scale != nullptr && (params->dk_map == nullptr || params->n_dk_map_scale < 1))
     return fail(BRAHMS_E_INVALID_ARG, "dk_map_scale needs dk_map and n_dk_map_scale >= 1");
-  if (!supported_length(nx) || !supported_length(ny) || !supported_length(nt))
+  if (!supported_length(nx) || !supported_length(ny) ||
+      !(supported_length(nt) || supported_long_tau(nt)))
     return fail(BRAHMS_E_UNSUPPORTED,
-                "axis lengths must be one of 1, 2, 4, 8, 16, 32, 64, 96, 128, 256");
+                "axis lengths must be one of 1, 2, 4, 8, 16, 32, 64, 96, 128, 256 "
+                "(tau also 512, 1024, 2048, 4096)");
   auto* p = new brahms_plan_s();
   p->nx = nx; p->ny = ny; p->nt = nt; p->nf = nfields;
   p->dz = params->dz;

@@ -26,7 +26,15 @@ namespace brahms {
 constexpr int kBlock = 256;        // threads per block in every pass
 constexpr int kNlCoef = 6;         // RK4 coefficients per field per half-step
 
-enum Axis { AX_X = 0, AX_Y = 1, AX_T = 2 };
+enum Axis { AX_X = 0, AX_Y = 1, AX_T = 2,
+            // a tau axis longer than one line transform, nt = A B, tau = a + A b
+            // (a four-step transform over three passes):
+            AX_TAF = 3,   // B-point transforms over b, times exp(-2 pi i a k_b / nt)
+            AX_TB = 4,    // A-point transforms over a, propagator, inverse transforms
+            AX_TAI = 5 }; // times exp(+2 pi i a k_b / nt), inverse B-point transforms
+constexpr int kMaxLongT = 4096;   // longest tau axis (entries of the staged table)
+
+__host__ __device__ constexpr bool long_tau_kind(int ax) { return ax >= AX_TAF; }
 enum NlMode { NL_NONE = 0, NL_BEFORE = 1, NL_AFTER = 2 };
 // Added to NL_BEFORE / NL_AFTER: the mismatch phase also has a transverse
 // part (a per-(x, y) table of exp(i m(x, y) Psi(z)) for each RK4 stage).
@@ -229,7 +237,7 @@ __device__ inline void store_field(float2* base, unsigned idx, float2 v) {
 template <int AX, int N2>
 __device__ __forceinline__ void map_factors(const float2* map, unsigned plane, unsigned xy0, int e,
                                             const float2* wt, float2* w) {
-  if constexpr (AX == AX_T) {
+  if constexpr (AX == AX_T || long_tau_kind(AX)) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) w[k] = wt[k];
   } else {
@@ -256,9 +264,13 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
   constexpr int NLM = NL & 3;                  // where the RK4 half-step goes
   constexpr bool MAP = (NL & NL_MAP) != 0;     // transverse mismatch map
   constexpr bool NT = (AX == AX_X) ? bool(BRAHMS_NT_X) : bool(BRAHMS_NT_YT);
+  constexpr bool LONG = long_tau_kind(AX);
   __shared__ float2 lds[G::LDS_ELEMS];
   __shared__ float2 s_tw[N];
-  __shared__ float2 s_prop[NF * N];
+  __shared__ float2 s_prop[LONG ? 1 : NF * N];
+  // long tau axis: the nt-point twiddles (a and b passes) or the tau
+  // propagator (transform pass) of the whole axis
+  __shared__ float2 s_long[LONG ? kMaxLongT : 1];
 
   const int tid = threadIdx.x;
   // RK4 coefficients of the half-step: the same for every thread, read
@@ -271,15 +283,34 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
       for (int c = 0; c < kNlCoef; ++c) co[j][c] = wave_uniform(args.nl[j * kNlCoef + c]);
   }
   // this step's twiddles and this block's propagators, staged once
-  for (int i = tid; i < N; i += kBlock) s_tw[i] = args.tw[i];
-  for (int i = tid; i < NF * N; i += kBlock) {
-    float2 pv = args.prop[(field0 + i / N) * args.field_stride + args.axis_off + i % N];
-    if (args.conj) pv.y = -pv.y;
-    s_prop[i] = pv;
+  if constexpr (LONG) {
+    // args.tw is the nt-point row exp(-2 pi i m / nt); the line transforms
+    // of length N take every (nt / N)-th entry
+    const int nt = args.nt;
+    const int stride = nt / N;
+    for (int i = tid; i < N; i += kBlock) s_tw[i] = args.tw[i * stride];
+    if constexpr (AX == AX_TB) {
+      const float2* pr = args.prop + field0 * args.field_stride + args.axis_off;
+      for (int i = tid; i < nt; i += kBlock) {
+        float2 pv = pr[i];
+        if (args.conj) pv.y = -pv.y;
+        s_long[i] = pv;
+      }
+    } else {
+      for (int i = tid; i < nt; i += kBlock) s_long[i] = args.tw[i];
+    }
+  } else {
+    for (int i = tid; i < N; i += kBlock) s_tw[i] = args.tw[i];
+    for (int i = tid; i < NF * N; i += kBlock) {
+      float2 pv = args.prop[(field0 + i / N) * args.field_stride + args.axis_off + i % N];
+      if (args.conj) pv.y = -pv.y;
+      s_prop[i] = pv;
+    }
   }
 
   int t, li;
   unsigned base, estride;
+  unsigned lidx = 0;     // long tau axis: a (b passes) or k_b (a pass) of the line
   bool valid = true;
   const float2* fin[NF];
   float2* fout[NF];
@@ -301,6 +332,25 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
     const unsigned tt = line / unsigned(args.nx);
     base = xx + unsigned(args.nx) * unsigned(args.ny) * tt;
     estride = args.nx;
+  } else if constexpr (LONG) {
+    // lines (column, a) of the b transforms or (column, k_b) of the a
+    // transforms, column-fastest: a block's lines are consecutive columns
+    li = tid % G::LPB;
+    t = tid / G::LPB;
+    const unsigned plane_xy = unsigned(args.nx) * unsigned(args.ny);
+    const unsigned nsub = unsigned(args.nt) / unsigned(N);     // A (b passes) or B (a pass)
+    const unsigned line = bx * unsigned(G::LPB) + li;
+    if constexpr (!FULL) valid = line < plane_xy * nsub;
+    const unsigned col = line % plane_xy;
+    // the other index: a (b passes) or k_b (a pass); clamped on padding lines
+    lidx = min(line / plane_xy, nsub - 1u);
+    if constexpr (AX == AX_TB) {
+      base = col + plane_xy * unsigned(N) * lidx;   // elements a at tau = a + A k_b
+      estride = plane_xy;
+    } else {
+      base = col + plane_xy * lidx;                 // elements b at tau = a + A b
+      estride = plane_xy * nsub;
+    }
   } else {
     li = tid % G::LPB;
     t = tid / G::LPB;
@@ -327,7 +377,7 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
   if constexpr (MAP) {
     plane = unsigned(args.nx) * unsigned(args.ny);
     xy0 = idx0 % plane;
-    if constexpr (AX == AX_T) {
+    if constexpr (AX == AX_T || LONG) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) wt[k] = args.map[k * plane + xy0];
     }
@@ -365,10 +415,31 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
 
 #pragma unroll
   for (int j = 0; j < NF; ++j) {
-    line_fft<N1, N2, false>(v[j], t, lbuf, s_tw, K);
+    if constexpr (AX == AX_TAF) {
+      // B-point transform, then exp(-2 pi i a k_b / nt) on output k_b
+      line_fft<N1, N2, false>(v[j], t, lbuf, s_tw, K);
 #pragma unroll
-    for (int e = 0; e < N1; ++e) v[j][e] = cmul(v[j][e], s_prop[j * N + t + N2 * e]);
-    line_fft<N1, N2, true>(v[j], t, lbuf, s_tw, K);
+      for (int e = 0; e < N1; ++e)
+        v[j][e] = cmul(v[j][e], s_long[(lidx * unsigned(t + N2 * e)) & unsigned(args.nt - 1)]);
+    } else if constexpr (AX == AX_TAI) {
+      // conjugate twiddle, then the inverse B-point transform
+#pragma unroll
+      for (int e = 0; e < N1; ++e)
+        v[j][e] = cmulc(v[j][e], s_long[(lidx * unsigned(t + N2 * e)) & unsigned(args.nt - 1)]);
+      line_fft<N1, N2, true>(v[j], t, lbuf, s_tw, K);
+    } else if constexpr (AX == AX_TB) {
+      // A-point transform over a gives frequency k = k_b + B k_a in slot k_a
+      line_fft<N1, N2, false>(v[j], t, lbuf, s_tw, K);
+      const unsigned nb = unsigned(args.nt) / unsigned(N);
+#pragma unroll
+      for (int e = 0; e < N1; ++e) v[j][e] = cmul(v[j][e], s_long[lidx + nb * unsigned(t + N2 * e)]);
+      line_fft<N1, N2, true>(v[j], t, lbuf, s_tw, K);
+    } else {
+      line_fft<N1, N2, false>(v[j], t, lbuf, s_tw, K);
+#pragma unroll
+      for (int e = 0; e < N1; ++e) v[j][e] = cmul(v[j][e], s_prop[j * N + t + N2 * e]);
+      line_fft<N1, N2, true>(v[j], t, lbuf, s_tw, K);
+    }
     if constexpr (NLM != NL_AFTER) {
       if (valid) {
 #pragma unroll
@@ -414,7 +485,9 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
 // One pass of one problem.
 template <int N1, int N2, int AX, int NF, int NL, bool FULL>
 __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass(PassArgs args) {
-  axis_pass_body<N1, N2, AX, NF, NL, FULL>(args, blockIdx.x, AX == AX_Y ? int(blockIdx.z) : 0);
+  // passes with one field per block take it from blockIdx.z
+  constexpr bool per_field = NF == 1 && (AX == AX_Y || long_tau_kind(AX));
+  axis_pass_body<N1, N2, AX, NF, NL, FULL>(args, blockIdx.x, per_field ? int(blockIdx.z) : 0);
 }
 
 // One pass over a group of problems of the same shape (a batch): descs[i]

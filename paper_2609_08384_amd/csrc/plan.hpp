@@ -67,6 +67,9 @@ constexpr int kDiagChunks = 64;  // chunks per (tau, field) slice in diagnostics
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// A tau axis longer than one line transform (three passes per step).
+inline bool long_tau(const brahms_plan_s& p) { return p.nt > 256; }
+
 brahms_status fail(brahms_status st, const std::string& msg);
 
 #define HIP_TRY(expr)                                                                          \

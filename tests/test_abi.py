@@ -71,7 +71,7 @@ def test_create_and_workspace(lib):
     ((8, 8, 8), 1, brahms.BRAHMS_E_INVALID_ARG),
     ((8, 8, 8), 4, brahms.BRAHMS_E_INVALID_ARG),
     ((12, 8, 8), 2, brahms.BRAHMS_E_UNSUPPORTED),
-    ((8, 8, 512), 3, brahms.BRAHMS_E_UNSUPPORTED),
+    ((8, 512, 8), 3, brahms.BRAHMS_E_UNSUPPORTED),   # only tau may exceed 256
     ((8, 7, 8), 3, brahms.BRAHMS_E_UNSUPPORTED),
 ])
 def test_create_rejects(lib, shape, nf, status):
@@ -186,3 +186,19 @@ def test_schedule_host_checks(lib):
     assert lib.brahms_plan_get_schedule(h, ctypes.byref(out)) == brahms.BRAHMS_OK
     assert (out.pass_order, out.graph) == (1, 1)
     lib.brahms_plan_destroy(h)
+
+
+def test_long_tau_host_checks(lib):
+    c, keep = _params()
+    st, h = _create(lib, 8, 8, 1024, 2, c)
+    assert st == brahms.BRAHMS_OK
+    size = ctypes.c_size_t()
+    assert lib.brahms_adjoint_workspace_size(h, 10, 5, ctypes.byref(size)) == brahms.BRAHMS_E_UNSUPPORTED
+    lib.brahms_plan_destroy(h)
+    assert _create(lib, 512, 8, 8, 2, c)[0] == brahms.BRAHMS_E_UNSUPPORTED   # only tau may be long
+    assert _create(lib, 8, 8, 8192, 2, c)[0] == brahms.BRAHMS_E_UNSUPPORTED
+    shapes = (ctypes.c_int * 4)(8, 8, 2048, 2)
+    params = (brahms.ParamsC * 1)(c)
+    steps = (ctypes.c_int * 1)(3)
+    hb = ctypes.c_void_p()
+    assert lib.brahms_batch_create(1, shapes, params, steps, None, ctypes.byref(hb)) == brahms.BRAHMS_E_UNSUPPORTED
