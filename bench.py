@@ -214,6 +214,46 @@ def dk_map_cost(dev):
     return out
 
 
+# (grid, paper's GPU-3 time in s for 100 000 steps, tab. gpu_runtime):
+# context only, other hardware, FP32, a physical MgO:PPLN workload
+PAPER_GRIDS = [((64, 64, 4096), 16611.0), ((128, 128, 1024), 5141.0)]
+
+
+def paper_grids(dev, steps=200):
+    """Three-field pulsed-focused grids of the paper's runtime table on this
+    engine: seeded OPG-type fields, `steps` timed steps after a warm-up."""
+    import numpy as np
+    import torch
+    from paper_2609_08384_amd import autotune, brahms, inputs
+    out = []
+    for (nx, ny, nt), paper_s in PAPER_GRIDS:
+        fs = [inputs.FieldSpec(kappa=2.0 * w, diffraction=20.0 / w, tan_rho=1.0, delay=10.0 * j,
+                               k2=500.0 * (1 - j)) for j, w in enumerate(inputs.OMEGA_RATIO)]
+        params = brahms.Params(dz=1e-3, fields=[brahms.FieldParams(f.kappa, f.diffraction, f.tan_rho,
+                                                                   f.delay, f.k2) for f in fs])
+        pump = inputs.focused_pulse(nx, ny, nt, nx / 8.0, inputs.fwhm_to_tau0(nt / 8.0), 0.5)
+        rng = np.random.default_rng(nt)
+        seeds = [1e-6 * (rng.standard_normal((nt, ny, nx)) + 1j * rng.standard_normal((nt, ny, nx)))
+                 for _ in range(2)]
+        fields = [torch.from_numpy(inputs.to_c64(a)).to(dev) for a in [pump] + seeds]
+        plan = brahms.Plan(nx, ny, nt, 3, params).bind(fields)
+        sched = autotune.apply(plan, dev)
+        plan.step(64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        plan.destroy()
+        n = nx * ny * nt
+        rate = n * steps / dt
+        out.append({"grid": f"{nx}x{ny}x{nt}", "fields": 3, "ms_per_step": dt / steps * 1e3,
+                    "rate": rate, "hbm_frac_step": (5 if nt > 256 else 3) * 48 * n / (dt / steps) / 8e12,
+                    "schedule": sched, "paper_gpu3_rate": n * 1e5 / paper_s,
+                    "vs_paper_gpu3": rate / (n * 1e5 / paper_s)})
+    return out
+
+
 def batch_ratio(dev):
     """Seeded SHG sweep (64 problems over 64^3, 96x96x64, 128x128x64 and
     128x128x256 grids, dk L in [-6, 6], xi in [0.1, 10], 200-600 steps): one
@@ -430,6 +470,7 @@ def main():
         extras["reduced_dims"] = reduced_dims(dev)
         extras["diagnostics"] = diagnostics_cost(dev, wl)
         extras["dk_map"] = dk_map_cost(dev)
+        extras["paper_grids"] = paper_grids(dev)
 
     cpu = None
     if not args.no_cpu_baseline:
