@@ -6,7 +6,9 @@
 // coefficients) that a small kernel refills every kChunk steps.  A z-step is
 // three launches on the caller's stream: X pass (RK4 half-step + x line
 // transforms), Y pass (y line transforms), T pass (tau line transforms + RK4
-// half-step).
+// half-step), or the same in the order T, Y, X; five launches when the tau
+// axis is longer than 256.  With the graph schedule whole chunks are replayed
+// from a hipGraph.
 #include <hip/hip_runtime.h>
 
 #include <cmath>

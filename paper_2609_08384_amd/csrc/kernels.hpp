@@ -14,7 +14,9 @@
 // the paper's own split into a tau step and an xy step (Sec. 4.3), taken one
 // axis further.  Fields stay x-fastest, [nt][ny][nx] complex64, in place:
 // the y and tau passes read their lines with a stride instead of
-// materialising the paper's reordered copy.
+// materialising the paper's reordered copy.  The passes may run in either
+// order (x, y, tau or tau, y, x); a tau axis longer than 256 takes three
+// passes (a four-step transform, AX_TAF / AX_TB / AX_TAI below).
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -115,3 +115,30 @@ def test_inverse_design_workload_vs_oracle(order):
     assert rel_l2(gf[g["top_idx"]], g["gF_top"]) < 1e-4
     power = (np.abs(x[0].grad.cpu().numpy().astype(np.complex128)) ** 2).sum(axis=(1, 2))
     assert rel_l2(power, g["gF_power"]) < 2e-4
+
+
+def test_inverse_design_forward_fields_vs_oracle():
+    """The forward fields of the inverse-design workload (SHG 128 x 128 x 64,
+    400 steps, per-step dk profile) at z = L: <= 2e-5 per field against the
+    oracle's reference data, from the plain plan and from the checkpointed
+    forward of the adjoint."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "shg_adjoint_400.npz")
+    if not os.path.exists(path):
+        pytest.skip("reference data not generated")
+    g = np.load(path)
+    wl = inputs.shg_adjoint()
+    params = brahms.params_from_workload(wl)
+    for adjoint in (False, True):
+        fields = [torch.from_numpy(a).to(DEV) for a in wl.init]
+        plan = brahms.Plan(wl.nx, wl.ny, wl.nt, wl.nf, params).bind(fields)
+        if adjoint:
+            plan.adjoint_forward(wl.nz, 20)
+        else:
+            plan.step(wl.nz)
+        torch.cuda.synchronize()
+        for j, f in enumerate(fields):
+            flat = f.cpu().numpy().reshape(-1)
+            assert rel_l2(flat[g["uniform_idx"]], g[f"f{j}_uniform"]) < 2e-5, (adjoint, j)
+            assert rel_l2(flat[g[f"f{j}_top_idx"]], g[f"f{j}_top"]) < 2e-5, (adjoint, j)
+        plan.destroy()
