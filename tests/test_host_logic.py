@@ -1,0 +1,60 @@
+"""Host-side logic that needs no GPU: the schedule autotuner's choice and
+cache, and the benchmark's command-line contract."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+from paper_2609_08384_amd import autotune, brahms
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture
+def fake_tuner(monkeypatch, tmp_path):
+    monkeypatch.setenv("BRAHMS_CACHE_DIR", str(tmp_path))
+    monkeypatch.setattr(autotune, "_arch", lambda device: "gfx950")
+    autotune._memo.clear()
+    calls = []
+
+    def install(times):
+        def measure(nx, ny, nt, nf, params, schedule, device="cuda:0", steps=64, warmup=3):
+            calls.append(dict(schedule))
+            return times[(schedule["pass_order"], schedule["graph"])]
+        monkeypatch.setattr(autotune, "measure", measure)
+        return calls
+    yield install
+    autotune._memo.clear()
+
+
+def _params():
+    return brahms.Params(dz=0.01, fields=[brahms.FieldParams(kappa=1.0)] * 2)
+
+
+def test_tuner_takes_the_fastest_order_and_caches(fake_tuner, tmp_path):
+    calls = fake_tuner({(0, 0): 1.0, (1, 0): 0.9, (0, 1): 0.95, (1, 1): 0.89})
+    best = autotune.tune(32, 32, 32, 2, _params())
+    # the graph is not 2 % faster than the best launch-by-launch order
+    assert best == {"pass_order": 1, "graph": 0}
+    assert len(calls) == 4
+    with open(os.path.join(str(tmp_path), "schedules.json")) as fh:
+        disk = json.load(fh)
+    (key, entry), = disk.items()
+    assert key == "v2:gfx950:32x32x32:nf2" and entry["schedule"] == best
+    autotune._memo.clear()
+    assert autotune.tune(32, 32, 32, 2, _params()) == best     # from the disk cache
+    assert len(calls) == 4
+
+
+def test_tuner_takes_the_graph_when_clearly_faster(fake_tuner):
+    fake_tuner({(0, 0): 1.0, (1, 0): 1.1, (0, 1): 0.5, (1, 1): 0.6})
+    assert autotune.tune(16, 16, 16, 3, _params(), refresh=True) == {"pass_order": 0, "graph": 1}
+
+
+def test_bench_refuses_more_than_one_gpu():
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=300)
+    assert res.returncode != 0
+    assert "one GPU" in (res.stdout + res.stderr)
