@@ -73,10 +73,15 @@ size_t state_bytes(const brahms_plan_s& p) {
 
 void make_groups(brahms_batch_s& b) {
   b.groups.clear();
-  std::map<std::tuple<int, int, int, int, int>, std::vector<int>> by_key;
+  // members of a group share the shape, the field count and the passes of a
+  // step (which also depend on the pass order and, for nt = 1, on loss)
+  std::map<std::tuple<int, int, int, int, int, int>, std::vector<int>> by_key;
   for (int i = 0; i < b.n; ++i) {
     const brahms_plan_s& p = *b.plans[i];
-    by_key[{p.nx, p.ny, p.nt, p.nf, p.order}].push_back(i);
+    const brahms::detail::StepPasses sp = brahms::detail::step_passes(p, true);
+    int code = sp.n;
+    for (int k = 0; k < sp.n; ++k) code = code * 8 + sp.ax[k];
+    by_key[{p.nx, p.ny, p.nt, p.nf, p.order, code}].push_back(i);
   }
   for (auto& kv : by_key) {
     const std::vector<int>& ids = kv.second;
@@ -125,16 +130,21 @@ void launch_batched(bool full, dim3 grid, hipStream_t st, const PassArgs* d, lon
     hipLaunchKernelGGL((axis_pass_batched<N1, N2, AX, NF, NL, false>), grid, dim3(kBlock), 0, st, d, step, nf);
 }
 
+template <int N1, int N2, int AX, int NF>
+void launch_batched_nl_nf(int nl, bool full, dim3 grid, hipStream_t st, const PassArgs* d,
+                          long long step) {
+  switch (nl) {
+    case NL_BEFORE: launch_batched<N1, N2, AX, NF, NL_BEFORE>(full, grid, st, d, step, NF); break;
+    case NL_AFTER: launch_batched<N1, N2, AX, NF, NL_AFTER>(full, grid, st, d, step, NF); break;
+    default: launch_batched<N1, N2, AX, NF, NL_BOTH>(full, grid, st, d, step, NF); break;
+  }
+}
+
 template <int N1, int N2, int AX>
 void launch_batched_nl(int nf, int nl, bool full, dim3 grid, hipStream_t st, const PassArgs* d,
                        long long step) {
-  if (nf == 3) {
-    if (nl == NL_BEFORE) launch_batched<N1, N2, AX, 3, NL_BEFORE>(full, grid, st, d, step, nf);
-    else launch_batched<N1, N2, AX, 3, NL_AFTER>(full, grid, st, d, step, nf);
-  } else {
-    if (nl == NL_BEFORE) launch_batched<N1, N2, AX, 2, NL_BEFORE>(full, grid, st, d, step, nf);
-    else launch_batched<N1, N2, AX, 2, NL_AFTER>(full, grid, st, d, step, nf);
-  }
+  if (nf == 3) launch_batched_nl_nf<N1, N2, AX, 3>(nl, full, grid, st, d, step);
+  else launch_batched_nl_nf<N1, N2, AX, 2>(nl, full, grid, st, d, step);
 }
 
 template <int N1, int N2>
@@ -149,8 +159,13 @@ void launch_group_pass(int axis, int nl, const brahms_batch_s::Group& g, hipStre
     launch_batched_nl<N1, N2, AX_X>(g.nf, nl, lines % G::LPB == 0, grid, st, d, step);
   } else if (axis == AX_Y) {
     const long lines = long(nx) * nt;
-    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(g.nf) * m);
-    launch_batched<N1, N2, AX_Y, 1, NL_NONE>(lines % G::LPB == 0, grid, st, d, step, g.nf);
+    if (nl == NL_NONE) {
+      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(g.nf) * m);
+      launch_batched<N1, N2, AX_Y, 1, NL_NONE>(lines % G::LPB == 0, grid, st, d, step, g.nf);
+    } else {
+      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), m);
+      launch_batched_nl<N1, N2, AX_Y>(g.nf, nl, lines % G::LPB == 0, grid, st, d, step);
+    }
   } else {
     const long lines = long(nx) * ny;
     const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), m);
@@ -196,8 +211,9 @@ brahms_status upload_descriptors(brahms_batch_s& b) {
       const int row_stride = table_row_stride(p.nf, p.nx, p.ny, p.nt);
       const float2* rows = reinterpret_cast<const float2*>(p.ws + p.off_prop);
       const float2* nls = reinterpret_cast<const float2*>(p.ws + p.off_nl);
-      for (int pass = 0; pass < 3; ++pass) {
-        const int ax = brahms::detail::pass_axis(p, pass);
+      const brahms::detail::StepPasses sp = brahms::detail::step_passes(p, true);
+      for (int pass = 0; pass < sp.n; ++pass) {
+        const int ax = sp.ax[pass];
         const int len = ax == AX_X ? p.nx : (ax == AX_Y ? p.ny : p.nt);
         for (int s = 0; s < kChunk; ++s) {
           PassArgs a{};
@@ -208,6 +224,7 @@ brahms_status upload_descriptors(brahms_batch_s& b) {
           a.prop = r;
           a.field_stride = per_field;
           a.nl = nls + (size_t(s) * 2 + (pass == 0 ? 0 : 1)) * p.nf * kNlCoef;
+          a.nl2 = nls + (size_t(s) * 2 + 1) * p.nf * kNlCoef;
           a.nx = p.nx; a.ny = p.ny; a.nt = p.nt;
           for (int j = 0; j < 3; ++j) {
             a.f[j] = p.fields[j];
@@ -254,7 +271,8 @@ brahms_status upload_descriptors(brahms_batch_s& b) {
 }
 
 // One launch group on stream st: per 64-step chunk, one batched table launch
-// and then three batched pass launches per step.
+// and then the batched pass launches of each step (three, fewer when an axis
+// of length 1 is left out).
 brahms_status enqueue_group(brahms_batch_s& b, const brahms_batch_s::Group& g, hipStream_t st) {
   {
     const brahms_plan_s& p0 = *b.plans[g.members[0]];
@@ -269,11 +287,12 @@ brahms_status enqueue_group(brahms_batch_s& b, const brahms_batch_s::Group& g, h
                          st, targs);
       HIP_TRY(hipGetLastError());
       const int cnt = std::min(kChunk, g.max_steps - c * kChunk);
+      const brahms::detail::StepPasses sp = brahms::detail::step_passes(p0, true);
       for (int s = 0; s < cnt; ++s) {
         const long long step = (long long)c * kChunk + s;
-        for (int pass = 0; pass < 3; ++pass) {
-          const int ax = brahms::detail::pass_axis(p0, pass);
-          const int nl = pass == 0 ? NL_BEFORE : (pass == 2 ? NL_AFTER : NL_NONE);
+        for (int pass = 0; pass < sp.n; ++pass) {
+          const int ax = sp.ax[pass];
+          const int nl = sp.nl[pass];
           const PassArgs* d = reinterpret_cast<const PassArgs*>(b.ws + b.off_desc + g.desc_off) +
                               (size_t(pass) * kChunk + s) * m;
           dispatch_group_pass(g.axis_len[ax], ax, nl, g, st, d, step);

@@ -95,6 +95,23 @@ void launch_nl(int nf, int nl, bool full, dim3 grid, hipStream_t st, const PassA
   else launch_nl_nf<N1, N2, AX, 2>(nl, full, grid, st, a);
 }
 
+// Half-step modes without the transverse map: y passes that carry a
+// half-step (nt = 1) and the single tau pass of a plane wave (NL_BOTH).
+template <int N1, int N2, int AX, int NF>
+void launch_plain_nl_nf(int nl, bool full, dim3 grid, hipStream_t st, const PassArgs& a) {
+  switch (nl) {
+    case NL_BEFORE: launch_pass<N1, N2, AX, NF, NL_BEFORE>(full, grid, st, a); break;
+    case NL_AFTER: launch_pass<N1, N2, AX, NF, NL_AFTER>(full, grid, st, a); break;
+    default: launch_pass<N1, N2, AX, NF, NL_BOTH>(full, grid, st, a); break;
+  }
+}
+
+template <int N1, int N2, int AX>
+void launch_plain_nl(int nf, int nl, bool full, dim3 grid, hipStream_t st, const PassArgs& a) {
+  if (nf == 3) launch_plain_nl_nf<N1, N2, AX, 3>(nl, full, grid, st, a);
+  else launch_plain_nl_nf<N1, N2, AX, 2>(nl, full, grid, st, a);
+}
+
 // One pass along `axis`; nl says where the RK4 half-step goes (NL_NONE only
 // for the y pass, which is always the middle pass of a step).
 template <int N1, int N2>
@@ -108,14 +125,20 @@ hipError_t launch_axis(int axis, int nl, int nf, const brahms_plan_s& p, PassArg
     launch_nl<N1, N2, AX_X>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
   } else if (axis == AX_Y) {
     const long lines = long(p.nx) * p.nt;
-    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(nf));
-    launch_pass<N1, N2, AX_Y, 1, NL_NONE>(lines % G::LPB == 0, grid, p.stream, a);
+    if (nl == NL_NONE) {
+      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(nf));
+      launch_pass<N1, N2, AX_Y, 1, NL_NONE>(lines % G::LPB == 0, grid, p.stream, a);
+    } else {
+      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
+      launch_plain_nl<N1, N2, AX_Y>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
+    }
   } else {
     const long lines = long(p.nx) * p.ny;
     const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
     a.tile_mul = tile_multiplier(grid.x);
     a.tiles = grid.x;
-    launch_nl<N1, N2, AX_T>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
+    if (nl == NL_BOTH) launch_plain_nl<N1, N2, AX_T>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
+    else launch_nl<N1, N2, AX_T>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
   }
   return hipGetLastError();
 }
@@ -273,6 +296,45 @@ int pass_axis(const brahms_plan_s& p, int k) {
   return p.order == 0 ? int(AX_T) : int(AX_X);
 }
 
+StepPasses step_passes(const brahms_plan_s& p, bool batched) {
+  StepPasses s{};
+  if (long_tau(p)) {
+    const int ax[5] = {AX_X, AX_Y, AX_TAF, AX_TB, AX_TAI};
+    s.n = 5;
+    for (int k = 0; k < 5; ++k) {
+      s.ax[k] = ax[k];
+      s.nl[k] = k == 0 ? NL_BEFORE : (k == 4 ? NL_AFTER : NL_NONE);
+    }
+    return s;
+  }
+  // A length-1 axis pass is the identity transform times that axis's
+  // propagator entry at zero frequency: exactly 1 along x and y, and along
+  // tau unless a field has loss (exp(-alpha dz / 2) sits in the tau table).
+  const bool no_map = p.dk_map.empty();
+  bool lossless = true;
+  for (int j = 0; j < p.nf; ++j) lossless = lossless && p.fp[j].alpha == 0.0;
+  if (no_map && p.nx == 1 && p.ny == 1 && p.nt > 1) {
+    s.n = 1;
+    s.ax[0] = AX_T;
+    s.nl[0] = NL_BOTH;
+    return s;
+  }
+  if (batched && no_map && lossless && p.nt == 1 && p.nx > 1 && p.ny > 1) {
+    s.n = 2;
+    s.ax[0] = p.order == 0 ? int(AX_X) : int(AX_Y);
+    s.ax[1] = p.order == 0 ? int(AX_Y) : int(AX_X);
+    s.nl[0] = NL_BEFORE;
+    s.nl[1] = NL_AFTER;
+    return s;
+  }
+  s.n = 3;
+  for (int k = 0; k < 3; ++k) {
+    s.ax[k] = pass_axis(p, k);
+    s.nl[k] = k == 0 ? NL_BEFORE : (k == 2 ? NL_AFTER : NL_NONE);
+  }
+  return s;
+}
+
 namespace {
 brahms_status map_table(brahms_plan_s& p, long long n0, int count);
 }  // namespace
@@ -361,16 +423,13 @@ brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io) {
   if (map && p.map_rows == 1)
     if (brahms_status st = map_table(p, p.table_n0 + row, 1)) return st;
   const size_t map_row = map ? size_t(p.map_rows == 1 ? 0 : row) * 5 * p.dk_map.size() : 0;
-  // pass order of the step: the first pass carries the first RK4 half-step,
-  // the last pass the second one (the axis operators commute).  A long tau
-  // axis takes three passes: x, y, tau-b, tau-a, inverse tau-b.
-  const bool longt = detail::long_tau(p);
-  const int npass = longt ? 5 : 3;
-  const int long_axes[5] = {AX_X, AX_Y, AX_TAF, AX_TB, AX_TAI};
-  for (int k = 0; k < npass; ++k) {
-    const int ax = longt ? long_axes[k] : pass_axis(p, k);
-    const bool first = k == 0, last = k == npass - 1;
-    int nlmode = first ? NL_BEFORE : (last ? NL_AFTER : NL_NONE);
+  // the first pass carries the first RK4 half-step, the last pass the second
+  // one (the axis operators commute)
+  const StepPasses sp = step_passes(p, false);
+  for (int k = 0; k < sp.n; ++k) {
+    const int ax = sp.ax[k];
+    const bool first = k == 0, last = k == sp.n - 1;
+    int nlmode = sp.nl[k];
     PassArgs a = pass_args(p, row, ax);
     if (map && nlmode != NL_NONE) {
       nlmode |= NL_MAP;
@@ -383,6 +442,7 @@ brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io) {
       a.pre[j] = last ? io.pre[j] : nullptr;
     }
     a.nl = nl_coefficients(p, row, first ? 0 : 1);
+    a.nl2 = nl_coefficients(p, row, 1);
     if (brahms_status st = timed_dispatch(p, ax, nlmode, a)) return st;
   }
   return BRAHMS_OK;

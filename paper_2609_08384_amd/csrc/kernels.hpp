@@ -37,7 +37,8 @@ enum Axis { AX_X = 0, AX_Y = 1, AX_T = 2,
 constexpr int kMaxLongT = 4096;   // longest tau axis (entries of the staged table)
 
 __host__ __device__ constexpr bool long_tau_kind(int ax) { return ax >= AX_TAF; }
-enum NlMode { NL_NONE = 0, NL_BEFORE = 1, NL_AFTER = 2 };
+enum NlMode { NL_NONE = 0, NL_BEFORE = 1, NL_AFTER = 2,
+              NL_BOTH = 3 };   // both half-steps in one pass (the only pass of a step)
 // Added to NL_BEFORE / NL_AFTER: the mismatch phase also has a transverse
 // part (a per-(x, y) table of exp(i m(x, y) Psi(z)) for each RK4 stage).
 constexpr int NL_MAP = 4;
@@ -52,6 +53,7 @@ struct PassArgs {
   const float2* prop;    // this step's propagators, field j's table of this
                          // axis at prop + j * field_stride + axis_off
   const float2* nl;      // RK4 coefficients of this half-step, [nf][6]
+  const float2* nl2;     // NL_BOTH: those of the second half-step
   const DftConsts* consts;  // this step's register-DFT constants
   int nx, ny, nt;
   int axis_off, field_stride;
@@ -267,6 +269,8 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
   constexpr bool MAP = (NL & NL_MAP) != 0;     // transverse mismatch map
   constexpr bool NT = (AX == AX_X) ? bool(BRAHMS_NT_X) : bool(BRAHMS_NT_YT);
   constexpr bool LONG = long_tau_kind(AX);
+  static_assert(!(MAP && (NLM == NL_BOTH || AX == AX_Y)),
+                "the transverse map runs only with a half-step per pass on x or tau");
   __shared__ float2 lds[G::LDS_ELEMS];
   __shared__ float2 s_tw[N];
   __shared__ float2 s_prop[LONG ? 1 : NF * N];
@@ -396,7 +400,7 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
   }
   __syncthreads();  // s_tw, s_prop staged
 
-  if constexpr (NLM == NL_BEFORE) {
+  if constexpr ((NLM & NL_BEFORE) != 0) {
 #pragma unroll
     for (int e = 0; e < N1; ++e) {
       float2 y[NF];
@@ -442,7 +446,7 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
       for (int e = 0; e < N1; ++e) v[j][e] = cmul(v[j][e], s_prop[j * N + t + N2 * e]);
       line_fft<N1, N2, true>(v[j], t, lbuf, s_tw, K);
     }
-    if constexpr (NLM != NL_AFTER) {
+    if constexpr ((NLM & NL_AFTER) == 0) {
       if (valid) {
 #pragma unroll
         for (int e = 0; e < N1; ++e) store_field<NT>(fout[j], idx0 + unsigned(e) * estep, v[j][e]);
@@ -450,7 +454,13 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
     }
   }
 
-  if constexpr (NLM == NL_AFTER) {
+  if constexpr ((NLM & NL_AFTER) != 0) {
+    if constexpr (NLM == NL_BOTH) {
+#pragma unroll
+      for (int j = 0; j < NF; ++j)
+#pragma unroll
+        for (int c = 0; c < kNlCoef; ++c) co[j][c] = wave_uniform(args.nl2[j * kNlCoef + c]);
+    }
     if (args.pre[0] != nullptr && valid) {
 #pragma unroll
       for (int j = 0; j < NF; ++j)
@@ -493,17 +503,18 @@ __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass(PassArgs 
 }
 
 // One pass over a group of problems of the same shape (a batch): descs[i]
-// describes problem i at this step; x/tau passes take the problem from
-// blockIdx.y, the y pass from blockIdx.z / nf.  Problems whose own step count
+// describes problem i at this step; passes over all fields take the problem
+// from blockIdx.y, linear y passes (one field per block) from blockIdx.z / nf.  Problems whose own step count
 // is reached (step >= nz) leave at once.
 template <int N1, int N2, int AX, int NF, int NL, bool FULL>
 __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass_batched(
     const PassArgs* descs, long long step, int nf) {
-  const unsigned inst = AX == AX_Y ? blockIdx.z / unsigned(nf) : blockIdx.y;
+  // linear y passes take one field per block: problem and field from blockIdx.z
+  constexpr bool per_field = NF == 1 && AX == AX_Y;
+  const unsigned inst = per_field ? blockIdx.z / unsigned(nf) : blockIdx.y;
   const PassArgs& a = descs[inst];
   if (step >= a.nz) return;
-  axis_pass_body<N1, N2, AX, NF, NL, FULL>(a, blockIdx.x,
-                                           AX == AX_Y ? int(blockIdx.z % unsigned(nf)) : 0);
+  axis_pass_body<N1, N2, AX, NF, NL, FULL>(a, blockIdx.x, per_field ? int(blockIdx.z % unsigned(nf)) : 0);
 }
 
 // ---------------------------------------------------------------------------

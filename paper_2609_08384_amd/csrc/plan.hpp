@@ -110,6 +110,19 @@ struct StepIO {
 
 // Fill table rows 0..count-1 for steps n0..n0+count-1.
 brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count);
+// The passes of one z-step in order: axis (AX_*) and RK4 mode (NL_*) of
+// each.  Three passes in general; passes along an axis of length 1 are left
+// out when they would multiply by exactly 1 (so the result is unchanged bit
+// for bit): nx = ny = 1 takes one tau pass with both half-steps; in a batch,
+// nt = 1 with no loss and no transverse map takes x and y passes (a single
+// CW problem keeps its tau pass, whose many short lines are its parallelism);
+// a long tau axis takes five passes.
+struct StepPasses {
+  int n;
+  int ax[5];
+  int nl[5];
+};
+StepPasses step_passes(const brahms_plan_s& p, bool batched);
 // One z-step with the tables of `row`.
 brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io);
 // The axis of the k-th pass of a step (k = 0, 1, 2) under the plan's order.

@@ -20,7 +20,8 @@ def _case(nf, shape, nz, seed, profile=True):
             dict(kappa=0.8, diffraction=0.5, tan_rho=-0.2, delay=0.2, k2=-0.6),
             dict(kappa=0.6, diffraction=1.4, delay=0.5, k2=0.3)]
     fields = [inputs.FieldSpec(**base[j]) for j in range(nf)]
-    init = inputs.random_fields(rng, nf, nx, ny, nt, scale=0.8, smooth=min(nx, ny, nt) / 2.5)
+    init = inputs.random_fields(rng, nf, nx, ny, nt, scale=0.8,
+                                smooth=min(d for d in shape if d > 1) / 2.5)
     dk = (2.0 + 0.7 * rng.standard_normal(nz)) if profile else None
     wl = inputs.Workload("adj", nx, ny, nt, nf, nz, 1.0 / nz, fields, dk_const=1.7, dk=dk)
     wl.init = init
@@ -54,7 +55,10 @@ def _oracle_grads(wl):
 
 @pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("nf,shape,nz,every", [(2, (16, 16, 8), 12, 5), (3, (8, 16, 16), 9, 4),
-                                                (2, (32, 8, 16), 7, 7)])
+                                                (2, (32, 8, 16), 7, 7),
+                                                # reduced dimensions: the forward leaves out the
+                                                # passes along length-1 axes, the reverse sweep not
+                                                (2, (32, 16, 1), 10, 4), (3, (1, 1, 64), 11, 5)])
 def test_adjoint_matches_oracle(nf, shape, nz, every, order):
     wl = _case(nf, shape, nz, seed=nf * 10 + nz)
     jg, g, gdk, _ = _gpu_grads(wl, every, order)
