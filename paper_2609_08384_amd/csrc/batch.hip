@@ -107,7 +107,8 @@ size_t descriptor_bytes(brahms_batch_s& b) {
   size_t off = 0;
   for (auto& g : b.groups) {
     g.desc_off = off;
-    off = align_up(off + sizeof(PassArgs) * 3 * kChunk * g.members.size());
+    const int npass = brahms::detail::step_passes(*b.plans[g.members[0]], true).n;
+    off = align_up(off + sizeof(PassArgs) * size_t(npass) * kChunk * g.members.size());
   }
   return off;
 }
@@ -171,6 +172,40 @@ void launch_group_pass(int axis, int nl, const brahms_batch_s::Group& g, hipStre
     const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), m);
     launch_batched_nl<N1, N2, AX_T>(g.nf, nl, lines % G::LPB == 0, grid, st, d, step);
   }
+}
+
+// The three passes of a long tau axis (nt = A B) over a group.
+template <int N1, int N2, int AX>
+void launch_group_long(int nl, const brahms_batch_s::Group& g, hipStream_t st, const PassArgs* d,
+                       long long step) {
+  using G = LineGeom<N1, N2>;
+  const unsigned m = unsigned(g.members.size());
+  const long lines = long(g.axis_len[0]) * g.axis_len[1] * (g.axis_len[2] / G::N);
+  const bool full = lines % G::LPB == 0;
+  if constexpr (AX == AX_TAI) {
+    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), m);
+    launch_batched_nl<N1, N2, AX_TAI>(g.nf, nl, full, grid, st, d, step);
+  } else {
+    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(g.nf) * m);
+    launch_batched<N1, N2, AX, 1, NL_NONE>(full, grid, st, d, step, g.nf);
+  }
+}
+
+template <int AX>
+void dispatch_group_long_len(int len, int nl, const brahms_batch_s::Group& g, hipStream_t st,
+                             const PassArgs* d, long long step) {
+  if (len == 16) launch_group_long<4, 4, AX>(nl, g, st, d, step);
+  else if (len == 32) launch_group_long<8, 4, AX>(nl, g, st, d, step);
+  else launch_group_long<8, 8, AX>(nl, g, st, d, step);
+}
+
+void dispatch_group_long(int axis, int nl, const brahms_batch_s::Group& g, hipStream_t st,
+                         const PassArgs* d, long long step) {
+  const int nt = g.axis_len[2];
+  const int na = brahms::detail::long_tau_a(nt);   // the b passes have length nt / na
+  if (axis == AX_TAF) dispatch_group_long_len<AX_TAF>(nt / na, nl, g, st, d, step);
+  else if (axis == AX_TB) dispatch_group_long_len<AX_TB>(na, nl, g, st, d, step);
+  else dispatch_group_long_len<AX_TAI>(nt / na, nl, g, st, d, step);
 }
 
 void dispatch_group_pass(int len, int axis, int nl, const brahms_batch_s::Group& g, hipStream_t st,
@@ -295,7 +330,8 @@ brahms_status enqueue_group(brahms_batch_s& b, const brahms_batch_s::Group& g, h
           const int nl = sp.nl[pass];
           const PassArgs* d = reinterpret_cast<const PassArgs*>(b.ws + b.off_desc + g.desc_off) +
                               (size_t(pass) * kChunk + s) * m;
-          dispatch_group_pass(g.axis_len[ax], ax, nl, g, st, d, step);
+          if (long_tau_kind(ax)) dispatch_group_long(ax, nl, g, st, d, step);
+          else dispatch_group_pass(g.axis_len[ax], ax, nl, g, st, d, step);
           HIP_TRY(hipGetLastError());
         }
       }
@@ -377,10 +413,10 @@ brahms_status brahms_batch_create(int n, const int* shapes, const brahms_params*
       brahms_batch_destroy(b);
       return st;
     }
-    if (!p->dk_map.empty() || brahms::detail::long_tau(*p)) {
+    if (!p->dk_map.empty()) {
       brahms_plan_destroy(p);
       brahms_batch_destroy(b);
-      return fail(BRAHMS_E_UNSUPPORTED, "batches take no transverse dk map and no nt > 256");
+      return fail(BRAHMS_E_UNSUPPORTED, "batches take no transverse dk map");
     }
     if (!p->dk.empty() && nsteps[i] > (int)p->dk.size()) {
       brahms_plan_destroy(p);

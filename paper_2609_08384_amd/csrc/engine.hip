@@ -159,10 +159,6 @@ hipError_t dispatch_axis(int n, int axis, int nl, int nf, const brahms_plan_s& p
   }
 }
 
-// Line length of a long-tau pass: B for the b passes, A for the a pass
-// (512 = 32 x 16, 1024 = 32 x 32, 2048 = 64 x 32, 4096 = 64 x 64).
-int long_tau_a(int nt) { return nt >= 2048 ? 64 : 32; }
-
 template <int N1, int N2, int AX>
 hipError_t launch_long(int nl, int nf, const brahms_plan_s& p, PassArgs a) {
   using G = LineGeom<N1, N2>;
@@ -191,7 +187,7 @@ hipError_t dispatch_long_len(int len, int nl, int nf, const brahms_plan_s& p, co
 }
 
 hipError_t dispatch_long(int axis, int nl, int nf, const brahms_plan_s& p, const PassArgs& a) {
-  const int na = long_tau_a(p.nt);
+  const int na = brahms::detail::long_tau_a(p.nt);
   const int nb = p.nt / na;
   if (axis == AX_TAF) return dispatch_long_len<AX_TAF>(nb, nl, nf, p, a);
   if (axis == AX_TB) return dispatch_long_len<AX_TB>(na, nl, nf, p, a);

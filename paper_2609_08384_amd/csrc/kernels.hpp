@@ -504,13 +504,14 @@ __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass(PassArgs 
 
 // One pass over a group of problems of the same shape (a batch): descs[i]
 // describes problem i at this step; passes over all fields take the problem
-// from blockIdx.y, linear y passes (one field per block) from blockIdx.z / nf.  Problems whose own step count
+// from blockIdx.y, passes with one field per block from blockIdx.z / nf.  Problems whose own step count
 // is reached (step >= nz) leave at once.
 template <int N1, int N2, int AX, int NF, int NL, bool FULL>
 __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass_batched(
     const PassArgs* descs, long long step, int nf) {
-  // linear y passes take one field per block: problem and field from blockIdx.z
-  constexpr bool per_field = NF == 1 && AX == AX_Y;
+  // linear y and long-tau passes take one field per block: problem and field
+  // from blockIdx.z
+  constexpr bool per_field = NF == 1 && (AX == AX_Y || long_tau_kind(AX));
   const unsigned inst = per_field ? blockIdx.z / unsigned(nf) : blockIdx.y;
   const PassArgs& a = descs[inst];
   if (step >= a.nz) return;

@@ -69,6 +69,9 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // A tau axis longer than one line transform (three passes per step).
 inline bool long_tau(const brahms_plan_s& p) { return p.nt > 256; }
+// Its split nt = A B (the a transforms have length A, the b transforms B):
+// 512 = 32 x 16, 1024 = 32 x 32, 2048 = 64 x 32, 4096 = 64 x 64.
+inline int long_tau_a(int nt) { return nt >= 2048 ? 64 : 32; }
 
 brahms_status fail(brahms_status st, const std::string& msg);
 

@@ -197,8 +197,3 @@ def test_long_tau_host_checks(lib):
     lib.brahms_plan_destroy(h)
     assert _create(lib, 512, 8, 8, 2, c)[0] == brahms.BRAHMS_E_UNSUPPORTED   # only tau may be long
     assert _create(lib, 8, 8, 8192, 2, c)[0] == brahms.BRAHMS_E_UNSUPPORTED
-    shapes = (ctypes.c_int * 4)(8, 8, 2048, 2)
-    params = (brahms.ParamsC * 1)(c)
-    steps = (ctypes.c_int * 1)(3)
-    hb = ctypes.c_void_p()
-    assert lib.brahms_batch_create(1, shapes, params, steps, None, ctypes.byref(hb)) == brahms.BRAHMS_E_UNSUPPORTED

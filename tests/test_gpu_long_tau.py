@@ -84,3 +84,31 @@ def test_paper_grid_opg_64x64x1024():
     ref = ssfm.propagate([to_torch(a) for a in wl.init], oracle_problem(wl), wl.nz)
     for a, r in zip(out, ref):
         assert rel_l2(a.cpu().numpy(), r.numpy()) < 1e-5
+
+
+@pytest.mark.parametrize("group_max", [0, 1])
+def test_long_tau_in_batches(group_max):
+    """Long-tau problems (nt = 512, 1024, 4096) in a batch with an ordinary
+    one: each bitwise equal to the same problem run alone, and one against
+    the oracle."""
+    rng = np.random.default_rng(21)
+    wls = []
+    for (nx, ny, nt), nf, nz in [((8, 4, 1024), 2, 9), ((4, 4, 4096), 3, 7), ((8, 4, 1024), 2, 5),
+                                 ((16, 8, 512), 3, 11), ((16, 16, 16), 2, 8)]:
+        wl = inputs.Workload("b", nx, ny, nt, nf, nz, 1.0 / nz, _fields_spec(nf, 1.5, rng), dk_const=0.7)
+        wl.init = _pulse_fields(rng, nf, nx, ny, nt, 0.8)
+        wls.append(wl)
+    batch = brahms.Batch([(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls])
+    batch.set_schedule(group_max)
+    fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
+    batch.bind(fields)
+    batch.run()
+    torch.cuda.synchronize()
+    batch.destroy()
+    for w, fs in zip(wls, fields):
+        alone = brahms.run_workload(w, device=DEV)
+        for a, b in zip(fs, alone):
+            assert torch.equal(a, b), (w.nx, w.ny, w.nt)
+    ref = ssfm.propagate([to_torch(a) for a in wls[1].init], oracle_problem(wls[1]), wls[1].nz)
+    for a, r in zip(fields[1], ref):
+        assert rel_l2(a.cpu().numpy(), r.numpy()) < 1e-5
