@@ -144,6 +144,11 @@ brahms_status brahms_plan_destroy(brahms_plan plan);
  * pass the second one.
  *   pass_order 0: x pass, y pass, tau pass (default)
  *   pass_order 1: tau pass, y pass, x pass
+ *   pass_order 2: x pass, tau pass, y pass (tau linear, one field per block)
+ *   pass_order 3: y pass, tau pass, x pass
+ *   (orders 2 and 3 act as 0 and 1 for a plan with a transverse dk map; the
+ *   adjoint runs with orders 0 and 1 only; a tau axis longer than 256 always
+ *   takes x, y and its three tau passes)
  *   graph 1: brahms_step replays whole 64-step chunks (tables and passes) from
  *     a hipGraph captured once per binding and schedule (bitwise the same
  *     result; removes the per-launch host cost).  Chunks that record timing,

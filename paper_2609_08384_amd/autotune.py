@@ -18,7 +18,7 @@ import torch
 
 from . import brahms
 
-CANDIDATES = [{"pass_order": o, "graph": g} for g in (0, 1) for o in (0, 1)]
+CANDIDATES = [{"pass_order": o, "graph": g} for g in (0, 1) for o in (0, 1, 2, 3)]
 _lock = threading.Lock()
 _memo: Dict[str, dict] = {}
 

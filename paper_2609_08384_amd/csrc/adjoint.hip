@@ -208,6 +208,7 @@ brahms_status brahms_adjoint_workspace_size(brahms_plan plan, int nsteps, int ch
   if (bytes == nullptr) return fail(BRAHMS_E_INVALID_ARG, "bytes is NULL");
   if (!plan->dk_map.empty()) return fail(BRAHMS_E_UNSUPPORTED, "no adjoint with a transverse dk map");
   if (brahms::detail::long_tau(*plan)) return fail(BRAHMS_E_UNSUPPORTED, "no adjoint with nt > 256");
+  if (plan->order > 1) return fail(BRAHMS_E_UNSUPPORTED, "the adjoint runs with pass order 0 or 1");
   if (nsteps < 1 || checkpoint_every < 1 || checkpoint_every > kChunk)
     return fail(BRAHMS_E_INVALID_ARG, "need nsteps >= 1 and 1 <= checkpoint_every <= 64");
   *bytes = adj_layout(*plan, nsteps, checkpoint_every).total;
@@ -221,6 +222,7 @@ brahms_status brahms_adjoint_forward(brahms_plan plan, int nsteps, int checkpoin
   if (!p.bound) return fail(BRAHMS_E_STATE, "brahms_adjoint_forward before brahms_plan_bind");
   if (!p.dk_map.empty()) return fail(BRAHMS_E_UNSUPPORTED, "no adjoint with a transverse dk map");
   if (brahms::detail::long_tau(p)) return fail(BRAHMS_E_UNSUPPORTED, "no adjoint with nt > 256");
+  if (p.order > 1) return fail(BRAHMS_E_UNSUPPORTED, "the adjoint runs with pass order 0 or 1");
   if (adj_workspace == nullptr || reinterpret_cast<uintptr_t>(adj_workspace) % 256 != 0)
     return fail(BRAHMS_E_INVALID_ARG, "adjoint workspace must be a 256-byte aligned device pointer");
   if (nsteps < 1 || checkpoint_every < 1 || checkpoint_every > kChunk)

@@ -169,8 +169,13 @@ void launch_group_pass(int axis, int nl, const brahms_batch_s::Group& g, hipStre
     }
   } else {
     const long lines = long(nx) * ny;
-    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), m);
-    launch_batched_nl<N1, N2, AX_T>(g.nf, nl, lines % G::LPB == 0, grid, st, d, step);
+    if (nl == NL_NONE) {
+      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(g.nf) * m);
+      launch_batched<N1, N2, AX_T, 1, NL_NONE>(lines % G::LPB == 0, grid, st, d, step, g.nf);
+    } else {
+      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), m);
+      launch_batched_nl<N1, N2, AX_T>(g.nf, nl, lines % G::LPB == 0, grid, st, d, step);
+    }
   }
 }
 
@@ -448,8 +453,8 @@ brahms_status brahms_batch_set_schedule(brahms_batch b, int group_max, const int
   if (group_max < 0) return fail(BRAHMS_E_INVALID_ARG, "group_max < 0");
   if (pass_order != nullptr)
     for (int i = 0; i < b->n; ++i)
-      if (pass_order[i] != 0 && pass_order[i] != 1)
-        return fail(BRAHMS_E_INVALID_ARG, "pass_order entries must be 0 or 1");
+      if (pass_order[i] < 0 || pass_order[i] > 3)
+        return fail(BRAHMS_E_INVALID_ARG, "pass_order entries must be 0, 1, 2 or 3");
   b->group_max = group_max;
   if (pass_order != nullptr)
     for (int i = 0; i < b->n; ++i) b->plans[i]->order = pass_order[i];

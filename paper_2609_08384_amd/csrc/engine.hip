@@ -137,8 +137,15 @@ hipError_t launch_axis(int axis, int nl, int nf, const brahms_plan_s& p, PassArg
     const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
     a.tile_mul = tile_multiplier(grid.x);
     a.tiles = grid.x;
-    if (nl == NL_BOTH) launch_plain_nl<N1, N2, AX_T>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
-    else launch_nl<N1, N2, AX_T>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
+    if (nl == NL_NONE) {
+      // linear tau pass (orders 2 and 3): one field per block
+      const dim3 gridf(grid.x, 1, unsigned(nf));
+      launch_pass<N1, N2, AX_T, 1, NL_NONE>(lines % G::LPB == 0, gridf, p.stream, a);
+    } else if (nl == NL_BOTH) {
+      launch_plain_nl<N1, N2, AX_T>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
+    } else {
+      launch_nl<N1, N2, AX_T>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
+    }
   }
   return hipGetLastError();
 }
@@ -287,9 +294,13 @@ const float2* nl_coefficients(const brahms_plan_s& p, int row, int half) {
 }
 
 int pass_axis(const brahms_plan_s& p, int k) {
-  if (k == 1) return AX_Y;
-  if (k == 0) return p.order == 0 ? int(AX_X) : int(AX_T);
-  return p.order == 0 ? int(AX_T) : int(AX_X);
+  // orders 0: x y tau, 1: tau y x, 2: x tau y, 3: y tau x
+  static const int axes[4][3] = {{AX_X, AX_Y, AX_T}, {AX_T, AX_Y, AX_X},
+                                 {AX_X, AX_T, AX_Y}, {AX_Y, AX_T, AX_X}};
+  // the transverse map runs only on x and tau passes: orders 2 and 3 fall
+  // back to 0 and 1 for a plan with a map
+  const int order = p.dk_map.empty() ? p.order : (p.order & 1);
+  return axes[order][k];
 }
 
 StepPasses step_passes(const brahms_plan_s& p, bool batched) {
@@ -317,8 +328,9 @@ StepPasses step_passes(const brahms_plan_s& p, bool batched) {
   }
   if (batched && no_map && lossless && p.nt == 1 && p.nx > 1 && p.ny > 1) {
     s.n = 2;
-    s.ax[0] = p.order == 0 ? int(AX_X) : int(AX_Y);
-    s.ax[1] = p.order == 0 ? int(AX_Y) : int(AX_X);
+    const bool x_first = p.order == 0 || p.order == 2;
+    s.ax[0] = x_first ? int(AX_X) : int(AX_Y);
+    s.ax[1] = x_first ? int(AX_Y) : int(AX_X);
     s.nl[0] = NL_BEFORE;
     s.nl[1] = NL_AFTER;
     return s;
@@ -736,8 +748,8 @@ brahms_status brahms_set_z(brahms_plan plan, double z) {
 brahms_status brahms_plan_set_schedule(brahms_plan plan, const brahms_schedule* sched) {
   if (brahms_status st = check_plan(plan)) return st;
   if (sched == nullptr) return fail(BRAHMS_E_INVALID_ARG, "schedule is NULL");
-  if (sched->pass_order != 0 && sched->pass_order != 1)
-    return fail(BRAHMS_E_INVALID_ARG, "pass_order must be 0 or 1");
+  if (sched->pass_order < 0 || sched->pass_order > 3)
+    return fail(BRAHMS_E_INVALID_ARG, "pass_order must be 0, 1, 2 or 3");
   if (sched->graph != 0 && sched->graph != 1) return fail(BRAHMS_E_INVALID_ARG, "graph must be 0 or 1");
   if (plan->order != sched->pass_order || plan->use_graph != (sched->graph != 0)) drop_chunk_graph(*plan);
   plan->order = sched->pass_order;

@@ -498,7 +498,7 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
 template <int N1, int N2, int AX, int NF, int NL, bool FULL>
 __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass(PassArgs args) {
   // passes with one field per block take it from blockIdx.z
-  constexpr bool per_field = NF == 1 && (AX == AX_Y || long_tau_kind(AX));
+  constexpr bool per_field = NF == 1 && (AX == AX_Y || AX == AX_T || long_tau_kind(AX));
   axis_pass_body<N1, N2, AX, NF, NL, FULL>(args, blockIdx.x, per_field ? int(blockIdx.z) : 0);
 }
 
@@ -511,7 +511,7 @@ __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass_batched(
     const PassArgs* descs, long long step, int nf) {
   // linear y and long-tau passes take one field per block: problem and field
   // from blockIdx.z
-  constexpr bool per_field = NF == 1 && (AX == AX_Y || long_tau_kind(AX));
+  constexpr bool per_field = NF == 1 && (AX == AX_Y || AX == AX_T || long_tau_kind(AX));
   const unsigned inst = per_field ? blockIdx.z / unsigned(nf) : blockIdx.y;
   const PassArgs& a = descs[inst];
   if (step >= a.nz) return;

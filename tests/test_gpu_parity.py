@@ -107,7 +107,7 @@ def test_plane_wave_opa():
     assert np.abs(i - wi).max() < _accumulation_bound(2 * nz, abs(wi)) + 1e-7 * abs(wi)
 
 
-@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
 @pytest.mark.parametrize("nf,shape", [(2, (32, 32, 32)), (3, (32, 32, 32)), (3, (64, 16, 96)),
                                       (2, (96, 96, 4)), (3, (16, 128, 64))])
 def test_coupled_steps_random(nf, shape, order):
@@ -133,7 +133,7 @@ def test_dk_profile_matches_oracle():
         assert rel_l2(g[j], o[j]) < 5e-6
 
 
-@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
 def test_shg32_full_run(order):
     """SHG 32^3, 100 steps (the small benchmark workload): <= 1e-5 per field."""
     wl = inputs.shg32()
@@ -199,7 +199,7 @@ def _check_golden(out, name, tol):
     return g
 
 
-@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
 def test_sfg128_full_run_vs_oracle(order):
     """SFG 128^3, 500 steps, pump depletion: <= 2e-5 per field."""
     wl = inputs.sfg128()
@@ -209,7 +209,7 @@ def test_sfg128_full_run_vs_oracle(order):
     assert np.allclose(e, g["energies"], rtol=4e-5)
 
 
-@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
 def test_opg256_first_steps_vs_oracle(order):
     """OPG 256^3 (the benchmark workload), first 10 steps at full size, in the
     launch configurations the benchmark may time: <= 3e-5 per field."""
@@ -218,7 +218,7 @@ def test_opg256_first_steps_vs_oracle(order):
     _check_golden(out, "opg256_10", 3e-5)
 
 
-@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
 def test_opg256_full_run_vs_oracle(order):
     """OPG 256^3, all 1000 steps (the benchmark workload end to end, in both
     launch configurations the benchmark may time): <= 3e-5 per field on the
@@ -233,7 +233,7 @@ def test_opg256_full_run_vs_oracle(order):
     assert np.allclose(e, g["energies"], rtol=6e-5)
 
 
-@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
 def test_graph_schedule_is_bitwise_eager(order):
     """Whole 64-step chunks replayed from the plan's hipGraph give the same
     bits as launch-by-launch stepping: ragged call lengths, a per-step dk

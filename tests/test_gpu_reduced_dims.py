@@ -90,7 +90,7 @@ def test_reduced_dims_batched_equal_single_runs(group_max):
     wls += inputs.plane_wave_pulse_sweep(count=3)
     for w in wls[2:]:
         w.nz = min(w.nz, 40)
-    orders = [k % 2 for k in range(len(wls))]
+    orders = [k % 4 for k in range(len(wls))]
     out = _batch_run(wls, group_max, orders)
     for w, fs, o in zip(wls, out, orders):
         alone = brahms.run_workload(w, device=DEV, pass_order=o)

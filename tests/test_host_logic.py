@@ -22,7 +22,7 @@ def fake_tuner(monkeypatch, tmp_path):
     def install(times):
         def measure(nx, ny, nt, nf, params, schedule, device="cuda:0", steps=64, warmup=3):
             calls.append(dict(schedule))
-            return times[(schedule["pass_order"], schedule["graph"])]
+            return times.get((schedule["pass_order"], schedule["graph"]), 10.0)
         monkeypatch.setattr(autotune, "measure", measure)
         return calls
     yield install
@@ -38,14 +38,14 @@ def test_tuner_takes_the_fastest_order_and_caches(fake_tuner, tmp_path):
     best = autotune.tune(32, 32, 32, 2, _params())
     # the graph is not 2 % faster than the best launch-by-launch order
     assert best == {"pass_order": 1, "graph": 0}
-    assert len(calls) == 4
+    assert len(calls) == len(autotune.CANDIDATES)
     with open(os.path.join(str(tmp_path), "schedules.json")) as fh:
         disk = json.load(fh)
     (key, entry), = disk.items()
     assert key == "v2:gfx950:32x32x32:nf2" and entry["schedule"] == best
     autotune._memo.clear()
     assert autotune.tune(32, 32, 32, 2, _params()) == best     # from the disk cache
-    assert len(calls) == 4
+    assert len(calls) == len(autotune.CANDIDATES)
 
 
 def test_tuner_takes_the_graph_when_clearly_faster(fake_tuner):
