@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint and batched-sweep side measurements")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle z-steps in the CPU sample")
-    ap.add_argument("--pass-order", default="auto", choices=["auto", "0", "1"],
+    ap.add_argument("--pass-order", default="auto", choices=["auto", "0", "1", "2", "3"],
                     help="plan schedule: autotuned (default) or a fixed pass order")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain 1 GiB device-to-device copy instead (reference for "
@@ -324,7 +324,9 @@ def batch_ratio(dev):
 KERNEL_SOURCES = ("paper_2609_08384_amd/csrc/kernels.hpp", "paper_2609_08384_amd/csrc/dft.hpp",
                   "paper_2609_08384_amd/csrc/engine.hip")
 NL_OF_PASS = {0: {"x_pass": "before", "y_pass": "none", "t_pass": "after"},
-              1: {"t_pass": "before", "y_pass": "none", "x_pass": "after"}}
+              1: {"t_pass": "before", "y_pass": "none", "x_pass": "after"},
+              2: {"x_pass": "before", "t_pass": "none", "y_pass": "after"},
+              3: {"y_pass": "before", "t_pass": "none", "x_pass": "after"}}
 
 
 def kernel_digest() -> str:
