@@ -4,7 +4,9 @@
 // Forward: the plain z-loop, with the state copied to a checkpoint every K
 // steps.  Backward, one K-step segment at a time from the last: recompute the
 // segment out of place from its checkpoint, keeping every step's input and
-// the input of its second RK4 half-step; then for each step in reverse apply
+// the input of its second RK4 half-step (for K <= 32 on a second stream,
+// into a second set of buffers, while the previous segment is swept back);
+// then for each step in reverse apply
 // the adjoint passes (reverse second half-step + conj-propagator transforms
 // along the last axis, conj-propagator transforms along y, conj-propagator
 // transforms along the first axis + reverse first half-step).  dJ/dPhi at the
@@ -32,12 +34,19 @@ using brahms::detail::kChunk;
 
 namespace {
 
+// Segment buffers come in two sets when a segment fits half of the table
+// ring (every <= 32): the reverse sweep of one segment then runs while the
+// next one is recomputed into the other set, on its own table rows.
 struct AdjLayout {
-  size_t ckpt = 0, seg = 0, pre = 0, parts = 0, dphi = 0, total = 0;
+  size_t ckpt = 0, dphi = 0, total = 0;
+  size_t seg[2] = {0, 0}, pre[2] = {0, 0}, parts[2] = {0, 0};
+  int nsets = 1;
   int nckpt = 0, every = 0, nsteps = 0;
   size_t field_bytes = 0;
   int max_blocks = 0;
 };
+
+constexpr int kSetRows = kChunk / 2;   // table rows of the second set start here
 
 template <int N1, int N2>
 int blocks_of(int axis, const brahms_plan_s& p) {
@@ -70,15 +79,18 @@ AdjLayout adj_layout(const brahms_plan_s& p, int nsteps, int every) {
   L.field_bytes = sizeof(float2) * size_t(p.nx) * p.ny * p.nt;
   const size_t state = align_up(L.field_bytes) * p.nf;
   L.max_blocks = std::max(pass_blocks(AX_X, p), pass_blocks(AX_T, p));
+  L.nsets = (every <= kSetRows && L.nckpt > 1) ? 2 : 1;
   size_t off = 0;
   L.ckpt = off;
   off += state * L.nckpt;
-  L.seg = off;
-  off += state * (every + 1);
-  L.pre = off;
-  off += state * every;
-  L.parts = off;
-  off = align_up(off + sizeof(double) * 3 * L.max_blocks * 2 * every);
+  for (int s = 0; s < L.nsets; ++s) {
+    L.seg[s] = off;
+    off += state * (every + 1);
+    L.pre[s] = off;
+    off += state * every;
+    L.parts[s] = off;
+    off = align_up(off + sizeof(double) * 3 * L.max_blocks * 2 * every);
+  }
   L.dphi = off;
   off = align_up(off + sizeof(double) * 6 * nsteps);
   L.total = off;
@@ -152,11 +164,12 @@ brahms_status copy_state(const brahms_plan_s& p, float2* const* dst, float2* con
 
 // One adjoint pass with an RK4 reverse sweep; its per-block phase
 // derivatives go to slot (row, k == 0 ? 0 : 1) of the segment's partials.
-brahms_status adj_pass(brahms_plan_s& p, const AdjLayout& L, int row, int k, float2* const* g,
-                       float2* const* y) {
+brahms_status adj_pass(brahms_plan_s& p, const AdjLayout& L, int set, int row, int k,
+                       float2* const* g, float2* const* y) {
   const int ax = brahms::detail::pass_axis(p, k);
   const int per_field = p.nx + p.ny + p.nt;
-  const float2* r = brahms::detail::table_row(p, row);
+  const int trow = set * kSetRows + row;
+  const float2* r = brahms::detail::table_row(p, trow);
   AdjArgs a{};
   for (int j = 0; j < 3; ++j) {
     a.g[j] = j < p.nf ? g[j] : nullptr;
@@ -167,9 +180,9 @@ brahms_status adj_pass(brahms_plan_s& p, const AdjLayout& L, int row, int k, flo
   a.consts = reinterpret_cast<const DftConsts*>(r + (p.nf + 1) * per_field);
   a.prop = r;
   a.field_stride = per_field;
-  a.nl = brahms::detail::nl_coefficients(p, row, k == 0 ? 0 : 1);
+  a.nl = brahms::detail::nl_coefficients(p, trow, k == 0 ? 0 : 1);
   a.nx = p.nx; a.ny = p.ny; a.nt = p.nt;
-  double* parts = reinterpret_cast<double*>(p.adj_ws + L.parts);
+  double* parts = reinterpret_cast<double*>(p.adj_ws + L.parts[set]);
   a.dphi_out = parts + (size_t(row) * 2 + (k == 0 ? 0 : 1)) * size_t(L.max_blocks) * 3;
   // exp(-i Phi) on the sum-frequency field, exp(+i Phi) on the others
   if (p.nf == 3) {
@@ -181,20 +194,71 @@ brahms_status adj_pass(brahms_plan_s& p, const AdjLayout& L, int row, int k, flo
   return BRAHMS_OK;
 }
 
-// Run steps s0 .. s0+cnt-1 (table rows 0..cnt-1) out of place through the
-// segment slots, keeping every step's input (slot i) and the input of its
-// second RK4 half-step; the last step writes `last_out` when given.
-brahms_status record_segment(brahms_plan_s& p, const AdjLayout& L, int cnt, float2* const* last_out) {
+// Run steps s0 .. s0+cnt-1 (table rows of the set) out of place through the
+// set's segment slots, keeping every step's input (slot i) and the input of
+// its second RK4 half-step; the last step writes `last_out` when given.
+brahms_status record_segment(brahms_plan_s& p, const AdjLayout& L, int set, int cnt,
+                             float2* const* last_out) {
   for (int i = 0; i < cnt; ++i) {
     brahms::detail::StepIO io{};
     for (int j = 0; j < p.nf; ++j) {
-      io.in[j] = state_field(p.adj_ws + L.seg, L, p, i, j);
-      io.out[j] = (i == cnt - 1 && last_out != nullptr) ? last_out[j]
-                                                        : state_field(p.adj_ws + L.seg, L, p, i + 1, j);
-      io.pre[j] = state_field(p.adj_ws + L.pre, L, p, i, j);
+      io.in[j] = state_field(p.adj_ws + L.seg[set], L, p, i, j);
+      io.out[j] = (i == cnt - 1 && last_out != nullptr)
+                      ? last_out[j]
+                      : state_field(p.adj_ws + L.seg[set], L, p, i + 1, j);
+      io.pre[j] = state_field(p.adj_ws + L.pre[set], L, p, i, j);
     }
-    if (brahms_status st = brahms::detail::launch_step(p, i, io)) return st;
+    if (brahms_status st = brahms::detail::launch_step(p, set * kSetRows + i, io)) return st;
   }
+  return BRAHMS_OK;
+}
+
+// Recompute segment c (steps s0 .. s0+cnt-1) from its checkpoint into a set.
+brahms_status recompute_segment(brahms_plan_s& p, const AdjLayout& L, int c, int set) {
+  const long long s0 = p.adj_n0 + (long long)c * p.adj_every;
+  const int cnt = int(std::min<long long>(p.adj_every, p.adj_n0 + p.adj_nsteps - s0));
+  if (brahms_status st = brahms::detail::refresh_tables(p, s0, cnt, set * kSetRows)) return st;
+  float2* slot0[3] = {nullptr, nullptr, nullptr};
+  float2* ck[3] = {nullptr, nullptr, nullptr};
+  for (int j = 0; j < p.nf; ++j) {
+    slot0[j] = state_field(p.adj_ws + L.seg[set], L, p, 0, j);
+    ck[j] = state_field(p.adj_ws + L.ckpt, L, p, c, j);
+  }
+  if (brahms_status st = copy_state(p, slot0, ck)) return st;
+  return record_segment(p, L, set, cnt, nullptr);
+}
+
+// Reverse sweep over segment c held in a set, then its dJ/dPhi reduction.
+brahms_status reverse_segment(brahms_plan_s& p, const AdjLayout& L, int c, int set, float2* const* g,
+                              double* dphi) {
+  const long long s0 = p.adj_n0 + (long long)c * p.adj_every;
+  const int cnt = int(std::min<long long>(p.adj_every, p.adj_n0 + p.adj_nsteps - s0));
+  for (int i = cnt - 1; i >= 0; --i) {
+    float2* y2[3] = {nullptr, nullptr, nullptr};
+    float2* y0[3] = {nullptr, nullptr, nullptr};
+    for (int j = 0; j < p.nf; ++j) {
+      y2[j] = state_field(p.adj_ws + L.pre[set], L, p, i, j);
+      y0[j] = state_field(p.adj_ws + L.seg[set], L, p, i, j);
+    }
+    if (brahms_status st = adj_pass(p, L, set, i, 2, g, y2)) return st;
+    if (brahms_status st = brahms::detail::launch_linear_pass(p, set * kSetRows + i, AX_Y, g, true))
+      return st;
+    if (brahms_status st = adj_pass(p, L, set, i, 0, g, y0)) return st;
+  }
+  // dJ/dPhi of the segment's steps, in a fixed order
+  const int nb_first = pass_blocks(brahms::detail::pass_axis(p, 0), p);
+  const int nb_last = pass_blocks(brahms::detail::pass_axis(p, 2), p);
+  hipLaunchKernelGGL(reduce_dphi_segment, dim3(unsigned(cnt), 2), dim3(256), 0, p.stream,
+                     reinterpret_cast<const double*>(p.adj_ws + L.parts[set]), nb_first, nb_last,
+                     L.max_blocks, dphi + 6 * (s0 - p.adj_n0));
+  HIP_TRY(hipGetLastError());
+  return BRAHMS_OK;
+}
+
+brahms_status side_stream(brahms_plan_s& p) {
+  if (!p.adj_side) HIP_TRY(hipStreamCreateWithFlags(&p.adj_side, hipStreamNonBlocking));
+  for (hipEvent_t& e : p.adj_ev)
+    if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   return BRAHMS_OK;
 }
 
@@ -246,10 +310,10 @@ brahms_status brahms_adjoint_forward(brahms_plan plan, int nsteps, int checkpoin
   // sweep starts without recomputing it
   const int cnt = nsteps - (L.nckpt - 1) * checkpoint_every;
   float2* slot0[3] = {nullptr, nullptr, nullptr};
-  for (int j = 0; j < p.nf; ++j) slot0[j] = state_field(p.adj_ws + L.seg, L, p, 0, j);
+  for (int j = 0; j < p.nf; ++j) slot0[j] = state_field(p.adj_ws + L.seg[0], L, p, 0, j);
   if (brahms_status st = copy_state(p, slot0, fields)) return st;
   if (brahms_status st = brahms::detail::refresh_tables(p, p.step, cnt)) return st;
-  if (brahms_status st = record_segment(p, L, cnt, fields)) return st;
+  if (brahms_status st = record_segment(p, L, 0, cnt, fields)) return st;
   p.step += cnt;
   p.adj_last_recorded = true;
   p.adj_ready = true;
@@ -271,42 +335,42 @@ brahms_status brahms_adjoint_backward(brahms_plan plan, void* const* grad, doubl
   hipLaunchKernelGGL(zero_doubles, dim3(64), dim3(256), 0, p.stream, dphi, long(6) * p.adj_nsteps);
   HIP_TRY(hipGetLastError());
   const long long saved_step = p.step;
-  for (int c = L.nckpt - 1; c >= 0; --c) {
-    const long long s0 = p.adj_n0 + (long long)c * p.adj_every;
-    const int cnt = int(std::min<long long>(p.adj_every, p.adj_n0 + p.adj_nsteps - s0));
-    if (c != L.nckpt - 1 || !p.adj_last_recorded) {
-      // recompute the segment out of place, keeping inputs and pre-RK4 states
-      if (brahms_status st = brahms::detail::refresh_tables(p, s0, cnt)) return st;
-      float2* slot0[3] = {nullptr, nullptr, nullptr};
-      float2* ck[3] = {nullptr, nullptr, nullptr};
-      for (int j = 0; j < p.nf; ++j) {
-        slot0[j] = state_field(p.adj_ws + L.seg, L, p, 0, j);
-        ck[j] = state_field(p.adj_ws + L.ckpt, L, p, c, j);
-      }
-      if (brahms_status st = copy_state(p, slot0, ck)) return st;
-      if (brahms_status st = record_segment(p, L, cnt, nullptr)) return st;
+  const int last = L.nckpt - 1;
+  if (L.nsets == 1) {
+    for (int c = last; c >= 0; --c) {
+      if (c != last || !p.adj_last_recorded)
+        if (brahms_status st = recompute_segment(p, L, c, 0)) return st;
+      if (brahms_status st = reverse_segment(p, L, c, 0, g, dphi)) return st;
     }
-    // reverse sweep over the segment
-    for (int i = cnt - 1; i >= 0; --i) {
-      const long long r = s0 + i - p.adj_n0;
-      float2* y2[3] = {nullptr, nullptr, nullptr};
-      float2* y0[3] = {nullptr, nullptr, nullptr};
-      for (int j = 0; j < p.nf; ++j) {
-        y2[j] = state_field(p.adj_ws + L.pre, L, p, i, j);
-        y0[j] = state_field(p.adj_ws + L.seg, L, p, i, j);
+  } else {
+    // Segment c lives in set (last - c) % 2.  While the caller's stream
+    // sweeps segment c backwards, the side stream recomputes segment c - 1
+    // into the other set, once the sweep of segment c + 1 has released it.
+    if (brahms_status st = side_stream(p)) return st;
+    hipEvent_t ev_start = p.adj_ev[0], *ev_ready = p.adj_ev + 1, *ev_free = p.adj_ev + 3;
+    const hipStream_t main = p.stream;
+    if (!p.adj_last_recorded)
+      if (brahms_status st = recompute_segment(p, L, last, 0)) return st;
+    HIP_TRY(hipEventRecord(ev_start, main));
+    HIP_TRY(hipStreamWaitEvent(p.adj_side, ev_start, 0));
+    brahms_status st = BRAHMS_OK;
+    for (int c = last; c >= 0 && st == BRAHMS_OK; --c) {
+      const int set = (last - c) % 2, other = 1 - set;
+      if (c > 0) {
+        if (c < last) HIP_TRY(hipStreamWaitEvent(p.adj_side, ev_free[other], 0));
+        p.stream = p.adj_side;
+        st = recompute_segment(p, L, c - 1, other);
+        p.stream = main;
+        if (st != BRAHMS_OK) break;
+        HIP_TRY(hipEventRecord(ev_ready[other], p.adj_side));
       }
-      if (brahms_status st = adj_pass(p, L, i, 2, g, y2)) return st;
-      if (brahms_status st = brahms::detail::launch_linear_pass(p, i, AX_Y, g, true)) return st;
-      if (brahms_status st = adj_pass(p, L, i, 0, g, y0)) return st;
-      (void)r;
+      if (c < last) HIP_TRY(hipStreamWaitEvent(main, ev_ready[set], 0));
+      st = reverse_segment(p, L, c, set, g, dphi);
+      if (st != BRAHMS_OK) break;
+      HIP_TRY(hipEventRecord(ev_free[set], main));
     }
-    // dJ/dPhi of the segment's steps, in a fixed order
-    const int nb_first = pass_blocks(brahms::detail::pass_axis(p, 0), p);
-    const int nb_last = pass_blocks(brahms::detail::pass_axis(p, 2), p);
-    hipLaunchKernelGGL(reduce_dphi_segment, dim3(unsigned(cnt), 2), dim3(256), 0, p.stream,
-                       reinterpret_cast<const double*>(p.adj_ws + L.parts), nb_first, nb_last,
-                       L.max_blocks, dphi + 6 * (s0 - p.adj_n0));
-    HIP_TRY(hipGetLastError());
+    p.stream = main;
+    if (st != BRAHMS_OK) return st;
   }
   p.adj_last_recorded = false;
   p.step = saved_step;

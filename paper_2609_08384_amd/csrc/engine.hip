@@ -347,12 +347,12 @@ namespace {
 brahms_status map_table(brahms_plan_s& p, long long n0, int count);
 }  // namespace
 
-brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count) {
+brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count, int row0) {
   const int per_field = p.nx + p.ny + p.nt;
   TableArgs ta{};
-  ta.rows = reinterpret_cast<float2*>(p.ws + p.off_prop);
   ta.row_stride = table_row_stride(p.nf, p.nx, p.ny, p.nt);
-  ta.nl = reinterpret_cast<float2*>(p.ws + p.off_nl);
+  ta.rows = reinterpret_cast<float2*>(p.ws + p.off_prop) + size_t(row0) * ta.row_stride;
+  ta.nl = reinterpret_cast<float2*>(p.ws + p.off_nl) + size_t(row0) * 2 * p.nf * kNlCoef;
   ta.phi0 = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_phi0);
   ta.dk = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_dk);
   ta.n0 = n0;
@@ -370,8 +370,10 @@ brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count) {
   if (brahms_status st = timing_start(p, 3)) return st;
   hipLaunchKernelGGL(step_tables, dim3(unsigned((total + 255) / 256)), dim3(256), 0, p.stream, ta);
   HIP_TRY(hipGetLastError());
-  if (!p.dk_map.empty() && p.map_rows == kChunk)
+  if (!p.dk_map.empty() && p.map_rows == kChunk) {
+    if (row0 != 0) return fail(BRAHMS_E_UNSUPPORTED, "map tables are filled from row 0");
     if (brahms_status st = map_table(p, n0, count)) return st;
+  }
   if (timed)
     if (brahms_status st = timing_stop(p)) return st;
   return BRAHMS_OK;
@@ -805,6 +807,9 @@ brahms_status brahms_plan_destroy(brahms_plan plan) {
   for (hipEvent_t e : plan->pool) (void)hipEventDestroy(e);
   drop_chunk_graph(*plan);
   if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
+  for (hipEvent_t e : plan->adj_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (plan->adj_side) (void)hipStreamDestroy(plan->adj_side);
   delete plan;
   return BRAHMS_OK;
 }

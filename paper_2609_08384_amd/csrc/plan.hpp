@@ -50,6 +50,9 @@ struct brahms_plan_s {
   int adj_nsteps = 0, adj_every = 0;
   bool adj_last_recorded = false;   // segment slots hold the last segment
   char* adj_ws = nullptr;
+  // reverse sweep: a second stream recomputes the next segment meanwhile
+  hipStream_t adj_side = nullptr;
+  hipEvent_t adj_ev[5] = {};          // start, ready[2], free[2]
   // diagnostics (brahms_set_monitor / brahms_set_snapshots)
   int mon_every = 0;                    // record when the step index is a multiple
   double* mon_records = nullptr;        // device, capacity x record doubles
@@ -111,8 +114,8 @@ struct StepIO {
   float2* pre[3];
 };
 
-// Fill table rows 0..count-1 for steps n0..n0+count-1.
-brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count);
+// Fill table rows row0..row0+count-1 for steps n0..n0+count-1.
+brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count, int row0 = 0);
 // The passes of one z-step in order: axis (AX_*) and RK4 mode (NL_*) of
 // each.  Three passes in general; passes along an axis of length 1 are left
 // out when they would multiply by exactly 1 (so the result is unchanged bit
