@@ -529,9 +529,10 @@ __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass_batched(
 // rounded at every z_n separately, the phase rounding errors of consecutive
 // steps cancel (a telescoping product) instead of accumulating coherently.
 //
-// The transform twiddles, the register-DFT constants and the RK4
-// coefficients (see rk4_point; Phi(z) = Phi_n + dk_n (z - z_n) is the
-// integrated mismatch) are rounded to float stochastically, with a
+// The propagator entries themselves, the transform twiddles, the register-DFT
+// constants and the RK4 coefficients (see rk4_point; Phi(z) = Phi_n +
+// dk_n (z - z_n) is the integrated mismatch) are rounded to float
+// stochastically, with a
 // counter-based hash of (step, entry) as the random source, so that their
 // rounding errors are independent from one z-step to the next; a fixed
 // rounding would repeat the same error every step and add up linearly.
@@ -671,7 +672,13 @@ __device__ __forceinline__ void step_tables_body(const TableArgs& a, long gid) {
     const double2 u0 = rounded_unit(phi * (double(n) * a.dz));
     const double re = (u1.x * u0.x + u1.y * u0.y) * scale;
     const double im = (u1.y * u0.x - u1.x * u0.y) * scale;
-    row[r] = make_float2(float(re), float(im));
+    // stochastic, like the other per-step constants: an entry that is the
+    // same at every step (zero frequency, where it is the 1/n scale, which is
+    // inexact for n = 96) would otherwise be rounded the same way every step
+    // and its error would grow linearly with the number of steps
+    const unsigned slot = 2u * unsigned(r);
+    row[r] = make_float2(stochastic_round(re, entry_bits(n, slot)),
+                         stochastic_round(im, entry_bits(n, slot + 1)));
     return;
   }
   const long g2 = gid - nrow;
