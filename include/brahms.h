@@ -256,6 +256,11 @@ brahms_status brahms_adjoint_backward(brahms_plan plan, void* const* grad, doubl
  *   brahms_plan_create.
  * brahms_batch_set_schedule: launch-group size and (optional, n entries)
  *   pass orders; invalidates the binding (bind again).
+ * brahms_batch_set_group_limits: per-problem launch-group sizes (n entries,
+ *   0 = from the cache budget) that replace group_max; a group takes the
+ *   limit of its first problem, so give problems of one shape the same one.
+ *   NULL goes back to group_max.  Invalidates the binding.  Errors:
+ *   BRAHMS_E_INVALID_ARG for a negative limit.
  * brahms_batch_bind: fields holds sum(nf_i) device pointers, problem-major,
  *   each in the field layout of brahms_plan_bind; workspace as for plans.
  * brahms_batch_run: propagate every problem nsteps[i] steps from z = 0
@@ -266,6 +271,7 @@ typedef struct brahms_batch_s* brahms_batch;
 brahms_status brahms_batch_create(int n, const int* shapes, const brahms_params* params,
                                   const int* nsteps, void* hip_stream, brahms_batch* out);
 brahms_status brahms_batch_set_schedule(brahms_batch batch, int group_max, const int* pass_order);
+brahms_status brahms_batch_set_group_limits(brahms_batch batch, const int* limits);
 brahms_status brahms_batch_workspace_size(brahms_batch batch, size_t* bytes);
 brahms_status brahms_batch_bind(brahms_batch batch, void* const* fields, void* workspace);
 brahms_status brahms_batch_run(brahms_batch batch);

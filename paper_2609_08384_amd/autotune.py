@@ -118,39 +118,81 @@ def apply(plan: brahms.Plan, device="cuda:0") -> dict:
 
 
 GROUP_CANDIDATES = (0, 1 << 30)   # cache-budget groups, or every same-shape problem at once
+LIMIT_CANDIDATES = (0, 1, 2, 4, 1 << 30)   # per-shape launch-group sizes
+
+
+def _probe_time(batch: "brahms.Batch", fields, device) -> float:
+    """Milliseconds of one run of an already scheduled batch (after a
+    warm-up run that also builds its graph)."""
+    batch.bind(fields)
+    batch.run()
+    torch.cuda.synchronize(device)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    batch.run()
+    ev1.record()
+    torch.cuda.synchronize(device)
+    return ev0.elapsed_time(ev1)
 
 
 def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64) -> dict:
-    """Pick the pass orders and the launch-group size of a batch by timing a
-    copy of it on scratch fields with at most max_steps steps per problem:
-    group sizes GROUP_CANDIDATES, each with the per-shape orders of `tune`
-    (the fastest for a plain solve) and with one order for every problem
-    (concurrent groups compete for the chip, so the best order alone need not
-    be the best order together).  Applies the choice to `batch`."""
-    tuned = [tune(nx, ny, nt, nf, prm, device)["pass_order"]
-             for (nx, ny, nt, nf, prm, _) in batch.problems]
-    n = len(batch.problems)
+    """Pick the pass orders and the launch-group sizes of a batch by timing
+    copies of it on scratch fields, with at most max_steps steps per problem:
+    * per grid shape alone, the group sizes LIMIT_CANDIDATES (the fastest
+      differs between shapes: small grids want many problems per launch,
+      large ones few, so that groups of different shapes overlap);
+    * the whole batch with those per-shape sizes, and with the global sizes
+      GROUP_CANDIDATES, each with the per-shape orders of `tune` (the fastest
+      for a plain solve) and with one order for every problem (concurrent
+      groups compete for the chip, so the best order alone need not be the
+      best order together).
+    Applies the fastest choice to `batch`."""
+    problems = batch.problems
+    n = len(problems)
+    tuned = [tune(nx, ny, nt, nf, prm, device)["pass_order"] for (nx, ny, nt, nf, prm, _) in problems]
     order_sets = {"per_shape": tuned, "all_0": [0] * n, "all_1": [1] * n}
-    probe = brahms.Batch([(nx, ny, nt, nf, prm, min(ns, max_steps))
-                          for (nx, ny, nt, nf, prm, ns) in batch.problems])
+    short = [(nx, ny, nt, nf, prm, min(ns, max_steps)) for (nx, ny, nt, nf, prm, ns) in problems]
     gen = torch.Generator(device="cpu").manual_seed(7)
     fields = [[(0.1 * torch.randn(nt, ny, nx, dtype=torch.complex64, generator=gen)).to(device)
-               for _ in range(nf)] for (nx, ny, nt, nf, _, _) in batch.problems]
-    times = []
+               for _ in range(nf)] for (nx, ny, nt, nf, _, _) in problems]
+    # per-shape group sizes
+    shapes = {}
+    for i, (nx, ny, nt, nf, _, _) in enumerate(problems):
+        shapes.setdefault((nx, ny, nt, nf), []).append(i)
+    limits = [0] * n
+    shape_ms = {}
+    for key, idx in shapes.items():
+        sub = brahms.Batch([short[i] for i in idx])
+        sub.set_schedule(0, [tuned[i] for i in idx])
+        times = []
+        for lim in LIMIT_CANDIDATES:
+            sub.set_group_limits([lim] * len(idx))
+            times.append((_probe_time(sub, [fields[i] for i in idx], device), lim))
+        sub.destroy()
+        best_ms, best_lim = min(times)
+        for i in idx:
+            limits[i] = best_lim
+        shape_ms["%dx%dx%d:nf%d" % key] = {str(l): t for t, l in times}
+    # the whole batch
+    probe = brahms.Batch(short)
+    candidates = []
+    probe.set_schedule(0, tuned)
+    probe.set_group_limits(limits)
+    candidates.append((_probe_time(probe, fields, device), "per_shape_limits", None, "per_shape"))
+    probe.set_group_limits(None)
     for gm in GROUP_CANDIDATES:
         for name, orders in order_sets.items():
             probe.set_schedule(gm, orders)
-            probe.bind(fields)
-            probe.run()
-            torch.cuda.synchronize(device)
-            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            ev0.record()
-            probe.run()
-            ev1.record()
-            torch.cuda.synchronize(device)
-            times.append((ev0.elapsed_time(ev1), gm, name))
+            candidates.append((_probe_time(probe, fields, device), f"group_max={gm}", gm, name))
     probe.destroy()
-    best_ms, best_gm, best_name = min(times)
-    batch.set_schedule(best_gm, order_sets[best_name])
-    return {"group_max": best_gm, "pass_orders": order_sets[best_name], "orders": best_name,
-            "probe_ms": {f"{g}/{o}": t for t, g, o in times}}
+    best = min(candidates, key=lambda c: c[0])
+    _, label, gm, oname = best
+    if gm is None:
+        batch.set_schedule(0, order_sets[oname])
+        batch.set_group_limits(limits)
+    else:
+        batch.set_group_limits(None)
+        batch.set_schedule(gm, order_sets[oname])
+    return {"choice": label, "group_max": gm, "group_limits": limits if gm is None else None,
+            "pass_orders": order_sets[oname], "orders": oname,
+            "probe_ms": {f"{c[1]}/{c[3]}": c[0] for c in candidates}, "shape_probe_ms": shape_ms}

@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "brahms_batch_create": [i, ctypes.POINTER(i), ctypes.POINTER(ParamsC), ctypes.POINTER(i), vp,
                                 ctypes.POINTER(vp)],
         "brahms_batch_set_schedule": [vp, i, ctypes.POINTER(i)],
+        "brahms_batch_set_group_limits": [vp, ctypes.POINTER(i)],
         "brahms_batch_workspace_size": [vp, ctypes.POINTER(ctypes.c_size_t)],
         "brahms_batch_bind": [vp, ctypes.POINTER(vp), vp],
         "brahms_batch_run": [vp],
@@ -433,6 +434,15 @@ class Batch:
             arr = (ctypes.c_int * len(self.problems))(*[int(v) for v in pass_orders])
         _check(self._lib.brahms_batch_set_schedule(self._h, int(group_max), arr),
                "brahms_batch_set_schedule")
+        if self.fields is not None:
+            self.bind(self.fields)
+
+    def set_group_limits(self, limits: Optional[Sequence[int]]):
+        """Per-problem launch-group sizes (0: from the cache budget), or None."""
+        arr = None
+        if limits is not None:
+            arr = (ctypes.c_int * len(self.problems))(*[int(v) for v in limits])
+        _check(self._lib.brahms_batch_set_group_limits(self._h, arr), "brahms_batch_set_group_limits")
         if self.fields is not None:
             self.bind(self.fields)
 

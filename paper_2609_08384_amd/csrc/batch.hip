@@ -45,6 +45,7 @@ struct brahms_batch_s {
   std::vector<size_t> plan_off;        // per problem: offset of its plan workspace
   size_t off_desc = 0, off_targs = 0, ws_size = 0;
   int group_max = 0;                   // 0: choose from the cache budget
+  std::vector<int> group_limit;        // per problem, overrides group_max (empty: none)
   // launch groups and descriptor placement (rebuilt when the schedule changes)
   struct Group {
     std::vector<int> members;
@@ -86,7 +87,7 @@ void make_groups(brahms_batch_s& b) {
   for (auto& kv : by_key) {
     const std::vector<int>& ids = kv.second;
     const brahms_plan_s& p0 = *b.plans[ids[0]];
-    int gmax = b.group_max;
+    int gmax = b.group_limit.empty() ? b.group_max : b.group_limit[size_t(ids[0])];
     if (gmax <= 0) gmax = int(std::max<size_t>(1, kCacheBudget / state_bytes(p0)));
     for (size_t s = 0; s < ids.size(); s += size_t(gmax)) {
       brahms_batch_s::Group g{};
@@ -458,6 +459,19 @@ brahms_status brahms_batch_set_schedule(brahms_batch b, int group_max, const int
   b->group_max = group_max;
   if (pass_order != nullptr)
     for (int i = 0; i < b->n; ++i) b->plans[i]->order = pass_order[i];
+  drop_graph(*b);
+  b->bound = false;
+  layout_batch(*b);
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_batch_set_group_limits(brahms_batch b, const int* limits) {
+  if (brahms_status st = check_batch(b)) return st;
+  if (limits != nullptr)
+    for (int i = 0; i < b->n; ++i)
+      if (limits[i] < 0) return fail(BRAHMS_E_INVALID_ARG, "group limits must be >= 0");
+  if (limits == nullptr) b->group_limit.clear();
+  else b->group_limit.assign(limits, limits + b->n);
   drop_graph(*b);
   b->bound = false;
   layout_batch(*b);
