@@ -197,3 +197,4 @@ def test_long_tau_host_checks(lib):
     lib.brahms_plan_destroy(h)
     assert _create(lib, 512, 8, 8, 2, c)[0] == brahms.BRAHMS_E_UNSUPPORTED   # only tau may be long
     assert _create(lib, 8, 8, 8192, 2, c)[0] == brahms.BRAHMS_E_UNSUPPORTED
+

@@ -29,13 +29,19 @@ def _problems(seed=11):
     return wls
 
 
-@pytest.mark.parametrize("group_max", [0, 2, 1])
+@pytest.mark.parametrize("group_max", [0, 2, 1, "limits"])
 def test_batch_equals_plain_runs_bitwise(group_max):
     wls = _problems()
     probs = [(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls]
     orders = [k % 4 for k in range(len(wls))]
     batch = brahms.Batch(probs)
-    batch.set_schedule(group_max, orders)
+    if group_max == "limits":
+        # per-problem group sizes (problems of one shape share theirs)
+        lim = {}
+        batch.set_schedule(0, orders)
+        batch.set_group_limits([lim.setdefault((w.nx, w.ny, w.nt, w.nf), len(lim) % 3) for w in wls])
+    else:
+        batch.set_schedule(group_max, orders)
     fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
     batch.bind(fields)
     batch.run()
@@ -137,3 +143,13 @@ def test_whole_sweep_matches_oracle_and_single_runs():
         alone = brahms.run_workload(w, device=DEV, pass_order=o)
         for a, b in zip(fs, alone):
             assert torch.equal(a, b), i
+
+
+def test_group_limits_reject_negative():
+    wls = _problems()[:2]
+    batch = brahms.Batch([(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls])
+    with pytest.raises(brahms.BrahmsError):
+        batch.set_group_limits([1, -1])
+    batch.set_group_limits([1, 0])
+    batch.set_group_limits(None)
+    batch.destroy()
