@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint and batched-sweep side measurements")
-    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle z-steps in the CPU sample")
+    ap.add_argument("--cpu-steps", type=int, default=4, help="oracle z-steps in the CPU sample")
     ap.add_argument("--pass-order", default="auto", choices=["auto", "0", "1", "2", "3"],
                     help="plan schedule: autotuned (default) or a fixed pass order")
     ap.add_argument("--copy-calibration", action="store_true",
