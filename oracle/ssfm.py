@@ -15,7 +15,13 @@ reordering beyond what the method states):
   exp(-/+ i dk z) mismatch phase;
 * symmetric splitting N/2 - L - N/2 (Sec. 3.1, eq. expon), the linear step
   done in Fourier space by a forward and an inverse transform, the nonlinear
-  half-steps by a classical fourth-order Runge-Kutta step (Sec. 3.1).
+  half-steps by a classical fourth-order Runge-Kutta step (Sec. 3.1);
+* as a second reference, the same splitting repeated over several steps with
+  each pair of adjacent nonlinear half-steps taken as one Runge-Kutta step of
+  size dz (Oracle.propagate_merged): eq. expon repeated puts two half-step
+  flows of N next to each other, and the exact flows of one ODE over
+  adjacent intervals compose to the flow over their union, so only the
+  Runge-Kutta truncation term differs from the literal splitting.
 
 Readings of passages that are silent or inconsistent (each is listed in the
 design notes of the repository):
@@ -268,9 +274,33 @@ class Oracle:
             a = self.step(a, n)
         return a
 
+    def propagate_merged(self, a: List[torch.Tensor], nsteps: int,
+                         n0: int = 0) -> List[torch.Tensor]:
+        """Steps n0 .. n0 + nsteps - 1 of eq. expon with adjacent nonlinear
+        half-steps merged: the first half-step of step n0, then per step the
+        linear step over dz followed by one RK4 step of size dz from
+        z_n + dz/2 (it covers the second half of step n and the first half of
+        step n + 1), except after the last step, which ends with its own
+        second half-step of size dz/2."""
+        p = self.prob
+        h = p.dz / 2
+        a = [torch.as_tensor(x).to(DTYPE_C).clone() for x in a]
+        if nsteps <= 0:
+            return a
+        a = rk4(a, n0 * p.dz, h, p, self.phi)
+        for n in range(n0, n0 + nsteps):
+            a = [linear_step(aj, lj, p.dz) for aj, lj in zip(a, self.lam)]
+            size = h if n == n0 + nsteps - 1 else p.dz
+            a = rk4(a, n * p.dz + h, size, p, self.phi)
+        return a
+
 
 def propagate(fields, prob: Problem, nsteps: int, n0: int = 0):
     return Oracle(prob).propagate(fields, nsteps, n0)
+
+
+def propagate_merged(fields, prob: Problem, nsteps: int, n0: int = 0):
+    return Oracle(prob).propagate_merged(fields, nsteps, n0)
 
 
 # ---------------------------------------------------------------------------

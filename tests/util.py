@@ -16,6 +16,15 @@ def oracle_problem(wl: inputs.Workload) -> ssfm.Problem:
                         dk_const=wl.dk_const, dk=dk, dk_map=wl.dk_map, dk_map_scale=scale)
 
 
+def oracle_run(wl: inputs.Workload, nsteps=None, merge=False):
+    """The oracle on a workload's entrance fields: the literal N/2 - L - N/2
+    loop, or with adjacent half-steps merged (the reference of engine runs
+    with merge_halves = 1)."""
+    nsteps = wl.nz if nsteps is None else nsteps
+    fn = ssfm.propagate_merged if merge else ssfm.propagate
+    return fn([to_torch(a) for a in wl.init], oracle_problem(wl), nsteps)
+
+
 def to_torch(a) -> torch.Tensor:
     return torch.from_numpy(np.asarray(a).astype(np.complex128))
 
