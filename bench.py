@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle z-steps in the CPU sample")
     ap.add_argument("--pass-order", default="auto", choices=["auto", "0", "1", "2", "3"],
                     help="plan schedule: autotuned (default) or a fixed pass order")
+    ap.add_argument("--literal-halves", action="store_true",
+                    help="keep both RK4 half-steps of every step (no merging of adjacent halves)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain 1 GiB device-to-device copy instead (reference for "
                          "achievable bandwidth and for scaling hardware byte counters)")
@@ -113,13 +115,15 @@ def _median_time(fn, reps=3):
 def reduced_dims(dev):
     """Focusing sweep of 99 CW problems (128 x 128 x 1, 200 steps each; the
     Boyd-Kleinman study of Sec. 5.2) as one batch, against the same problems
-    propagated one after another with plain plans."""
+    propagated one after another with plain plans (both with merged RK4
+    half-steps)."""
     import torch
     from paper_2609_08384_amd import brahms, inputs
     wls = inputs.bk_sweep()
     init = [[torch.from_numpy(a).to(dev) for a in w.init] for w in wls]
     fields = [[a.clone() for a in fs] for fs in init]
     batch = brahms.Batch([(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls])
+    batch.set_merge_halves(1)
     batch.bind(fields)
 
     def run_batch():
@@ -130,8 +134,11 @@ def reduced_dims(dev):
         return time.perf_counter() - t0
     t_batch = _median_time(run_batch)
     batch.destroy()
-    plans = [brahms.Plan(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w)).bind(fs)
-             for w, fs in zip(wls, fields)]
+    plans = []
+    for w, fs in zip(wls, fields):
+        pl = brahms.Plan(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w))
+        pl.set_schedule(0, 0, 1)
+        plans.append(pl.bind(fs))
 
     def run_seq():
         for pl in plans:
@@ -339,7 +346,16 @@ def kernel_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, pass_name: str, pass_order: int):
+def nl_of_pass(pass_order: int, merge_halves: int) -> dict:
+    """RK4 mode of each pass in the steady state of a run: with merged
+    half-steps the first pass of every step but the run's first is linear."""
+    modes = dict(NL_OF_PASS[pass_order])
+    if merge_halves:
+        modes = {k: ("none" if v == "before" else v) for k, v in modes.items()}
+    return modes
+
+
+def measured_traffic(workload: str, pass_name: str, pass_order: int, merge_halves: int = 0):
     """HBM bytes per launch of one pass kernel from the hardware-counter
     summary profiles/hbm_traffic_<workload>.json (FETCH_SIZE and WRITE_SIZE
     per dispatch, each scaled by what the counter reads for a plain copy of
@@ -353,7 +369,7 @@ def measured_traffic(workload: str, pass_name: str, pass_order: int):
         return None
     if rec.get("kernel_digest") != kernel_digest():
         return None
-    key = f"{pass_name}:{NL_OF_PASS[pass_order][pass_name]}"
+    key = f"{pass_name}:{nl_of_pass(pass_order, merge_halves)[pass_name]}"
     k = rec.get("kernels", {}).get(key)
     if k is None:
         return None
@@ -412,9 +428,9 @@ def main():
     plan = brahms.Plan(wl.nx, wl.ny, wl.nt, wl.nf, brahms.params_from_workload(wl)).bind(fields)
     if args.pass_order == "auto":
         from paper_2609_08384_amd import autotune
-        schedule = autotune.apply(plan, dev)
+        schedule = autotune.apply(plan, dev, merge_halves=not args.literal_halves)
     else:
-        plan.set_schedule(int(args.pass_order))
+        plan.set_schedule(int(args.pass_order), 0, 0 if args.literal_halves else 1)
         schedule = plan.get_schedule()
 
     def reset():
@@ -458,7 +474,10 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(wl.name, dom, int(schedule["pass_order"])), "kernel": dom,
+                "traffic": measured_traffic(wl.name, dom, int(schedule["pass_order"]),
+                                            int(schedule.get("merge_halves", 0))),
+                "kernel": dom, "kernel_rk4": nl_of_pass(int(schedule["pass_order"]),
+                                                        int(schedule.get("merge_halves", 0)))[dom],
                 "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": bytes_per_launch}
     per_kernel = {k: {"avg_ms": round(v[0] / max(v[1], 1), 5), "launches": v[1],
                       "GBps": (round(bytes_per_launch / (v[0] / v[1] * 1e-3) / 1e9, 1)

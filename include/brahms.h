@@ -136,8 +136,10 @@ brahms_status brahms_set_z(brahms_plan plan, double z);
 
 brahms_status brahms_plan_destroy(brahms_plan plan);
 
-/* Execution schedule of a plan (no effect on what is computed, only on how;
- * results of different schedules agree to rounding).  The linear step is
+/* Execution schedule of a plan (pass order and graph replay change only how
+ * the method is computed; merge_halves changes the integrator of the
+ * nonlinear part by O(h^5) per step; results of different schedules agree
+ * to rounding).  The linear step is
  * applied as three commuting one-axis operators (Sec. 3.1: the dispersion
  * and diffraction operators commute), each a pass over the fields; the first
  * pass of a z-step also performs the first Runge-Kutta half-step and the last
@@ -155,11 +157,23 @@ brahms_status brahms_plan_destroy(brahms_plan plan);
  *     monitors or snapshots, partial chunks, and plans whose transverse map
  *     tables are filled per step run launch by launch.  The graph is captured
  *     by brahms_plan_set_schedule or brahms_plan_bind, whichever comes last.
+ *   merge_halves 1: within one brahms_step call, the second RK4 half-step of
+ *     step n and the first of step n + 1 (Eq. expon: N/2 - L - N/2 repeated)
+ *     run as one classical RK4 step of size dz from z_n + dz/2.  The exact
+ *     nonlinear flows over the two halves compose to the flow over dz, so
+ *     only the RK4 truncation term changes (O(dz^5) per step); the call's
+ *     first step keeps its first half-step and its last step its second one,
+ *     so the fields returned are those at a step boundary.  One RK4 update
+ *     per step instead of two.  Needs a constant dk (no profile) and no
+ *     transverse map (BRAHMS_E_UNSUPPORTED otherwise); calls run with literal
+ *     half-steps while monitor records or snapshots are set; the adjoint
+ *     always differentiates the literal half-steps.
  * The autotuner in the Python package times the candidates per grid shape. */
 typedef struct {
   int pass_order;
   int graph;
-  int reserved[6];
+  int merge_halves;
+  int reserved[5];
 } brahms_schedule;
 
 brahms_status brahms_plan_set_schedule(brahms_plan plan, const brahms_schedule* sched);
@@ -256,6 +270,12 @@ brahms_status brahms_adjoint_backward(brahms_plan plan, void* const* grad, doubl
  *   brahms_plan_create.
  * brahms_batch_set_schedule: launch-group size and (optional, n entries)
  *   pass orders; invalidates the binding (bind again).
+ * brahms_batch_set_merge_halves: 1 runs every problem with merged RK4
+ *   half-steps (as the plan schedule field merge_halves: each run's first
+ *   step keeps its first half-step, each problem's last step its second
+ *   one); 0 (default) keeps the literal N/2 - L - N/2.  Invalidates the
+ *   binding.  Errors: BRAHMS_E_INVALID_ARG for another value,
+ *   BRAHMS_E_UNSUPPORTED if a problem has a dk profile.
  * brahms_batch_set_group_limits: per-problem launch-group sizes (n entries,
  *   0 = from the cache budget) that replace group_max; a group takes the
  *   limit of its first problem, so give problems of one shape the same one.
@@ -272,6 +292,7 @@ brahms_status brahms_batch_create(int n, const int* shapes, const brahms_params*
                                   const int* nsteps, void* hip_stream, brahms_batch* out);
 brahms_status brahms_batch_set_schedule(brahms_batch batch, int group_max, const int* pass_order);
 brahms_status brahms_batch_set_group_limits(brahms_batch batch, const int* limits);
+brahms_status brahms_batch_set_merge_halves(brahms_batch batch, int merge_halves);
 brahms_status brahms_batch_workspace_size(brahms_batch batch, size_t* bytes);
 brahms_status brahms_batch_bind(brahms_batch batch, void* const* fields, void* workspace);
 brahms_status brahms_batch_run(brahms_batch batch);

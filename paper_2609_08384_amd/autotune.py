@@ -6,6 +6,12 @@ This is the plan-by-measurement idea of the paper's CPU backend (FFTW
 planning with measurement, Sec. 5.1) applied to the GPU schedules.  The
 timing loop only calls the C ABI; every candidate computes the same result to
 rounding.
+
+Merged RK4 half-steps (schedule field merge_halves) are not a trade-off to
+measure: they take one RK4 update per step instead of two and change the
+result by O(dz^5) per step, far below FP32 rounding.  The tuner turns them on
+wherever the plan allows them (a constant dk and no transverse map) unless
+asked not to, and times the other fields with them.
 """
 from __future__ import annotations
 
@@ -34,8 +40,13 @@ def _arch(device) -> str:
     return getattr(props, "gcnArchName", "unknown").split(":")[0]
 
 
-def _key(arch: str, nx: int, ny: int, nt: int, nf: int) -> str:
-    return f"v2:{arch}:{nx}x{ny}x{nt}:nf{nf}"
+def _key(arch: str, nx: int, ny: int, nt: int, nf: int, merge: int) -> str:
+    return f"v3:{arch}:{nx}x{ny}x{nt}:nf{nf}:m{merge}"
+
+
+def can_merge(params: brahms.Params) -> bool:
+    """Whether a plan with these parameters accepts merge_halves = 1."""
+    return params.dk is None and getattr(params, "dk_map", None) is None
 
 
 def _load() -> dict:
@@ -80,10 +91,11 @@ def measure(nx: int, ny: int, nt: int, nf: int, params: brahms.Params, schedule:
 
 
 def tune(nx: int, ny: int, nt: int, nf: int, params: brahms.Params, device="cuda:0",
-         refresh: bool = False) -> dict:
+         refresh: bool = False, merge_halves: bool = True) -> dict:
     """Best schedule for this shape (cached in memory and on disk)."""
     arch = _arch(device)
-    key = _key(arch, nx, ny, nt, nf)
+    merge = int(merge_halves and can_merge(params))
+    key = _key(arch, nx, ny, nt, nf, merge)
     with _lock:
         if not refresh:
             if key in _memo:
@@ -95,7 +107,8 @@ def tune(nx: int, ny: int, nt: int, nf: int, params: brahms.Params, device="cuda
         # time with the same linear coefficients but no coupling blow-up risk
         scratch = brahms.Params(dz=params.dz, fields=params.fields, dk_const=params.dk_const,
                                 dk=None, dx=params.dx, dy=params.dy, dt=params.dt)
-        times = [(measure(nx, ny, nt, nf, scratch, c, device), c) for c in CANDIDATES]
+        cands = [dict(c, merge_halves=merge) for c in CANDIDATES]
+        times = [(measure(nx, ny, nt, nf, scratch, c, device), c) for c in cands]
         best_ms, best = min(((t, c) for t, c in times if not c["graph"]), key=lambda tc: tc[0])
         # a graph pays off only where launches are a visible cost: take it
         # when it is at least 2 % faster than the best launch-by-launch order
@@ -110,9 +123,9 @@ def tune(nx: int, ny: int, nt: int, nf: int, params: brahms.Params, device="cuda
         return _memo[key]
 
 
-def apply(plan: brahms.Plan, device="cuda:0") -> dict:
+def apply(plan: brahms.Plan, device="cuda:0", merge_halves: bool = True) -> dict:
     """Tune (or look up) the plan's shape and set the chosen schedule."""
-    sched = tune(plan.nx, plan.ny, plan.nt, plan.nf, plan.params, device)
+    sched = tune(plan.nx, plan.ny, plan.nt, plan.nf, plan.params, device, merge_halves=merge_halves)
     plan.set_schedule(**sched)
     return sched
 
@@ -135,7 +148,8 @@ def _probe_time(batch: "brahms.Batch", fields, device) -> float:
     return ev0.elapsed_time(ev1)
 
 
-def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64) -> dict:
+def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
+               merge_halves: bool = True) -> dict:
     """Pick the pass orders and the launch-group sizes of a batch by timing
     copies of it on scratch fields, with at most max_steps steps per problem:
     * per grid shape alone, the group sizes LIMIT_CANDIDATES (the fastest
@@ -146,10 +160,13 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64) -> d
       for a plain solve) and with one order for every problem (concurrent
       groups compete for the chip, so the best order alone need not be the
       best order together).
-    Applies the fastest choice to `batch`."""
+    Merged half-steps are taken when every problem allows them.  Applies the
+    fastest choice to `batch`."""
     problems = batch.problems
     n = len(problems)
-    tuned = [tune(nx, ny, nt, nf, prm, device)["pass_order"] for (nx, ny, nt, nf, prm, _) in problems]
+    merge = int(merge_halves and all(can_merge(prm) for (_, _, _, _, prm, _) in problems))
+    tuned = [tune(nx, ny, nt, nf, prm, device, merge_halves=bool(merge))["pass_order"]
+             for (nx, ny, nt, nf, prm, _) in problems]
     order_sets = {"per_shape": tuned, "all_0": [0] * n, "all_1": [1] * n}
     short = [(nx, ny, nt, nf, prm, min(ns, max_steps)) for (nx, ny, nt, nf, prm, ns) in problems]
     gen = torch.Generator(device="cpu").manual_seed(7)
@@ -163,6 +180,7 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64) -> d
     shape_ms = {}
     for key, idx in shapes.items():
         sub = brahms.Batch([short[i] for i in idx])
+        sub.set_merge_halves(merge)
         sub.set_schedule(0, [tuned[i] for i in idx])
         times = []
         for lim in LIMIT_CANDIDATES:
@@ -175,6 +193,7 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64) -> d
         shape_ms["%dx%dx%d:nf%d" % key] = {str(l): t for t, l in times}
     # the whole batch
     probe = brahms.Batch(short)
+    probe.set_merge_halves(merge)
     candidates = []
     probe.set_schedule(0, tuned)
     probe.set_group_limits(limits)
@@ -187,6 +206,7 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64) -> d
     probe.destroy()
     best = min(candidates, key=lambda c: c[0])
     _, label, gm, oname = best
+    batch.set_merge_halves(merge)
     if gm is None:
         batch.set_schedule(0, order_sets[oname])
         batch.set_group_limits(limits)
@@ -194,5 +214,5 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64) -> d
         batch.set_group_limits(None)
         batch.set_schedule(gm, order_sets[oname])
     return {"choice": label, "group_max": gm, "group_limits": limits if gm is None else None,
-            "pass_orders": order_sets[oname], "orders": oname,
+            "pass_orders": order_sets[oname], "orders": oname, "merge_halves": merge,
             "probe_ms": {f"{c[1]}/{c[3]}": c[0] for c in candidates}, "shape_probe_ms": shape_ms}

@@ -41,7 +41,8 @@ class BrahmsError(RuntimeError):
 
 
 class ScheduleC(ctypes.Structure):
-    _fields_ = [("pass_order", ctypes.c_int), ("graph", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
+    _fields_ = [("pass_order", ctypes.c_int), ("graph", ctypes.c_int),
+                ("merge_halves", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
 
 
 class FieldParamsC(ctypes.Structure):
@@ -90,6 +91,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                 ctypes.POINTER(vp)],
         "brahms_batch_set_schedule": [vp, i, ctypes.POINTER(i)],
         "brahms_batch_set_group_limits": [vp, ctypes.POINTER(i)],
+        "brahms_batch_set_merge_halves": [vp, i],
         "brahms_batch_workspace_size": [vp, ctypes.POINTER(ctypes.c_size_t)],
         "brahms_batch_bind": [vp, ctypes.POINTER(vp), vp],
         "brahms_batch_run": [vp],
@@ -250,10 +252,13 @@ class Plan:
     def set_z(self, z: float):
         _check(self._lib.brahms_set_z(self._h, float(z)), "brahms_set_z")
 
-    def set_schedule(self, pass_order: int, graph: int = 0):
+    def set_schedule(self, pass_order: int, graph: int = 0, merge_halves: int = 0):
+        """Pass order 0-3, graph replay of 64-step chunks, and merged RK4
+        half-steps within a call (constant dk, no transverse map)."""
         sc = ScheduleC()
         sc.pass_order = int(pass_order)
         sc.graph = int(graph)
+        sc.merge_halves = int(merge_halves)
         _check(self._lib.brahms_plan_set_schedule(self._h, ctypes.byref(sc)),
                "brahms_plan_set_schedule")
 
@@ -261,7 +266,7 @@ class Plan:
         sc = ScheduleC()
         _check(self._lib.brahms_plan_get_schedule(self._h, ctypes.byref(sc)),
                "brahms_plan_get_schedule")
-        return {"pass_order": sc.pass_order, "graph": sc.graph}
+        return {"pass_order": sc.pass_order, "graph": sc.graph, "merge_halves": sc.merge_halves}
 
     # --- adjoint (reverse-mode gradient of the z-loop) ---
     def adjoint_workspace_bytes(self, nsteps: int, checkpoint_every: int) -> int:
@@ -382,14 +387,15 @@ class Plan:
 
 def run_workload(wl, nsteps: Optional[int] = None, device: str = "cuda:0",
                  stream: Optional[torch.cuda.Stream] = None,
-                 pass_order: Optional[int] = None) -> List[torch.Tensor]:
+                 pass_order: Optional[int] = None,
+                 merge_halves: int = 0) -> List[torch.Tensor]:
     """Upload a seeded workload's entrance fields, propagate nsteps (default:
     all of them) and return the device fields."""
     nsteps = wl.nz if nsteps is None else nsteps
     fields = [torch.from_numpy(a).to(device) for a in wl.init]
     plan = Plan(wl.nx, wl.ny, wl.nt, wl.nf, params_from_workload(wl), stream=stream)
-    if pass_order is not None:
-        plan.set_schedule(pass_order)
+    if pass_order is not None or merge_halves:
+        plan.set_schedule(pass_order or 0, 0, merge_halves)
     plan.bind(fields)
     plan.step(nsteps)
     torch.cuda.synchronize()
@@ -434,6 +440,13 @@ class Batch:
             arr = (ctypes.c_int * len(self.problems))(*[int(v) for v in pass_orders])
         _check(self._lib.brahms_batch_set_schedule(self._h, int(group_max), arr),
                "brahms_batch_set_schedule")
+        if self.fields is not None:
+            self.bind(self.fields)
+
+    def set_merge_halves(self, merge_halves: int):
+        """1: merged RK4 half-steps for every problem (constant dk only)."""
+        _check(self._lib.brahms_batch_set_merge_halves(self._h, int(merge_halves)),
+               "brahms_batch_set_merge_halves")
         if self.fields is not None:
             self.bind(self.fields)
 

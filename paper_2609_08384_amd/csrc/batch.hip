@@ -46,6 +46,7 @@ struct brahms_batch_s {
   size_t off_desc = 0, off_targs = 0, ws_size = 0;
   int group_max = 0;                   // 0: choose from the cache budget
   std::vector<int> group_limit;        // per problem, overrides group_max (empty: none)
+  bool merge = false;                  // merged RK4 half-steps (constant dk only)
   // launch groups and descriptor placement (rebuilt when the schedule changes)
   struct Group {
     std::vector<int> members;
@@ -157,8 +158,13 @@ void launch_group_pass(int axis, int nl, const brahms_batch_s::Group& g, hipStre
   const int nx = g.axis_len[0], ny = g.axis_len[1], nt = g.axis_len[2];
   if (axis == AX_X) {
     const long lines = long(ny) * nt;
-    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), m);
-    launch_batched_nl<N1, N2, AX_X>(g.nf, nl, lines % G::LPB == 0, grid, st, d, step);
+    if (nl == NL_NONE) {
+      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(g.nf) * m);
+      launch_batched<N1, N2, AX_X, 1, NL_NONE>(lines % G::LPB == 0, grid, st, d, step, g.nf);
+    } else {
+      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), m);
+      launch_batched_nl<N1, N2, AX_X>(g.nf, nl, lines % G::LPB == 0, grid, st, d, step);
+    }
   } else if (axis == AX_Y) {
     const long lines = long(nx) * nt;
     if (nl == NL_NONE) {
@@ -264,7 +270,7 @@ brahms_status upload_descriptors(brahms_batch_s& b) {
           a.consts = reinterpret_cast<const DftConsts*>(r + (p.nf + 1) * per_field);
           a.prop = r;
           a.field_stride = per_field;
-          a.nl = nls + (size_t(s) * 2 + (pass == 0 ? 0 : 1)) * p.nf * kNlCoef;
+          a.nl = nls + size_t(s) * 2 * p.nf * kNlCoef;
           a.nl2 = nls + (size_t(s) * 2 + 1) * p.nf * kNlCoef;
           a.nx = p.nx; a.ny = p.ny; a.nt = p.nt;
           for (int j = 0; j < 3; ++j) {
@@ -293,6 +299,7 @@ brahms_status upload_descriptors(brahms_batch_s& b) {
         ta.phi0 = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_phi0);
         ta.dk = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_dk);
         ta.n0 = (long long)c * kChunk;
+        ta.merge_last = b.merge ? (long long)b.nsteps[g.members[k]] - 1 : -1;
         ta.count = std::max(0, std::min(kChunk, b.nsteps[g.members[k]] - c * kChunk));
         ta.nx = p.nx; ta.ny = p.ny; ta.nt = p.nt; ta.nf = p.nf;
         ta.dz = p.dz; ta.dx = p.dx; ta.dy = p.dy; ta.dt = p.dt; ta.dk_const = p.dk_const;
@@ -313,7 +320,8 @@ brahms_status upload_descriptors(brahms_batch_s& b) {
 
 // One launch group on stream st: per 64-step chunk, one batched table launch
 // and then the batched pass launches of each step (three, fewer when an axis
-// of length 1 is left out).
+// of length 1 is left out).  With merged halves only step 0 has a first
+// half-step of its own.
 brahms_status enqueue_group(brahms_batch_s& b, const brahms_batch_s::Group& g, hipStream_t st) {
   {
     const brahms_plan_s& p0 = *b.plans[g.members[0]];
@@ -333,7 +341,7 @@ brahms_status enqueue_group(brahms_batch_s& b, const brahms_batch_s::Group& g, h
         const long long step = (long long)c * kChunk + s;
         for (int pass = 0; pass < sp.n; ++pass) {
           const int ax = sp.ax[pass];
-          const int nl = sp.nl[pass];
+          const int nl = b.merge && step > 0 && pass == 0 ? (sp.nl[pass] & ~NL_BEFORE) : sp.nl[pass];
           const PassArgs* d = reinterpret_cast<const PassArgs*>(b.ws + b.off_desc + g.desc_off) +
                               (size_t(pass) * kChunk + s) * m;
           if (long_tau_kind(ax)) dispatch_group_long(ax, nl, g, st, d, step);
@@ -459,6 +467,19 @@ brahms_status brahms_batch_set_schedule(brahms_batch b, int group_max, const int
   b->group_max = group_max;
   if (pass_order != nullptr)
     for (int i = 0; i < b->n; ++i) b->plans[i]->order = pass_order[i];
+  drop_graph(*b);
+  b->bound = false;
+  layout_batch(*b);
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_batch_set_merge_halves(brahms_batch b, int merge_halves) {
+  if (brahms_status st = check_batch(b)) return st;
+  if (merge_halves != 0 && merge_halves != 1) return fail(BRAHMS_E_INVALID_ARG, "merge_halves must be 0 or 1");
+  if (merge_halves)
+    for (brahms_plan p : b->plans)
+      if (!p->dk.empty()) return fail(BRAHMS_E_UNSUPPORTED, "merge_halves needs a constant dk");
+  b->merge = merge_halves != 0;
   drop_graph(*b);
   b->bound = false;
   layout_batch(*b);

@@ -112,8 +112,8 @@ void launch_plain_nl(int nf, int nl, bool full, dim3 grid, hipStream_t st, const
   else launch_plain_nl_nf<N1, N2, AX, 2>(nl, full, grid, st, a);
 }
 
-// One pass along `axis`; nl says where the RK4 half-step goes (NL_NONE only
-// for the y pass, which is always the middle pass of a step).
+// One pass along `axis`; nl says where the RK4 half-step goes.  Linear
+// passes (NL_NONE) take one field per block.
 template <int N1, int N2>
 hipError_t launch_axis(int axis, int nl, int nf, const brahms_plan_s& p, PassArgs a) {
   using G = LineGeom<N1, N2>;
@@ -121,8 +121,13 @@ hipError_t launch_axis(int axis, int nl, int nf, const brahms_plan_s& p, PassArg
   a.tiles = 1;
   if (axis == AX_X) {
     const long lines = long(p.ny) * p.nt;
-    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
-    launch_nl<N1, N2, AX_X>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
+    if (nl == NL_NONE) {
+      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(nf));
+      launch_pass<N1, N2, AX_X, 1, NL_NONE>(lines % G::LPB == 0, grid, p.stream, a);
+    } else {
+      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
+      launch_nl<N1, N2, AX_X>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
+    }
   } else if (axis == AX_Y) {
     const long lines = long(p.nx) * p.nt;
     if (nl == NL_NONE) {
@@ -229,7 +234,7 @@ void layout(brahms_plan_s& p) {
   p.off_diag = off;
   off = align_up(off + sizeof(double) * size_t(kDiagChunks) * p.nf * p.nt);
   p.off_n0 = off;
-  off = align_up(off + sizeof(long long));
+  off = align_up(off + 2 * sizeof(long long));
   if (!p.dk_map.empty()) {
     // phase tables of a whole 64-step chunk when they take at most 64 MB,
     // else one step at a time
@@ -347,7 +352,12 @@ namespace {
 brahms_status map_table(brahms_plan_s& p, long long n0, int count);
 }  // namespace
 
-brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count, int row0) {
+bool merging(const brahms_plan_s& p) {
+  return p.merge && p.dk.empty() && p.dk_map.empty() && p.mon_every == 0 && p.snap_steps.empty();
+}
+
+brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count, int row0,
+                             long long merge_last) {
   const int per_field = p.nx + p.ny + p.nt;
   TableArgs ta{};
   ta.row_stride = table_row_stride(p.nf, p.nx, p.ny, p.nt);
@@ -357,6 +367,7 @@ brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count, int row0
   ta.dk = p.dk.empty() ? nullptr : reinterpret_cast<const double*>(p.ws + p.off_dk);
   ta.n0 = n0;
   ta.n0_dev = p.table_n0_dev;
+  ta.merge_last = merge_last;
   ta.count = count;
   p.table_n0 = n0;
   ta.nx = p.nx; ta.ny = p.ny; ta.nt = p.nt; ta.nf = p.nf;
@@ -428,7 +439,7 @@ brahms_status map_table(brahms_plan_s& p, long long n0, int count) {
 
 }  // namespace
 
-brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io) {
+brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io, bool continued) {
   const bool map = !p.dk_map.empty();
   if (map && p.map_rows == 1)
     if (brahms_status st = map_table(p, p.table_n0 + row, 1)) return st;
@@ -436,10 +447,11 @@ brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io) {
   // the first pass carries the first RK4 half-step, the last pass the second
   // one (the axis operators commute)
   const StepPasses sp = step_passes(p, false);
+  if (continued && map) return fail(BRAHMS_E_UNSUPPORTED, "merged half-steps with a map");
   for (int k = 0; k < sp.n; ++k) {
     const int ax = sp.ax[k];
     const bool first = k == 0, last = k == sp.n - 1;
-    int nlmode = sp.nl[k];
+    int nlmode = first && continued ? (sp.nl[k] & ~NL_BEFORE) : sp.nl[k];
     PassArgs a = pass_args(p, row, ax);
     if (map && nlmode != NL_NONE) {
       nlmode |= NL_MAP;
@@ -451,7 +463,7 @@ brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io) {
       a.fo[j] = io.out[j];
       a.pre[j] = last ? io.pre[j] : nullptr;
     }
-    a.nl = nl_coefficients(p, row, first ? 0 : 1);
+    a.nl = nl_coefficients(p, row, 0);
     a.nl2 = nl_coefficients(p, row, 1);
     if (brahms_status st = timed_dispatch(p, ax, nlmode, a)) return st;
   }
@@ -499,8 +511,10 @@ void drop_chunk_graph(brahms_plan_s& p) {
 }
 
 // Capture the tables and the 64 steps of one chunk on a private stream; the
-// tables read the chunk's first step from the workspace (set before each
-// replay), everything else is the same for every chunk.
+// tables read the chunk's first step (and, with merged halves, the run's last
+// step) from the workspace, set before each replay; everything else is the
+// same for every chunk.  With merged halves the captured chunk continues a
+// run: none of its steps has a first half-step of its own.
 brahms_status build_chunk_graph(brahms_plan_s& p) {
   drop_chunk_graph(p);
   if (!p.capture_stream) HIP_TRY(hipStreamCreateWithFlags(&p.capture_stream, hipStreamNonBlocking));
@@ -512,8 +526,9 @@ brahms_status build_chunk_graph(brahms_plan_s& p) {
   hipError_t e = hipStreamBeginCapture(p.capture_stream, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     const detail::StepIO io = plain_io(p);
+    const bool continued = detail::merging(p);
     st = detail::refresh_tables(p, 0, kChunk);
-    for (int s = 0; s < kChunk && st == BRAHMS_OK; ++s) st = detail::launch_step(p, s, io);
+    for (int s = 0; s < kChunk && st == BRAHMS_OK; ++s) st = detail::launch_step(p, s, io, continued);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(p.capture_stream, &g);
     if (st == BRAHMS_OK && e == hipSuccess) {
@@ -537,16 +552,25 @@ brahms_status build_chunk_graph(brahms_plan_s& p) {
   return BRAHMS_OK;
 }
 
+// nsteps z-steps from p.step.  With merged halves, the first step of the call
+// keeps its first half-step, every step but the last ends with one RK4 step
+// of size dz that also covers the next step's first half, and the last ends
+// on its own second half-step, so the fields after the call are those at a
+// step boundary.
 brahms_status run_steps(brahms_plan_s& p, int nsteps) {
   const detail::StepIO io = plain_io(p);
+  const bool merge = detail::merging(p);
+  const long long merge_last = merge ? p.step + nsteps - 1 : -1;
   int done = 0;
   while (done < nsteps) {
     const int count = std::min(kChunk, nsteps - done);
-    if (count == kChunk && graph_chunk_ok(p)) {
+    // a captured chunk has no leading half-step when merging, so the call's
+    // first chunk runs eagerly
+    if (count == kChunk && graph_chunk_ok(p) && !(merge && done == 0)) {
       if (!p.chunk_exec)
         if (brahms_status st = build_chunk_graph(p)) return st;
       hipLaunchKernelGGL(set_step_index, dim3(1), dim3(1), 0, p.stream,
-                         reinterpret_cast<long long*>(p.ws + p.off_n0), p.step);
+                         reinterpret_cast<long long*>(p.ws + p.off_n0), p.step, merge_last);
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipGraphLaunch(p.chunk_exec, p.stream));
       p.table_n0 = p.step;
@@ -554,10 +578,11 @@ brahms_status run_steps(brahms_plan_s& p, int nsteps) {
       done += count;
       continue;
     }
-    if (brahms_status st = detail::refresh_tables(p, p.step, count)) return st;
+    if (brahms_status st = detail::refresh_tables(p, p.step, count, 0, merge_last)) return st;
     const bool watch = p.mon_every > 0 || !p.snap_steps.empty();
     for (int s = 0; s < count; ++s) {
-      if (brahms_status st = detail::launch_step(p, s, io)) return st;
+      const bool continued = merge && (done > 0 || s > 0);
+      if (brahms_status st = detail::launch_step(p, s, io, continued)) return st;
       if (watch)
         if (brahms_status st = detail::after_step(p, p.step + s + 1)) return st;
     }
@@ -753,9 +778,16 @@ brahms_status brahms_plan_set_schedule(brahms_plan plan, const brahms_schedule* 
   if (sched->pass_order < 0 || sched->pass_order > 3)
     return fail(BRAHMS_E_INVALID_ARG, "pass_order must be 0, 1, 2 or 3");
   if (sched->graph != 0 && sched->graph != 1) return fail(BRAHMS_E_INVALID_ARG, "graph must be 0 or 1");
-  if (plan->order != sched->pass_order || plan->use_graph != (sched->graph != 0)) drop_chunk_graph(*plan);
+  if (sched->merge_halves != 0 && sched->merge_halves != 1)
+    return fail(BRAHMS_E_INVALID_ARG, "merge_halves must be 0 or 1");
+  if (sched->merge_halves && (!plan->dk.empty() || !plan->dk_map.empty()))
+    return fail(BRAHMS_E_UNSUPPORTED, "merge_halves needs a constant dk and no transverse map");
+  if (plan->order != sched->pass_order || plan->use_graph != (sched->graph != 0) ||
+      plan->merge != (sched->merge_halves != 0))
+    drop_chunk_graph(*plan);
   plan->order = sched->pass_order;
   plan->use_graph = sched->graph != 0;
+  plan->merge = sched->merge_halves != 0;
   // capture now rather than in the first call that replays it
   if (graph_chunk_ok(*plan) && !plan->chunk_exec) return build_chunk_graph(*plan);
   return BRAHMS_OK;
@@ -767,6 +799,7 @@ brahms_status brahms_plan_get_schedule(brahms_plan plan, brahms_schedule* sched)
   *sched = brahms_schedule{};
   sched->pass_order = plan->order;
   sched->graph = plan->use_graph ? 1 : 0;
+  sched->merge_halves = plan->merge ? 1 : 0;
   return BRAHMS_OK;
 }
 

@@ -52,8 +52,10 @@ struct PassArgs {
   const float2* tw;      // this step's forward twiddles exp(-2 pi i m / N), m < N
   const float2* prop;    // this step's propagators, field j's table of this
                          // axis at prop + j * field_stride + axis_off
-  const float2* nl;      // RK4 coefficients of this half-step, [nf][6]
-  const float2* nl2;     // NL_BOTH: those of the second half-step
+  const float2* nl;      // RK4 coefficients of the step's first half-step, [nf][6]
+  const float2* nl2;     // those of its second half-step (or, when adjacent
+                         // halves are merged, of one RK4 step of size dz
+                         // from z_n + dz/2)
   const DftConsts* consts;  // this step's register-DFT constants
   int nx, ny, nt;
   int axis_off, field_stride;
@@ -73,6 +75,9 @@ struct PassArgs {
 // with a1 = h/2 c(z_a), a2 = h/2 c(z_m), a3 = h c(z_m), b1 = h/6 c(z_a),
 // b2 = h/3 c(z_m), b4 = h/6 c(z_a + h), z_m = z_a + h/2.  The coefficients
 // are formed in double precision per half-step by the table kernel.
+// Adjacent halves (the second half of step n and the first of step n + 1)
+// may be merged into one RK4 step of size h = dz from z_n + dz/2: the exact
+// flows compose, and the two integrators differ by O(h^5) per step.
 // ---------------------------------------------------------------------------
 template <int NF>
 __device__ inline void chi2_products(const float2* y, float2* q) {
@@ -286,7 +291,8 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
 #pragma unroll
     for (int j = 0; j < NF; ++j)
 #pragma unroll
-      for (int c = 0; c < kNlCoef; ++c) co[j][c] = wave_uniform(args.nl[j * kNlCoef + c]);
+      for (int c = 0; c < kNlCoef; ++c)
+        co[j][c] = wave_uniform(((NLM & NL_BEFORE) != 0 ? args.nl : args.nl2)[j * kNlCoef + c]);
   }
   // this step's twiddles and this block's propagators, staged once
   if constexpr (LONG) {
@@ -498,7 +504,7 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
 template <int N1, int N2, int AX, int NF, int NL, bool FULL>
 __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass(PassArgs args) {
   // passes with one field per block take it from blockIdx.z
-  constexpr bool per_field = NF == 1 && (AX == AX_Y || AX == AX_T || long_tau_kind(AX));
+  constexpr bool per_field = NF == 1;
   axis_pass_body<N1, N2, AX, NF, NL, FULL>(args, blockIdx.x, per_field ? int(blockIdx.z) : 0);
 }
 
@@ -511,7 +517,7 @@ __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass_batched(
     const PassArgs* descs, long long step, int nf) {
   // linear y and long-tau passes take one field per block: problem and field
   // from blockIdx.z
-  constexpr bool per_field = NF == 1 && (AX == AX_Y || AX == AX_T || long_tau_kind(AX));
+  constexpr bool per_field = NF == 1;
   const unsigned inst = per_field ? blockIdx.z / unsigned(nf) : blockIdx.y;
   const PassArgs& a = descs[inst];
   if (step >= a.nz) return;
@@ -550,7 +556,10 @@ struct TableArgs {
   const double* phi0;    // Phi_n prefix (profile) or null
   const double* dk;      // dk_n (profile) or null
   long n0;               // first step of the rows (unless n0_dev is set)
-  const long long* n0_dev;  // device copy of n0 (graph replays), or null
+  const long long* n0_dev;  // device copies of n0 and merge_last (graph
+                            // replays), or null
+  long long merge_last;  // steps n < merge_last get the merged second
+                         // half-step coefficients; -1: none (constant dk only)
   int count;
   int nx, ny, nt, nf;
   int row_stride;
@@ -559,7 +568,11 @@ struct TableArgs {
 };
 
 __device__ inline long table_n0(const TableArgs& a) {
-  return a.n0_dev != nullptr ? long(*a.n0_dev) : a.n0;
+  return a.n0_dev != nullptr ? long(a.n0_dev[0]) : a.n0;
+}
+
+__device__ inline long long table_merge_last(const TableArgs& a) {
+  return a.n0_dev != nullptr ? a.n0_dev[1] : a.merge_last;
 }
 
 __host__ __device__ inline int table_row_stride(int nf, int nx, int ny, int nt) {
@@ -700,11 +713,15 @@ __device__ __forceinline__ void step_tables_body(const TableArgs& a, long gid) {
   double sigma;
   if (a.nf == 3) sigma = (j == 0) ? -1.0 : 1.0;
   else sigma = (j == 0) ? 1.0 : -1.0;
-  const double h = 0.5 * a.dz;
+  // merged: one step of size dz from z_n + dz/2 (stages at dz/2, dz, 3 dz/2
+  // past z_n; only for a constant dk, so Phi stays linear across z_{n+1})
+  const bool merged = half == 1 && n < table_merge_last(a);
+  const double h = merged ? a.dz : 0.5 * a.dz;
   const double kap = a.fc[j].kappa;
   double2 c[3];  // c_j at z_a, z_a + h/2, z_a + h
   for (int k = 0; k < 3; ++k) {
-    const double off = (double(half) * 2.0 + double(k)) * 0.25 * a.dz;  // z - z_n
+    const double off = merged ? (0.5 + 0.5 * double(k)) * a.dz                   // z - z_n
+                              : (double(half) * 2.0 + double(k)) * 0.25 * a.dz;
     const double ph = reduce_2pi(phi_n + dkn * off);
     double sn, cs;
     sincos(ph, &sn, &cs);
@@ -763,9 +780,13 @@ static __global__ void map_phase_table(MapArgs a) {
   }
 }
 
-// First step index of a chunk, for tables read by a replayed graph.
-static __global__ void set_step_index(long long* dst, long long n0) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *dst = n0;
+// First step index of a chunk and the last step of the run (merged halves),
+// for tables read by a replayed graph.
+static __global__ void set_step_index(long long* dst, long long n0, long long merge_last) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    dst[0] = n0;
+    dst[1] = merge_last;
+  }
 }
 
 static __global__ void finite_check(const float2* f, long n, int* flag) {

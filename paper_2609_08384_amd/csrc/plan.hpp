@@ -26,12 +26,16 @@ struct brahms_plan_s {
   bool bound = false;
   long long step = 0;          // z = step * dz
   int order = 0;               // 0: x, y, tau passes; 1: tau, y, x
+  // schedule field merge_halves: adjacent RK4 half-steps of one call run as
+  // one RK4 step of size dz (constant dk, no map, no monitor or snapshots)
+  bool merge = false;
   // hipGraph replay of whole 64-step chunks (schedule field `graph`)
   bool use_graph = false;
   hipGraph_t chunk_graph = nullptr;
   hipGraphExec_t chunk_exec = nullptr;
   hipStream_t capture_stream = nullptr;   // private stream the chunk is captured on
-  const long long* table_n0_dev = nullptr;  // while capturing: tables read n0 here
+  const long long* table_n0_dev = nullptr;  // while capturing: tables read n0
+                                            // and merge_last here
   // workspace offsets (bytes)
   size_t off_phi0 = 0, off_dk = 0, off_prop = 0, off_nl = 0, off_flag = 0, ws_size = 0;
   size_t off_map = 0, off_maptab = 0;   // map (FP64) and its per-step phase tables
@@ -114,8 +118,15 @@ struct StepIO {
   float2* pre[3];
 };
 
-// Fill table rows row0..row0+count-1 for steps n0..n0+count-1.
-brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count, int row0 = 0);
+// Fill table rows row0..row0+count-1 for steps n0..n0+count-1; steps
+// n < merge_last get the merged second half-step (see merging()).
+brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count, int row0 = 0,
+                             long long merge_last = -1);
+// Whether a call of brahms_propagate merges adjacent half-steps: only for a
+// constant dk (Phi linear in z across a step boundary) with no transverse
+// map, and not while monitor records or snapshots are due (every step they
+// look at must end on its own second half-step).
+bool merging(const brahms_plan_s& p);
 // The passes of one z-step in order: axis (AX_*) and RK4 mode (NL_*) of
 // each.  Three passes in general; passes along an axis of length 1 are left
 // out when they would multiply by exactly 1 (so the result is unchanged bit
@@ -129,8 +140,9 @@ struct StepPasses {
   int nl[5];
 };
 StepPasses step_passes(const brahms_plan_s& p, bool batched);
-// One z-step with the tables of `row`.
-brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io);
+// One z-step with the tables of `row`; with continued = true the step's first
+// half-step is left out (it was merged into the previous step's second one).
+brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io, bool continued = false);
 // The axis of the k-th pass of a step (k = 0, 1, 2) under the plan's order.
 int pass_axis(const brahms_plan_s& p, int k);
 // A linear-only pass (FFT . P . IFFT, or with conj(P)) along `axis`, in place.

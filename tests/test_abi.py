@@ -5,7 +5,6 @@ import os
 import re
 
 import numpy as np
-
 import pytest
 
 from paper_2609_08384_amd import brahms
@@ -184,7 +183,20 @@ def test_schedule_host_checks(lib):
     assert lib.brahms_plan_set_schedule(h, ctypes.byref(sc)) == brahms.BRAHMS_OK  # unbound: no capture
     out = brahms.ScheduleC()
     assert lib.brahms_plan_get_schedule(h, ctypes.byref(out)) == brahms.BRAHMS_OK
-    assert (out.pass_order, out.graph) == (1, 1)
+    assert (out.pass_order, out.graph, out.merge_halves) == (1, 1, 0)
+    sc.merge_halves = 2
+    assert lib.brahms_plan_set_schedule(h, ctypes.byref(sc)) == brahms.BRAHMS_E_INVALID_ARG
+    sc.merge_halves = 1
+    assert lib.brahms_plan_set_schedule(h, ctypes.byref(sc)) == brahms.BRAHMS_OK
+    assert lib.brahms_plan_get_schedule(h, ctypes.byref(out)) == brahms.BRAHMS_OK
+    assert out.merge_halves == 1
+    lib.brahms_plan_destroy(h)
+    # merged half-steps need Phi linear across step boundaries: no dk profile
+    # and no transverse map
+    c2, keep2 = _params(dk=np.ones(10))
+    st, h = _create(lib, 8, 8, 8, 2, c2)
+    assert st == brahms.BRAHMS_OK
+    assert lib.brahms_plan_set_schedule(h, ctypes.byref(sc)) == brahms.BRAHMS_E_UNSUPPORTED
     lib.brahms_plan_destroy(h)
 
 

@@ -7,7 +7,7 @@ import torch
 
 from oracle import ssfm
 from paper_2609_08384_amd import brahms, inputs
-from tests.util import oracle_problem, rel_l2, to_torch
+from tests.util import oracle_problem, oracle_run, rel_l2, to_torch
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -140,9 +140,43 @@ def test_whole_sweep_matches_oracle_and_single_runs():
             assert rel_l2(flat[g[key + f"f{j}_top_idx"]], g[key + f"f{j}_top"]) < 3e-5, (i, j)
             p = (np.abs(f.cpu().numpy().astype(np.complex128)) ** 2).sum(axis=(1, 2))
             assert rel_l2(p, g[key + f"f{j}_power"]) < 4e-5, (i, j)
-        alone = brahms.run_workload(w, device=DEV, pass_order=o)
+        alone = brahms.run_workload(w, device=DEV, pass_order=o, merge_halves=tuned["merge_halves"])
         for a, b in zip(fs, alone):
             assert torch.equal(a, b), i
+
+
+@pytest.mark.parametrize("group_max", [0, 1])
+def test_merged_batch_equals_plain_runs_and_oracle(group_max):
+    """Merged half-steps in a batch (constant dk): each problem, with its own
+    last step, bitwise equal to the same problem run alone with merged
+    half-steps, and within the oracle tolerance; a batch with a dk profile
+    refuses merging."""
+    wls = _problems(seed=13)
+    for w in wls:
+        w.dk = None
+    probs = [(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls]
+    orders = [(k + 1) % 4 for k in range(len(wls))]
+    batch = brahms.Batch(probs)
+    batch.set_schedule(group_max, orders)
+    batch.set_merge_halves(1)
+    fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
+    batch.bind(fields)
+    batch.run()
+    torch.cuda.synchronize()
+    batch.destroy()
+    for w, fs, o in zip(wls, fields, orders):
+        alone = brahms.run_workload(w, device=DEV, pass_order=o, merge_halves=1)
+        for a, b in zip(fs, alone):
+            assert torch.equal(a, b), (w.nx, w.ny, w.nt, w.nz)
+    for w, fs in list(zip(wls, fields))[:3]:
+        for a, r in zip(fs, oracle_run(w, merge=True)):
+            assert rel_l2(a.cpu().numpy(), r.numpy()) < 1e-5
+    prof = _problems(seed=13)[:2]
+    b2 = brahms.Batch([(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in prof])
+    with pytest.raises(brahms.BrahmsError) as ei:
+        b2.set_merge_halves(1)
+    assert ei.value.status == brahms.BRAHMS_E_UNSUPPORTED
+    b2.destroy()
 
 
 def test_group_limits_reject_negative():

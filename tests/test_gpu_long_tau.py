@@ -9,7 +9,7 @@ import torch
 
 from oracle import ssfm
 from paper_2609_08384_amd import brahms, inputs
-from tests.util import oracle_problem, rel_l2, to_torch
+from tests.util import oracle_problem, oracle_run, rel_l2, to_torch
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -61,10 +61,10 @@ def test_coupled_long_tau(nf, shape, profile, map_):
                          dk=(1.0 + rng.standard_normal(nz)) if profile else None,
                          dk_map=rng.uniform(-4, 4, (ny, nx)) if map_ else None)
     wl.init = _pulse_fields(rng, nf, nx, ny, nt, 0.8)
-    out = brahms.run_workload(wl, device=DEV)
-    ref = ssfm.propagate([to_torch(a) for a in wl.init], oracle_problem(wl), wl.nz)
-    for a, r in zip(out, ref):
-        assert rel_l2(a.cpu().numpy(), r.numpy()) < 1e-5
+    for m in ([0] if profile or map_ else [0, 1]):
+        out = brahms.run_workload(wl, device=DEV, merge_halves=m)
+        for a, r in zip(out, oracle_run(wl, merge=bool(m))):
+            assert rel_l2(a.cpu().numpy(), r.numpy()) < 1e-5, m
 
 
 def test_paper_grid_opg_64x64x1024():
@@ -86,8 +86,9 @@ def test_paper_grid_opg_64x64x1024():
         assert rel_l2(a.cpu().numpy(), r.numpy()) < 1e-5
 
 
+@pytest.mark.parametrize("merge", [0, 1])
 @pytest.mark.parametrize("group_max", [0, 1])
-def test_long_tau_in_batches(group_max):
+def test_long_tau_in_batches(group_max, merge):
     """Long-tau problems (nt = 512, 1024, 4096) in a batch with an ordinary
     one: each bitwise equal to the same problem run alone, and one against
     the oracle."""
@@ -100,15 +101,15 @@ def test_long_tau_in_batches(group_max):
         wls.append(wl)
     batch = brahms.Batch([(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls])
     batch.set_schedule(group_max)
+    batch.set_merge_halves(merge)
     fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
     batch.bind(fields)
     batch.run()
     torch.cuda.synchronize()
     batch.destroy()
     for w, fs in zip(wls, fields):
-        alone = brahms.run_workload(w, device=DEV)
+        alone = brahms.run_workload(w, device=DEV, merge_halves=merge)
         for a, b in zip(fs, alone):
             assert torch.equal(a, b), (w.nx, w.ny, w.nt)
-    ref = ssfm.propagate([to_torch(a) for a in wls[1].init], oracle_problem(wls[1]), wls[1].nz)
-    for a, r in zip(fields[1], ref):
+    for a, r in zip(fields[1], oracle_run(wls[1], merge=bool(merge))):
         assert rel_l2(a.cpu().numpy(), r.numpy()) < 1e-5

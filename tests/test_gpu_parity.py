@@ -7,9 +7,8 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import ssfm
 from paper_2609_08384_amd import brahms, inputs
-from tests.util import oracle_problem, rel_l2, to_torch
+from tests.util import oracle_run, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -31,15 +30,13 @@ def _wl(nx, ny, nt, nf, nz, dz, fields, dk_const=0.0, dk=None, init=None):
     return wl
 
 
-def _gpu(wl, nsteps=None, pass_order=None):
-    out = brahms.run_workload(wl, nsteps=nsteps, device=DEV, pass_order=pass_order)
+def _gpu(wl, nsteps=None, pass_order=None, merge=0):
+    out = brahms.run_workload(wl, nsteps=nsteps, device=DEV, pass_order=pass_order, merge_halves=merge)
     return [f.cpu().numpy() for f in out]
 
 
-def _oracle(wl, nsteps=None):
-    nsteps = wl.nz if nsteps is None else nsteps
-    out = ssfm.propagate([to_torch(a) for a in wl.init], oracle_problem(wl), nsteps)
-    return [a.numpy() for a in out]
+def _oracle(wl, nsteps=None, merge=0):
+    return [a.numpy() for a in oracle_run(wl, nsteps, merge=bool(merge))]
 
 
 def _all_terms(nf, scale=1.0, kappa=0.0):
@@ -66,13 +63,15 @@ def test_linear_step_each_axis_length(shape):
         assert rel_l2(g[j], o[j]) < 2e-6, (shape, j)
 
 
-def test_plane_wave_depleted_shg():
+@pytest.mark.parametrize("merge", [0, 1])
+def test_plane_wave_depleted_shg(merge):
     """Uniform fields: only the k = 0 mode, so the loop is the RK4 half-steps
-    alone; depleted SHG has F = F0 sech(G z), S = i sqrt(kS/kF) F0 tanh(G z)."""
+    alone; depleted SHG has F = F0 sech(G z), S = i sqrt(kS/kF) F0 tanh(G z)
+    (also with adjacent halves merged into RK4 steps of size dz)."""
     kf, ks, f0, nz = 1.3, 0.6, 1.5, 100
     init = [np.full((4, 4, 4), f0, np.complex64), np.zeros((4, 4, 4), np.complex64)]
     wl = _wl(4, 4, 4, 2, nz, 1.0 / nz, [inputs.FieldSpec(kappa=kf), inputs.FieldSpec(kappa=ks)], init=init)
-    f, s = _gpu(wl)
+    f, s = _gpu(wl, merge=merge)
     g = math.sqrt(kf * ks) * f0
     bound = _accumulation_bound(2 * nz, f0)
     assert np.abs(f - f0 / math.cosh(g)).max() < bound
@@ -107,19 +106,35 @@ def test_plane_wave_opa():
     assert np.abs(i - wi).max() < _accumulation_bound(2 * nz, abs(wi)) + 1e-7 * abs(wi)
 
 
+@pytest.mark.parametrize("merge", [0, 1])
 @pytest.mark.parametrize("order", [0, 1, 2, 3])
 @pytest.mark.parametrize("nf,shape", [(2, (32, 32, 32)), (3, (32, 32, 32)), (3, (64, 16, 96)),
                                       (2, (96, 96, 4)), (3, (16, 128, 64))])
-def test_coupled_steps_random(nf, shape, order):
-    """All linear terms and the chi(2) coupling, 10 steps, ragged tiles, both
-    pass orders."""
+def test_coupled_steps_random(nf, shape, order, merge):
+    """All linear terms and the chi(2) coupling, 10 steps, ragged tiles, every
+    pass order, literal and merged half-steps."""
     nx, ny, nt = shape
     rng = np.random.default_rng(100 + nf)
     init = inputs.random_fields(rng, nf, nx, ny, nt, scale=0.7, smooth=min(nx, ny, nt) / 2.0)
     wl = _wl(nx, ny, nt, nf, 10, 0.02, _all_terms(nf, kappa=1.5), dk_const=2.3, init=init)
-    g, o = _gpu(wl, pass_order=order), _oracle(wl)
+    g, o = _gpu(wl, pass_order=order, merge=merge), _oracle(wl, merge=merge)
     for j in range(nf):
         assert rel_l2(g[j], o[j]) < 5e-6, j
+
+
+@pytest.mark.parametrize("shape", [(32, 16, 8), (1, 1, 256), (256, 2, 1), (8, 96, 1), (96, 64, 2)])
+def test_merged_half_steps_differ_from_literal_by_truncation_only(shape):
+    """Merged halves really run (the bits differ from the literal splitting)
+    and match the oracle's merged loop; every pass structure (three passes,
+    the single tau pass of nx = ny = 1, CW grids)."""
+    nx, ny, nt = shape
+    rng = np.random.default_rng(sum(shape))
+    init = inputs.random_fields(rng, 3, nx, ny, nt, scale=0.7, smooth=max(1.0, min(nx, ny, nt) / 2.0))
+    wl = _wl(nx, ny, nt, 3, 40, 0.02, _all_terms(3, kappa=1.5), dk_const=-1.7, init=init)
+    lit, mer, o = _gpu(wl), _gpu(wl, merge=1), _oracle(wl, merge=1)
+    assert any(not np.array_equal(a, b) for a, b in zip(lit, mer))
+    for j in range(3):
+        assert rel_l2(mer[j], o[j]) < 5e-6, j
 
 
 def test_dk_profile_matches_oracle():
@@ -133,11 +148,12 @@ def test_dk_profile_matches_oracle():
         assert rel_l2(g[j], o[j]) < 5e-6
 
 
+@pytest.mark.parametrize("merge", [0, 1])
 @pytest.mark.parametrize("order", [0, 1, 2, 3])
-def test_shg32_full_run(order):
+def test_shg32_full_run(order, merge):
     """SHG 32^3, 100 steps (the small benchmark workload): <= 1e-5 per field."""
     wl = inputs.shg32()
-    g, o = _gpu(wl, pass_order=order), _oracle(wl)
+    g, o = _gpu(wl, pass_order=order, merge=merge), _oracle(wl, merge=merge)
     for j in range(2):
         assert rel_l2(g[j], o[j]) < 1e-5, j
 
@@ -184,7 +200,9 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 def _check_golden(out, name, tol):
     """Compare a GPU run with the oracle reference data written by
     tests/golden/make_golden.py: sampled values, power traces P(tau),
-    fluence maps and Manley-Rowe combinations."""
+    fluence maps and Manley-Rowe combinations.  The data are those of the
+    literal loop; at the step sizes of these workloads the merged loop
+    differs from it by ~1e-11 (FP64), so they serve merged runs too."""
     g = np.load(f"{GOLDEN}/{name}.npz")
     for j, a in enumerate(out):
         flat = a.reshape(-1)
@@ -199,27 +217,30 @@ def _check_golden(out, name, tol):
     return g
 
 
-@pytest.mark.parametrize("order", [0, 1, 2, 3])
-def test_sfg128_full_run_vs_oracle(order):
+SCHEDULES = [(0, 0), (1, 0), (2, 0), (3, 0), (0, 1), (1, 1), (2, 1), (3, 1)]
+
+
+@pytest.mark.parametrize("order,merge", SCHEDULES)
+def test_sfg128_full_run_vs_oracle(order, merge):
     """SFG 128^3, 500 steps, pump depletion: <= 2e-5 per field."""
     wl = inputs.sfg128()
-    out = _gpu(wl, pass_order=order)
+    out = _gpu(wl, pass_order=order, merge=merge)
     g = _check_golden(out, "sfg128_500", 2e-5)
     e = [float((np.abs(a.astype(np.complex128)) ** 2).sum()) for a in out]
     assert np.allclose(e, g["energies"], rtol=4e-5)
 
 
-@pytest.mark.parametrize("order", [0, 1, 2, 3])
-def test_opg256_first_steps_vs_oracle(order):
+@pytest.mark.parametrize("order,merge", SCHEDULES)
+def test_opg256_first_steps_vs_oracle(order, merge):
     """OPG 256^3 (the benchmark workload), first 10 steps at full size, in the
     launch configurations the benchmark may time: <= 3e-5 per field."""
     wl = inputs.opg256()
-    out = _gpu(wl, 10, pass_order=order)
+    out = _gpu(wl, 10, pass_order=order, merge=merge)
     _check_golden(out, "opg256_10", 3e-5)
 
 
-@pytest.mark.parametrize("order", [0, 1, 2, 3])
-def test_opg256_full_run_vs_oracle(order):
+@pytest.mark.parametrize("order,merge", SCHEDULES)
+def test_opg256_full_run_vs_oracle(order, merge):
     """OPG 256^3, all 1000 steps (the benchmark workload end to end, in both
     launch configurations the benchmark may time): <= 3e-5 per field on the
     sampled values, power traces and fluence maps; energies and Manley-Rowe
@@ -227,7 +248,7 @@ def test_opg256_full_run_vs_oracle(order):
     if not os.path.exists(f"{GOLDEN}/opg256_1000.npz"):
         pytest.skip("reference data not generated")
     wl = inputs.opg256()
-    out = _gpu(wl, pass_order=order)
+    out = _gpu(wl, pass_order=order, merge=merge)
     g = _check_golden(out, "opg256_1000", 3e-5)
     e = [float((np.abs(a.astype(np.complex128)) ** 2).sum()) for a in out]
     assert np.allclose(e, g["energies"], rtol=6e-5)
@@ -276,4 +297,59 @@ def test_graph_schedule_is_bitwise_eager(order):
     eager = run(0, calls)
     graph = run(1, calls)
     for a, b in zip(eager, graph):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
+def test_graph_schedule_with_merged_halves_is_bitwise_eager(order):
+    """Merged half-steps: graph replays (which continue a call, so a call's
+    first chunk runs eagerly) give the bits of launch-by-launch stepping over
+    ragged calls, a resume, a monitor (whose calls keep literal half-steps)
+    and a rebind; and merged calls differ from literal ones."""
+    rng = np.random.default_rng(78)
+    nz = 500
+    fs = [inputs.FieldSpec(kappa=1.2, diffraction=0.8, tan_rho=0.3, k2=0.5),
+          inputs.FieldSpec(kappa=0.9, diffraction=0.4, delay=-0.6, k2=-0.7),
+          inputs.FieldSpec(kappa=0.5, diffraction=1.1, delay=0.4, k2=0.2)]
+    wl = inputs.Workload("g", 32, 16, 8, 3, nz, 1.0 / nz, fs, dk_const=2.5)
+    wl.init = inputs.random_fields(rng, 3, 32, 16, 8, scale=0.5, smooth=6.0)
+    params = brahms.params_from_workload(wl)
+
+    def run(graph, merge, calls):
+        f = [torch.from_numpy(a).to(DEV) for a in wl.init]
+        plan = brahms.Plan(wl.nx, wl.ny, wl.nt, wl.nf, params)
+        plan.set_schedule(order, graph, merge)
+        plan.bind(f)
+        for c in calls:
+            if c == "monitor":
+                plan.set_monitor(10, capacity=8)
+            elif c == "nomonitor":
+                plan.set_monitor(0)
+            elif c == "rebind":
+                f = [x.clone() for x in f]
+                plan.bind(f)
+            elif isinstance(c, tuple):
+                plan.set_z(c[1] * wl.dz)
+            else:
+                plan.step(c)
+        torch.cuda.synchronize()
+        out = [x.clone() for x in f]
+        plan.destroy()
+        return out
+
+    calls = [200, 64, ("z", 100), 129, "monitor", 64, "nomonitor", "rebind", 64, 5, 140]
+    eager = run(0, 1, calls)
+    graph = run(1, 1, calls)
+    for a, b in zip(eager, graph):
+        assert torch.equal(a, b)
+    literal = run(0, 0, calls)
+    for a, b in zip(eager, literal):
+        assert not torch.equal(a, b)
+        # ~730 steps: the two differ by their FP32 rounding (each ~1e-5 of
+        # the exact result at this length), the truncation term is ~1e-11
+        assert float((a - b).norm() / b.norm()) < 2e-5
+    # with a monitor set the calls keep literal half-steps: the same bits as
+    # a plan without merging
+    mon = ["monitor", 70]
+    for a, b in zip(run(0, 1, mon), run(0, 0, mon)):
         assert torch.equal(a, b)

@@ -12,17 +12,18 @@ import torch
 
 from oracle import ssfm
 from paper_2609_08384_amd import brahms, inputs
-from tests.util import bk_efficiency, oracle_problem, rel_l2, to_torch
+from tests.util import bk_efficiency, oracle_problem, oracle_run, rel_l2
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def _batch_run(wls, group_max=0, orders=None):
+def _batch_run(wls, group_max=0, orders=None, merge=0):
     probs = [(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls]
     batch = brahms.Batch(probs)
     batch.set_schedule(group_max, orders)
+    batch.set_merge_halves(merge)
     fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
     batch.bind(fields)
     batch.run()
@@ -31,7 +32,8 @@ def _batch_run(wls, group_max=0, orders=None):
     return fields
 
 
-def test_focusing_sweep_matches_boyd_kleinman():
+@pytest.mark.parametrize("merge", [0, 1])
+def test_focusing_sweep_matches_boyd_kleinman(merge):
     """99 CW problems (11 xi x 9 dk L on 128^2, 200 steps) in one batch: each
     efficiency within the paper's 0.2 % of the closed form (and within 2e-4),
     the best grid point at xi = 2.8, dk L = -3.2 (nearest to the printed
@@ -39,7 +41,7 @@ def test_focusing_sweep_matches_boyd_kleinman():
     with open(os.path.join(GOLDEN, "boyd_kleinman.json")) as fh:
         g = json.load(fh)
     wls = inputs.bk_sweep()
-    out = _batch_run(wls)
+    out = _batch_run(wls, merge=merge)
     eff = np.zeros((len(inputs.BK_XI), len(inputs.BK_DKL)))
     worst = 0.0
     for k, (w, fs) in enumerate(zip(wls, out)):
@@ -59,23 +61,24 @@ def test_focusing_sweep_matches_boyd_kleinman():
     assert abs(h - 1.068) < 2e-3, h
 
 
-def test_focusing_sweep_instances_match_oracle():
+@pytest.mark.parametrize("merge", [0, 1])
+def test_focusing_sweep_instances_match_oracle(merge):
     wls = [inputs.bk_cw_instance(2.8, -3.2), inputs.bk_cw_instance(4.0, -2.4)]
-    out = _batch_run(wls)
+    out = _batch_run(wls, merge=merge)
     for w, fs in zip(wls, out):
-        ref = ssfm.propagate([to_torch(a) for a in w.init], oracle_problem(w), w.nz)
-        for a, r in zip(fs, ref):
+        for a, r in zip(fs, oracle_run(w, merge=bool(merge))):
             assert rel_l2(a.cpu().numpy(), r.numpy()) < 1e-5
 
 
-def test_plane_wave_pulses_match_oracle():
+@pytest.mark.parametrize("merge", [0, 1])
+def test_plane_wave_pulses_match_oracle(merge):
     """16 pulsed plane-wave problems (1 x 1 x 256, 100-300 steps, depleted
     pump) in one batch against the oracle."""
     wls = inputs.plane_wave_pulse_sweep()
-    out = _batch_run(wls)
+    out = _batch_run(wls, merge=merge)
     conv = []
     for w, fs in zip(wls, out):
-        ref = ssfm.propagate([to_torch(a) for a in w.init], oracle_problem(w), w.nz)
+        ref = oracle_run(w, merge=bool(merge))
         for a, r in zip(fs, ref):
             assert rel_l2(a.cpu().numpy(), r.numpy()) < 1e-5, w.name
         e = ssfm.energies(ref, oracle_problem(w))
@@ -84,15 +87,16 @@ def test_plane_wave_pulses_match_oracle():
     assert max(conv) > 0.5
 
 
+@pytest.mark.parametrize("merge", [0, 1])
 @pytest.mark.parametrize("group_max", [0, 1])
-def test_reduced_dims_batched_equal_single_runs(group_max):
+def test_reduced_dims_batched_equal_single_runs(group_max, merge):
     wls = [inputs.bk_cw_instance(2.0, -4.0, n=64, nz=30), inputs.bk_cw_instance(3.0, -3.0, n=64, nz=17)]
     wls += inputs.plane_wave_pulse_sweep(count=3)
     for w in wls[2:]:
         w.nz = min(w.nz, 40)
     orders = [k % 4 for k in range(len(wls))]
-    out = _batch_run(wls, group_max, orders)
+    out = _batch_run(wls, group_max, orders, merge)
     for w, fs, o in zip(wls, out, orders):
-        alone = brahms.run_workload(w, device=DEV, pass_order=o)
+        alone = brahms.run_workload(w, device=DEV, pass_order=o, merge_halves=merge)
         for a, b in zip(fs, alone):
             assert torch.equal(a, b), w.name

@@ -37,12 +37,13 @@ def test_tuner_takes_the_fastest_order_and_caches(fake_tuner, tmp_path):
     calls = fake_tuner({(0, 0): 1.0, (1, 0): 0.9, (0, 1): 0.95, (1, 1): 0.89})
     best = autotune.tune(32, 32, 32, 2, _params())
     # the graph is not 2 % faster than the best launch-by-launch order
-    assert best == {"pass_order": 1, "graph": 0}
+    assert best == {"pass_order": 1, "graph": 0, "merge_halves": 1}
     assert len(calls) == len(autotune.CANDIDATES)
+    assert all(c["merge_halves"] == 1 for c in calls)   # constant dk: merged half-steps
     with open(os.path.join(str(tmp_path), "schedules.json")) as fh:
         disk = json.load(fh)
     (key, entry), = disk.items()
-    assert key == "v2:gfx950:32x32x32:nf2" and entry["schedule"] == best
+    assert key == "v3:gfx950:32x32x32:nf2:m1" and entry["schedule"] == best
     autotune._memo.clear()
     assert autotune.tune(32, 32, 32, 2, _params()) == best     # from the disk cache
     assert len(calls) == len(autotune.CANDIDATES)
@@ -50,7 +51,22 @@ def test_tuner_takes_the_fastest_order_and_caches(fake_tuner, tmp_path):
 
 def test_tuner_takes_the_graph_when_clearly_faster(fake_tuner):
     fake_tuner({(0, 0): 1.0, (1, 0): 1.1, (0, 1): 0.5, (1, 1): 0.6})
-    assert autotune.tune(16, 16, 16, 3, _params(), refresh=True) == {"pass_order": 0, "graph": 1}
+    assert autotune.tune(16, 16, 16, 3, _params(), refresh=True) == {
+        "pass_order": 0, "graph": 1, "merge_halves": 1}
+
+
+def test_tuner_keeps_literal_half_steps_where_merging_is_refused(fake_tuner):
+    """A dk profile or a transverse map keeps the literal N/2 - L - N/2 (the
+    plan refuses merge_halves there), and so does merge_halves=False."""
+    import numpy as np
+    calls = fake_tuner({(1, 0): 0.5})
+    prof = brahms.Params(dz=0.01, fields=[brahms.FieldParams(kappa=1.0)] * 2, dk=np.ones(10))
+    assert autotune.tune(8, 8, 8, 2, prof)["merge_halves"] == 0
+    mapped = brahms.Params(dz=0.01, fields=[brahms.FieldParams(kappa=1.0)] * 2,
+                           dk_map=np.ones((8, 8)))
+    assert autotune.tune(8, 8, 8, 2, mapped)["merge_halves"] == 0
+    assert autotune.tune(8, 8, 8, 2, _params(), merge_halves=False)["merge_halves"] == 0
+    assert all(c["merge_halves"] == 0 for c in calls)
 
 
 def test_bench_refuses_more_than_one_gpu():
