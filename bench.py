@@ -27,6 +27,11 @@ if ROOT not in sys.path:
 
 METRIC = "grid-point·z-steps/s + % HBM peak; adjoint/forward time; batched vs plain"
 HBM_PEAK_GBS = 8000.0
+# MI355X FP32 vector peak (published, with packed FP32 math) and the peak of
+# the unpacked FP32 instructions these kernels are built with: 256 CUs x 4
+# SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+FP32_PEAK_TFLOPS = 157.3
+FP32_UNPACKED_TFLOPS = 78.6
 
 
 def parse():
@@ -45,6 +50,8 @@ def parse():
                     help="plan schedule: autotuned (default) or a fixed pass order")
     ap.add_argument("--literal-halves", action="store_true",
                     help="keep both RK4 half-steps of every step (no merging of adjacent halves)")
+    ap.add_argument("--no-fuse", action="store_true",
+                    help="with a fixed pass order: three passes per step (no fused step pairs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain 1 GiB device-to-device copy instead (reference for "
                          "achievable bandwidth and for scaling hardware byte counters)")
@@ -346,16 +353,33 @@ def kernel_digest() -> str:
     return h.hexdigest()
 
 
-def nl_of_pass(pass_order: int, merge_halves: int) -> dict:
+def nl_of_pass(pass_order: int, merge_halves: int, fuse_steps: int = 0) -> dict:
     """RK4 mode of each pass in the steady state of a run: with merged
-    half-steps the first pass of every step but the run's first is linear."""
+    half-steps the first pass of every step but the run's first is linear;
+    with fused step pairs the first and last axes alternate as the pass that
+    ends one step and begins the next ("fused")."""
     modes = dict(NL_OF_PASS[pass_order])
+    if merge_halves and fuse_steps:
+        return {k: ("none" if v == "none" else "fused") for k, v in modes.items()}
     if merge_halves:
         modes = {k: ("none" if v == "before" else v) for k, v in modes.items()}
     return modes
 
 
-def measured_traffic(workload: str, pass_name: str, pass_order: int, merge_halves: int = 0):
+def fused_pass_flops(nf: int, points: int, n_axis: int) -> float:
+    """Algorithmic FP32 flops of one fused pass: per grid point and field two
+    round trips along the axis (forward and inverse transform at the
+    conventional 5 N log2 N flops each, and the 6-flop propagator product)
+    and one RK4 step of the coupled equations (per field four stages of one
+    complex product of two fields, 6 flops, the product with the stage
+    coefficient, 6, the stage update, 2, and the weighted accumulation, 8)."""
+    import math
+    per_trip = 2 * 5 * math.log2(n_axis) + 6
+    return float(points) * nf * (2 * per_trip + 4 * (6 + 6 + 2 + 8))
+
+
+def measured_traffic(workload: str, pass_name: str, pass_order: int, merge_halves: int = 0,
+                     fuse_steps: int = 0):
     """HBM bytes per launch of one pass kernel from the hardware-counter
     summary profiles/hbm_traffic_<workload>.json (FETCH_SIZE and WRITE_SIZE
     per dispatch, each scaled by what the counter reads for a plain copy of
@@ -369,7 +393,7 @@ def measured_traffic(workload: str, pass_name: str, pass_order: int, merge_halve
         return None
     if rec.get("kernel_digest") != kernel_digest():
         return None
-    key = f"{pass_name}:{nl_of_pass(pass_order, merge_halves)[pass_name]}"
+    key = f"{pass_name}:{nl_of_pass(pass_order, merge_halves, fuse_steps)[pass_name]}"
     k = rec.get("kernels", {}).get(key)
     if k is None:
         return None
@@ -430,7 +454,8 @@ def main():
         from paper_2609_08384_amd import autotune
         schedule = autotune.apply(plan, dev, merge_halves=not args.literal_halves)
     else:
-        plan.set_schedule(int(args.pass_order), 0, 0 if args.literal_halves else 1)
+        merge = 0 if args.literal_halves else 1
+        plan.set_schedule(int(args.pass_order), 0, merge, merge and not args.no_fuse)
         schedule = plan.get_schedule()
 
     def reset():
@@ -472,17 +497,29 @@ def main():
     # once, 2 * 8 B per complex64 value
     bytes_per_launch = 2 * 8 * wl.nf * wl.points
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(wl.name, dom, int(schedule["pass_order"]),
-                                            int(schedule.get("merge_halves", 0))),
-                "kernel": dom, "kernel_rk4": nl_of_pass(int(schedule["pass_order"]),
-                                                        int(schedule.get("merge_halves", 0)))[dom],
-                "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": bytes_per_launch}
+    order, merge, fuse = (int(schedule["pass_order"]), int(schedule.get("merge_halves", 0)),
+                          int(schedule.get("fuse_steps", 0)))
+    modes = nl_of_pass(order, merge, fuse)
+    traffic = measured_traffic(wl.name, dom, order, merge, fuse)
+    if modes[dom] == "fused":
+        # two axis transforms and the RK4 step per value read and written:
+        # bound by FP32 vector issue, not by HBM
+        axis_len = {"x_pass": wl.nx, "y_pass": wl.ny, "t_pass": wl.nt}[dom]
+        flops = fused_pass_flops(wl.nf, wl.points, axis_len)
+        tflops = flops / (avg_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(tflops, 2), "peak": FP32_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
+                    "frac_of_unpacked_fp32_peak": round(tflops / FP32_UNPACKED_TFLOPS, 4),
+                    "hbm_GBps": round(achieved, 1), "algorithmic_flops_per_launch": flops}
+    else:
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+    roofline.update({"kernel": dom, "kernel_rk4": modes[dom], "avg_launch_ms": round(avg_ms, 5),
+                     "algorithmic_bytes_per_launch": bytes_per_launch})
     per_kernel = {k: {"avg_ms": round(v[0] / max(v[1], 1), 5), "launches": v[1],
                       "GBps": (round(bytes_per_launch / (v[0] / v[1] * 1e-3) / 1e9, 1)
                                if v[1] and k != "tables" else None)} for k, v in tim.items()}
-    step_bytes = 3 * bytes_per_launch
+    step_bytes = (2 if merge and fuse else 3) * bytes_per_launch
     plan.destroy()
 
     extras = {}

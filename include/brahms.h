@@ -136,10 +136,10 @@ brahms_status brahms_set_z(brahms_plan plan, double z);
 
 brahms_status brahms_plan_destroy(brahms_plan plan);
 
-/* Execution schedule of a plan (pass order and graph replay change only how
- * the method is computed; merge_halves changes the integrator of the
- * nonlinear part by O(h^5) per step; results of different schedules agree
- * to rounding).  The linear step is
+/* Execution schedule of a plan (pass order, graph replay and fused step
+ * pairs change only how the method is computed; merge_halves changes the
+ * integrator of the nonlinear part by O(h^5) per step; results of different
+ * schedules agree to rounding).  The linear step is
  * applied as three commuting one-axis operators (Sec. 3.1: the dispersion
  * and diffraction operators commute), each a pass over the fields; the first
  * pass of a z-step also performs the first Runge-Kutta half-step and the last
@@ -168,12 +168,23 @@ brahms_status brahms_plan_destroy(brahms_plan plan);
  *     transverse map (BRAHMS_E_UNSUPPORTED otherwise); calls run with literal
  *     half-steps while monitor records or snapshots are set; the adjoint
  *     always differentiates the literal half-steps.
+ *   fuse_steps 1 (needs merge_halves 1; three passes per step, so tau <= 256
+ *     and not nx = ny = 1): within one call, even steps (counted from the
+ *     call's first) take the axes in pass_order's order a, m, b and odd steps
+ *     in the order b, m, a.  The axis operators commute (Sec. 3.1), so this
+ *     is the same linear step; and each step's last transform, the merged RK4
+ *     step and the next step's first transform are along one axis and run
+ *     as one pass: two reads and writes of the fields per step instead of
+ *     three.  Calls run without it while merge_halves is suspended.
+ *     BRAHMS_E_INVALID_ARG without merge_halves, BRAHMS_E_UNSUPPORTED for
+ *     other step structures.
  * The autotuner in the Python package times the candidates per grid shape. */
 typedef struct {
   int pass_order;
   int graph;
   int merge_halves;
-  int reserved[5];
+  int fuse_steps;
+  int reserved[4];
 } brahms_schedule;
 
 brahms_status brahms_plan_set_schedule(brahms_plan plan, const brahms_schedule* sched);

@@ -11,7 +11,9 @@ Merged RK4 half-steps (schedule field merge_halves) are not a trade-off to
 measure: they take one RK4 update per step instead of two and change the
 result by O(dz^5) per step, far below FP32 rounding.  The tuner turns them on
 wherever the plan allows them (a constant dk and no transverse map) unless
-asked not to, and times the other fields with them.
+asked not to, and times the other fields with them.  Fused step pairs (two
+passes per step instead of three, same arithmetic) are a trade of HBM
+traffic for register pressure and are timed like the pass orders.
 """
 from __future__ import annotations
 
@@ -41,12 +43,18 @@ def _arch(device) -> str:
 
 
 def _key(arch: str, nx: int, ny: int, nt: int, nf: int, merge: int) -> str:
-    return f"v3:{arch}:{nx}x{ny}x{nt}:nf{nf}:m{merge}"
+    return f"v4:{arch}:{nx}x{ny}x{nt}:nf{nf}:m{merge}"
 
 
 def can_merge(params: brahms.Params) -> bool:
     """Whether a plan with these parameters accepts merge_halves = 1."""
     return params.dk is None and getattr(params, "dk_map", None) is None
+
+
+def can_fuse(nx: int, ny: int, nt: int) -> bool:
+    """Whether a plan of this shape takes three passes per step (and so
+    accepts fuse_steps = 1 with merged half-steps)."""
+    return nt <= 256 and not (nx == 1 and ny == 1)
 
 
 def _load() -> dict:
@@ -107,7 +115,8 @@ def tune(nx: int, ny: int, nt: int, nf: int, params: brahms.Params, device="cuda
         # time with the same linear coefficients but no coupling blow-up risk
         scratch = brahms.Params(dz=params.dz, fields=params.fields, dk_const=params.dk_const,
                                 dk=None, dx=params.dx, dy=params.dy, dt=params.dt)
-        cands = [dict(c, merge_halves=merge) for c in CANDIDATES]
+        fuses = (0, 1) if merge and can_fuse(nx, ny, nt) else (0,)
+        cands = [dict(c, merge_halves=merge, fuse_steps=f) for f in fuses for c in CANDIDATES]
         times = [(measure(nx, ny, nt, nf, scratch, c, device), c) for c in cands]
         best_ms, best = min(((t, c) for t, c in times if not c["graph"]), key=lambda tc: tc[0])
         # a graph pays off only where launches are a visible cost: take it

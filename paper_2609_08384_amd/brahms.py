@@ -42,7 +42,8 @@ class BrahmsError(RuntimeError):
 
 class ScheduleC(ctypes.Structure):
     _fields_ = [("pass_order", ctypes.c_int), ("graph", ctypes.c_int),
-                ("merge_halves", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
+                ("merge_halves", ctypes.c_int), ("fuse_steps", ctypes.c_int),
+                ("reserved", ctypes.c_int * 4)]
 
 
 class FieldParamsC(ctypes.Structure):
@@ -252,13 +253,16 @@ class Plan:
     def set_z(self, z: float):
         _check(self._lib.brahms_set_z(self._h, float(z)), "brahms_set_z")
 
-    def set_schedule(self, pass_order: int, graph: int = 0, merge_halves: int = 0):
-        """Pass order 0-3, graph replay of 64-step chunks, and merged RK4
-        half-steps within a call (constant dk, no transverse map)."""
+    def set_schedule(self, pass_order: int, graph: int = 0, merge_halves: int = 0,
+                     fuse_steps: int = 0):
+        """Pass order 0-3, graph replay of 64-step chunks, merged RK4
+        half-steps within a call (constant dk, no transverse map), and fused
+        step pairs (with merged half-steps: two passes per step)."""
         sc = ScheduleC()
         sc.pass_order = int(pass_order)
         sc.graph = int(graph)
         sc.merge_halves = int(merge_halves)
+        sc.fuse_steps = int(fuse_steps)
         _check(self._lib.brahms_plan_set_schedule(self._h, ctypes.byref(sc)),
                "brahms_plan_set_schedule")
 
@@ -266,7 +270,8 @@ class Plan:
         sc = ScheduleC()
         _check(self._lib.brahms_plan_get_schedule(self._h, ctypes.byref(sc)),
                "brahms_plan_get_schedule")
-        return {"pass_order": sc.pass_order, "graph": sc.graph, "merge_halves": sc.merge_halves}
+        return {"pass_order": sc.pass_order, "graph": sc.graph, "merge_halves": sc.merge_halves,
+                "fuse_steps": sc.fuse_steps}
 
     # --- adjoint (reverse-mode gradient of the z-loop) ---
     def adjoint_workspace_bytes(self, nsteps: int, checkpoint_every: int) -> int:
@@ -388,14 +393,14 @@ class Plan:
 def run_workload(wl, nsteps: Optional[int] = None, device: str = "cuda:0",
                  stream: Optional[torch.cuda.Stream] = None,
                  pass_order: Optional[int] = None,
-                 merge_halves: int = 0) -> List[torch.Tensor]:
+                 merge_halves: int = 0, fuse_steps: int = 0) -> List[torch.Tensor]:
     """Upload a seeded workload's entrance fields, propagate nsteps (default:
     all of them) and return the device fields."""
     nsteps = wl.nz if nsteps is None else nsteps
     fields = [torch.from_numpy(a).to(device) for a in wl.init]
     plan = Plan(wl.nx, wl.ny, wl.nt, wl.nf, params_from_workload(wl), stream=stream)
     if pass_order is not None or merge_halves:
-        plan.set_schedule(pass_order or 0, 0, merge_halves)
+        plan.set_schedule(pass_order or 0, 0, merge_halves, fuse_steps)
     plan.bind(fields)
     plan.step(nsteps)
     torch.cuda.synchronize()

@@ -25,6 +25,7 @@ using namespace brahms;
 using brahms::detail::fail;
 using brahms::detail::kAlign;
 using brahms::detail::kChunk;
+using brahms::detail::kTableRows;
 using brahms::detail::kDiagChunks;
 using brahms::detail::align_up;
 
@@ -81,6 +82,12 @@ using brahms::detail::tile_multiplier;
 
 template <int N1, int N2, int AX, int NF>
 void launch_nl_nf(int nl, bool full, dim3 grid, hipStream_t st, const PassArgs& a) {
+  if constexpr (!long_tau_kind(AX)) {
+    if (nl == (NL_AFTER | NL_FUSE)) {
+      launch_pass<N1, N2, AX, NF, NL_AFTER | NL_FUSE>(full, grid, st, a);
+      return;
+    }
+  }
   switch (nl) {
     case NL_BEFORE: launch_pass<N1, N2, AX, NF, NL_BEFORE>(full, grid, st, a); break;
     case NL_AFTER: launch_pass<N1, N2, AX, NF, NL_AFTER>(full, grid, st, a); break;
@@ -102,6 +109,7 @@ void launch_plain_nl_nf(int nl, bool full, dim3 grid, hipStream_t st, const Pass
   switch (nl) {
     case NL_BEFORE: launch_pass<N1, N2, AX, NF, NL_BEFORE>(full, grid, st, a); break;
     case NL_AFTER: launch_pass<N1, N2, AX, NF, NL_AFTER>(full, grid, st, a); break;
+    case NL_AFTER | NL_FUSE: launch_pass<N1, N2, AX, NF, NL_AFTER | NL_FUSE>(full, grid, st, a); break;
     default: launch_pass<N1, N2, AX, NF, NL_BOTH>(full, grid, st, a); break;
   }
 }
@@ -226,9 +234,9 @@ void layout(brahms_plan_s& p) {
   p.off_dk = off;
   off = align_up(off + sizeof(double) * (p.dk.size() + 1));
   p.off_prop = off;
-  off = align_up(off + sizeof(float2) * size_t(kChunk) * table_row_stride(p.nf, p.nx, p.ny, p.nt));
+  off = align_up(off + sizeof(float2) * size_t(kTableRows) * table_row_stride(p.nf, p.nx, p.ny, p.nt));
   p.off_nl = off;
-  off = align_up(off + sizeof(float2) * size_t(kChunk) * 2 * p.nf * kNlCoef);
+  off = align_up(off + sizeof(float2) * size_t(kTableRows) * 2 * p.nf * kNlCoef);
   p.off_flag = off;
   off = align_up(off + sizeof(int));
   p.off_diag = off;
@@ -356,6 +364,10 @@ bool merging(const brahms_plan_s& p) {
   return p.merge && p.dk.empty() && p.dk_map.empty() && p.mon_every == 0 && p.snap_steps.empty();
 }
 
+bool fusing(const brahms_plan_s& p) {
+  return p.fuse && merging(p) && !long_tau(p) && step_passes(p, false).n == 3;
+}
+
 brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count, int row0,
                              long long merge_last) {
   const int per_field = p.nx + p.ny + p.nt;
@@ -470,6 +482,40 @@ brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io, bool cont
   return BRAHMS_OK;
 }
 
+brahms_status launch_fused_step(brahms_plan_s& p, int row, bool first, bool last, bool odd) {
+  // axes a, m, b of the schedule; odd steps run them as b, m, a
+  const int a0 = pass_axis(p, 0), mid = pass_axis(p, 1), b0 = pass_axis(p, 2);
+  const int lead = odd ? b0 : a0, tail = odd ? a0 : b0;
+  auto in_place = [&](PassArgs& a) {
+    for (int j = 0; j < 3; ++j) {
+      a.f[j] = p.fields[j];
+      a.fo[j] = p.fields[j];
+    }
+    a.nl = nl_coefficients(p, row, 0);
+    a.nl2 = nl_coefficients(p, row, 1);
+  };
+  if (first) {
+    // the call's first step: its own first half-step, then its first axis
+    PassArgs a = pass_args(p, row, lead);
+    in_place(a);
+    if (brahms_status st = timed_dispatch(p, lead, NL_BEFORE, a)) return st;
+  }
+  {
+    PassArgs a = pass_args(p, row, mid);
+    in_place(a);
+    if (brahms_status st = timed_dispatch(p, mid, NL_NONE, a)) return st;
+  }
+  PassArgs a = pass_args(p, row, tail);
+  in_place(a);
+  if (last) return timed_dispatch(p, tail, NL_AFTER, a);   // its own second half-step
+  // the RK4 step of size dz from z_n + dz/2, then step n+1's first axis
+  const PassArgs next = pass_args(p, row + 1, tail);
+  a.tw2 = next.tw;
+  a.prop2 = next.prop;
+  a.consts2 = next.consts;
+  return timed_dispatch(p, tail, NL_AFTER | NL_FUSE, a);
+}
+
 brahms_status launch_linear_pass(brahms_plan_s& p, int row, int axis, float2* const* fields,
                                  bool conj) {
   if (axis != AX_Y) return fail(BRAHMS_E_INVALID_ARG, "linear-only passes run along y");
@@ -526,9 +572,17 @@ brahms_status build_chunk_graph(brahms_plan_s& p) {
   hipError_t e = hipStreamBeginCapture(p.capture_stream, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     const detail::StepIO io = plain_io(p);
-    const bool continued = detail::merging(p);
-    st = detail::refresh_tables(p, 0, kChunk);
-    for (int s = 0; s < kChunk && st == BRAHMS_OK; ++s) st = detail::launch_step(p, s, io, continued);
+    if (detail::fusing(p)) {
+      // an inner chunk of a call with fused step pairs (it starts on an
+      // even step of the call and does not hold the call's last step)
+      st = detail::refresh_tables(p, 0, kChunk + 1);
+      for (int s = 0; s < kChunk && st == BRAHMS_OK; ++s)
+        st = detail::launch_fused_step(p, s, false, false, (s & 1) != 0);
+    } else {
+      const bool continued = detail::merging(p);
+      st = detail::refresh_tables(p, 0, kChunk);
+      for (int s = 0; s < kChunk && st == BRAHMS_OK; ++s) st = detail::launch_step(p, s, io, continued);
+    }
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(p.capture_stream, &g);
     if (st == BRAHMS_OK && e == hipSuccess) {
@@ -557,7 +611,43 @@ brahms_status build_chunk_graph(brahms_plan_s& p) {
 // of size dz that also covers the next step's first half, and the last ends
 // on its own second half-step, so the fields after the call are those at a
 // step boundary.
+// Fused step pairs: the call's steps alternate their axis order (even steps
+// relative to the call's first take the schedule's order, odd ones its
+// reverse), so each step but the last ends with one pass that holds its last
+// transform, the merged RK4 step and the next step's first transform.  The
+// tables of a chunk hold one more row, the next step's.  Graph replays take
+// the inner chunks (from an even step, not holding the call's last step).
+brahms_status run_fused(brahms_plan_s& p, int nsteps) {
+  const long long merge_last = p.step + nsteps - 1;
+  int done = 0;
+  while (done < nsteps) {
+    const int count = std::min(kChunk, nsteps - done);
+    if (count == kChunk && graph_chunk_ok(p) && done > 0 && done + kChunk < nsteps) {
+      if (!p.chunk_exec)
+        if (brahms_status st = build_chunk_graph(p)) return st;
+      hipLaunchKernelGGL(set_step_index, dim3(1), dim3(1), 0, p.stream,
+                         reinterpret_cast<long long*>(p.ws + p.off_n0), p.step, merge_last);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipGraphLaunch(p.chunk_exec, p.stream));
+      p.table_n0 = p.step;
+      p.step += count;
+      done += count;
+      continue;
+    }
+    if (brahms_status st = detail::refresh_tables(p, p.step, count + 1, 0, merge_last)) return st;
+    for (int s = 0; s < count; ++s) {
+      const int g = done + s;
+      if (brahms_status st = detail::launch_fused_step(p, s, g == 0, g == nsteps - 1, (g & 1) != 0))
+        return st;
+    }
+    p.step += count;
+    done += count;
+  }
+  return BRAHMS_OK;
+}
+
 brahms_status run_steps(brahms_plan_s& p, int nsteps) {
+  if (detail::fusing(p)) return run_fused(p, nsteps);
   const detail::StepIO io = plain_io(p);
   const bool merge = detail::merging(p);
   const long long merge_last = merge ? p.step + nsteps - 1 : -1;
@@ -782,12 +872,19 @@ brahms_status brahms_plan_set_schedule(brahms_plan plan, const brahms_schedule* 
     return fail(BRAHMS_E_INVALID_ARG, "merge_halves must be 0 or 1");
   if (sched->merge_halves && (!plan->dk.empty() || !plan->dk_map.empty()))
     return fail(BRAHMS_E_UNSUPPORTED, "merge_halves needs a constant dk and no transverse map");
+  if (sched->fuse_steps != 0 && sched->fuse_steps != 1)
+    return fail(BRAHMS_E_INVALID_ARG, "fuse_steps must be 0 or 1");
+  if (sched->fuse_steps && !sched->merge_halves)
+    return fail(BRAHMS_E_INVALID_ARG, "fuse_steps needs merge_halves");
+  if (sched->fuse_steps && (detail::long_tau(*plan) || detail::step_passes(*plan, false).n != 3))
+    return fail(BRAHMS_E_UNSUPPORTED, "fuse_steps needs three passes per step (tau <= 256, nx or ny > 1)");
   if (plan->order != sched->pass_order || plan->use_graph != (sched->graph != 0) ||
-      plan->merge != (sched->merge_halves != 0))
+      plan->merge != (sched->merge_halves != 0) || plan->fuse != (sched->fuse_steps != 0))
     drop_chunk_graph(*plan);
   plan->order = sched->pass_order;
   plan->use_graph = sched->graph != 0;
   plan->merge = sched->merge_halves != 0;
+  plan->fuse = sched->fuse_steps != 0;
   // capture now rather than in the first call that replays it
   if (graph_chunk_ok(*plan) && !plan->chunk_exec) return build_chunk_graph(*plan);
   return BRAHMS_OK;
@@ -800,6 +897,7 @@ brahms_status brahms_plan_get_schedule(brahms_plan plan, brahms_schedule* sched)
   sched->pass_order = plan->order;
   sched->graph = plan->use_graph ? 1 : 0;
   sched->merge_halves = plan->merge ? 1 : 0;
+  sched->fuse_steps = plan->fuse ? 1 : 0;
   return BRAHMS_OK;
 }
 

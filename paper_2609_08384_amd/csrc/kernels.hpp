@@ -42,6 +42,11 @@ enum NlMode { NL_NONE = 0, NL_BEFORE = 1, NL_AFTER = 2,
 // Added to NL_BEFORE / NL_AFTER: the mismatch phase also has a transverse
 // part (a per-(x, y) table of exp(i m(x, y) Psi(z)) for each RK4 stage).
 constexpr int NL_MAP = 4;
+// Added to NL_AFTER (fused step pair): after the RK4 step the pass applies
+// the next z-step's transform along the same axis, with that step's tables
+// (tw2, prop2, consts2), so the last axis of step n and the first axis of
+// step n + 1 cost one read and one write of the fields.
+constexpr int NL_FUSE = 8;
 
 struct PassArgs {
   float2* f[3];          // fields read (complex64, [nt][ny][nx])
@@ -64,6 +69,9 @@ struct PassArgs {
   long long nz;          // batched launches: the instance is done once step >= nz
   const float2* map;     // NL_MAP: exp(i m(x,y) Psi) at this half-step's three
                          // stage positions, [3][ny][nx]
+  const float2* tw2;     // NL_FUSE: the next step's twiddles, propagators and
+  const float2* prop2;   // DFT constants along the same axis
+  const DftConsts* consts2;
 };
 
 // ---------------------------------------------------------------------------
@@ -274,11 +282,16 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
   constexpr bool MAP = (NL & NL_MAP) != 0;     // transverse mismatch map
   constexpr bool NT = (AX == AX_X) ? bool(BRAHMS_NT_X) : bool(BRAHMS_NT_YT);
   constexpr bool LONG = long_tau_kind(AX);
+  constexpr bool FUSE = (NL & NL_FUSE) != 0;   // and the next step's transform
   static_assert(!(MAP && (NLM == NL_BOTH || AX == AX_Y)),
                 "the transverse map runs only with a half-step per pass on x or tau");
+  static_assert(!FUSE || (NLM == NL_AFTER && !MAP && !LONG),
+                "a fused step pair ends one step and begins the next on one short axis");
   __shared__ float2 lds[G::LDS_ELEMS];
   __shared__ float2 s_tw[N];
   __shared__ float2 s_prop[LONG ? 1 : NF * N];
+  __shared__ float2 s_tw2[FUSE ? N : 1];
+  __shared__ float2 s_prop2[FUSE ? NF * N : 1];
   // long tau axis: the nt-point twiddles (a and b passes) or the tau
   // propagator (transform pass) of the whole axis
   __shared__ float2 s_long[LONG ? kMaxLongT : 1];
@@ -317,6 +330,11 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
       float2 pv = args.prop[(field0 + i / N) * args.field_stride + args.axis_off + i % N];
       if (args.conj) pv.y = -pv.y;
       s_prop[i] = pv;
+    }
+    if constexpr (FUSE) {
+      for (int i = tid; i < N; i += kBlock) s_tw2[i] = args.tw2[i];
+      for (int i = tid; i < NF * N; i += kBlock)
+        s_prop2[i] = args.prop2[(field0 + i / N) * args.field_stride + args.axis_off + i % N];
     }
   }
 
@@ -490,6 +508,17 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
       }
 #pragma unroll
       for (int j = 0; j < NF; ++j) v[j][e] = y[j];
+    }
+    if constexpr (FUSE) {
+      // the next step's first transform along this axis
+      const DftConsts K2 = *args.consts2;
+#pragma unroll
+      for (int j = 0; j < NF; ++j) {
+        line_fft<N1, N2, false>(v[j], t, lbuf, s_tw2, K2);
+#pragma unroll
+        for (int e = 0; e < N1; ++e) v[j][e] = cmul(v[j][e], s_prop2[j * N + t + N2 * e]);
+        line_fft<N1, N2, true>(v[j], t, lbuf, s_tw2, K2);
+      }
     }
     if (valid) {
 #pragma unroll

@@ -29,6 +29,10 @@ struct brahms_plan_s {
   // schedule field merge_halves: adjacent RK4 half-steps of one call run as
   // one RK4 step of size dz (constant dk, no map, no monitor or snapshots)
   bool merge = false;
+  // schedule field fuse_steps (with merged halves): steps alternate their
+  // axis order so that step n's last transform, the RK4 step and step n+1's
+  // first transform run as one pass
+  bool fuse = false;
   // hipGraph replay of whole 64-step chunks (schedule field `graph`)
   bool use_graph = false;
   hipGraph_t chunk_graph = nullptr;
@@ -68,7 +72,9 @@ struct brahms_plan_s {
 namespace brahms {
 namespace detail {
 
-constexpr int kChunk = 64;     // steps per table refill (rows in the workspace)
+constexpr int kChunk = 64;     // steps per table refill
+constexpr int kTableRows = kChunk + 1;  // table rows in the workspace: a chunk and
+                                        // the next step (fused step pairs)
 constexpr size_t kAlign = 256;
 constexpr int kDiagChunks = 64;  // chunks per (tau, field) slice in diagnostics
 
@@ -127,6 +133,8 @@ brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count, int row0
 // map, and not while monitor records or snapshots are due (every step they
 // look at must end on its own second half-step).
 bool merging(const brahms_plan_s& p);
+// Whether a call fuses step pairs: merging, and three passes per step.
+bool fusing(const brahms_plan_s& p);
 // The passes of one z-step in order: axis (AX_*) and RK4 mode (NL_*) of
 // each.  Three passes in general; passes along an axis of length 1 are left
 // out when they would multiply by exactly 1 (so the result is unchanged bit
@@ -143,6 +151,13 @@ StepPasses step_passes(const brahms_plan_s& p, bool batched);
 // One z-step with the tables of `row`; with continued = true the step's first
 // half-step is left out (it was merged into the previous step's second one).
 brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io, bool continued = false);
+// One step of a call with fused step pairs (tables of `row`, and of row + 1
+// unless `last`): the call's first step adds its first half-step and first
+// axis, every step runs its middle axis, then either its own second
+// half-step on its last axis (the call's last step) or the fused pass of its
+// last axis, the merged RK4 step and step n+1's first axis.  Steps with `odd`
+// set run the schedule's axes in reverse order.
+brahms_status launch_fused_step(brahms_plan_s& p, int row, bool first, bool last, bool odd);
 // The axis of the k-th pass of a step (k = 0, 1, 2) under the plan's order.
 int pass_axis(const brahms_plan_s& p, int k);
 // A linear-only pass (FFT . P . IFFT, or with conj(P)) along `axis`, in place.

@@ -190,6 +190,22 @@ def test_schedule_host_checks(lib):
     assert lib.brahms_plan_set_schedule(h, ctypes.byref(sc)) == brahms.BRAHMS_OK
     assert lib.brahms_plan_get_schedule(h, ctypes.byref(out)) == brahms.BRAHMS_OK
     assert out.merge_halves == 1
+    # fused step pairs need merged half-steps
+    sc.fuse_steps = 2
+    assert lib.brahms_plan_set_schedule(h, ctypes.byref(sc)) == brahms.BRAHMS_E_INVALID_ARG
+    sc.fuse_steps, sc.merge_halves = 1, 0
+    assert lib.brahms_plan_set_schedule(h, ctypes.byref(sc)) == brahms.BRAHMS_E_INVALID_ARG
+    sc.merge_halves = 1
+    assert lib.brahms_plan_set_schedule(h, ctypes.byref(sc)) == brahms.BRAHMS_OK
+    assert lib.brahms_plan_get_schedule(h, ctypes.byref(out)) == brahms.BRAHMS_OK
+    assert (out.merge_halves, out.fuse_steps) == (1, 1)
+    sc.fuse_steps = 0
+    lib.brahms_plan_destroy(h)
+    # a long tau axis takes five passes per step: no fused pairs
+    st, h = _create(lib, 8, 8, 1024, 2, c)
+    sc.fuse_steps = 1
+    assert lib.brahms_plan_set_schedule(h, ctypes.byref(sc)) == brahms.BRAHMS_E_UNSUPPORTED
+    sc.fuse_steps = 0
     lib.brahms_plan_destroy(h)
     # merged half-steps need Phi linear across step boundaries: no dk profile
     # and no transverse map

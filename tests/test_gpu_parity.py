@@ -30,8 +30,9 @@ def _wl(nx, ny, nt, nf, nz, dz, fields, dk_const=0.0, dk=None, init=None):
     return wl
 
 
-def _gpu(wl, nsteps=None, pass_order=None, merge=0):
-    out = brahms.run_workload(wl, nsteps=nsteps, device=DEV, pass_order=pass_order, merge_halves=merge)
+def _gpu(wl, nsteps=None, pass_order=None, merge=0, fuse=0):
+    out = brahms.run_workload(wl, nsteps=nsteps, device=DEV, pass_order=pass_order, merge_halves=merge,
+                              fuse_steps=fuse)
     return [f.cpu().numpy() for f in out]
 
 
@@ -217,30 +218,31 @@ def _check_golden(out, name, tol):
     return g
 
 
-SCHEDULES = [(0, 0), (1, 0), (2, 0), (3, 0), (0, 1), (1, 1), (2, 1), (3, 1)]
+# (pass order, merged half-steps, fused step pairs)
+SCHEDULES = [(o, m, f) for m, f in ((0, 0), (1, 0), (1, 1)) for o in range(4)]
 
 
-@pytest.mark.parametrize("order,merge", SCHEDULES)
-def test_sfg128_full_run_vs_oracle(order, merge):
+@pytest.mark.parametrize("order,merge,fuse", SCHEDULES)
+def test_sfg128_full_run_vs_oracle(order, merge, fuse):
     """SFG 128^3, 500 steps, pump depletion: <= 2e-5 per field."""
     wl = inputs.sfg128()
-    out = _gpu(wl, pass_order=order, merge=merge)
+    out = _gpu(wl, pass_order=order, merge=merge, fuse=fuse)
     g = _check_golden(out, "sfg128_500", 2e-5)
     e = [float((np.abs(a.astype(np.complex128)) ** 2).sum()) for a in out]
     assert np.allclose(e, g["energies"], rtol=4e-5)
 
 
-@pytest.mark.parametrize("order,merge", SCHEDULES)
-def test_opg256_first_steps_vs_oracle(order, merge):
+@pytest.mark.parametrize("order,merge,fuse", SCHEDULES)
+def test_opg256_first_steps_vs_oracle(order, merge, fuse):
     """OPG 256^3 (the benchmark workload), first 10 steps at full size, in the
     launch configurations the benchmark may time: <= 3e-5 per field."""
     wl = inputs.opg256()
-    out = _gpu(wl, 10, pass_order=order, merge=merge)
+    out = _gpu(wl, 10, pass_order=order, merge=merge, fuse=fuse)
     _check_golden(out, "opg256_10", 3e-5)
 
 
-@pytest.mark.parametrize("order,merge", SCHEDULES)
-def test_opg256_full_run_vs_oracle(order, merge):
+@pytest.mark.parametrize("order,merge,fuse", SCHEDULES)
+def test_opg256_full_run_vs_oracle(order, merge, fuse):
     """OPG 256^3, all 1000 steps (the benchmark workload end to end, in both
     launch configurations the benchmark may time): <= 3e-5 per field on the
     sampled values, power traces and fluence maps; energies and Manley-Rowe
@@ -248,7 +250,7 @@ def test_opg256_full_run_vs_oracle(order, merge):
     if not os.path.exists(f"{GOLDEN}/opg256_1000.npz"):
         pytest.skip("reference data not generated")
     wl = inputs.opg256()
-    out = _gpu(wl, pass_order=order, merge=merge)
+    out = _gpu(wl, pass_order=order, merge=merge, fuse=fuse)
     g = _check_golden(out, "opg256_1000", 3e-5)
     e = [float((np.abs(a.astype(np.complex128)) ** 2).sum()) for a in out]
     assert np.allclose(e, g["energies"], rtol=6e-5)
@@ -300,8 +302,9 @@ def test_graph_schedule_is_bitwise_eager(order):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("fuse", [0, 1])
 @pytest.mark.parametrize("order", [0, 1, 2, 3])
-def test_graph_schedule_with_merged_halves_is_bitwise_eager(order):
+def test_graph_schedule_with_merged_halves_is_bitwise_eager(order, fuse):
     """Merged half-steps: graph replays (which continue a call, so a call's
     first chunk runs eagerly) give the bits of launch-by-launch stepping over
     ragged calls, a resume, a monitor (whose calls keep literal half-steps)
@@ -318,7 +321,7 @@ def test_graph_schedule_with_merged_halves_is_bitwise_eager(order):
     def run(graph, merge, calls):
         f = [torch.from_numpy(a).to(DEV) for a in wl.init]
         plan = brahms.Plan(wl.nx, wl.ny, wl.nt, wl.nf, params)
-        plan.set_schedule(order, graph, merge)
+        plan.set_schedule(order, graph, merge, fuse if merge else 0)
         plan.bind(f)
         for c in calls:
             if c == "monitor":
@@ -353,3 +356,31 @@ def test_graph_schedule_with_merged_halves_is_bitwise_eager(order):
     mon = ["monitor", 70]
     for a, b in zip(run(0, 1, mon), run(0, 0, mon)):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
+@pytest.mark.parametrize("nf,shape", [(3, (32, 32, 32)), (3, (64, 16, 96)), (2, (96, 96, 4)),
+                                      (3, (16, 128, 64)), (2, (256, 2, 1)), (3, (8, 96, 1))])
+def test_fused_step_pairs_match_merged_oracle(nf, shape, order):
+    """Fused step pairs (alternating axis orders, step n's last transform,
+    the RK4 step and step n+1's first transform in one pass) compute the
+    merged loop: against the oracle's merged loop, for call lengths that
+    end on an even or odd step and that cross a 64-step table chunk."""
+    nx, ny, nt = shape
+    rng = np.random.default_rng(300 + nf + nt)
+    init = inputs.random_fields(rng, nf, nx, ny, nt, scale=0.7, smooth=max(1.0, min(nx, ny, nt) / 2.0))
+    for nz in (1, 2, 7, 66):
+        wl = _wl(nx, ny, nt, nf, nz, 0.01, _all_terms(nf, kappa=1.5), dk_const=2.3, init=init)
+        g, o = _gpu(wl, pass_order=order, merge=1, fuse=1), _oracle(wl, merge=1)
+        for j in range(nf):
+            assert rel_l2(g[j], o[j]) < 5e-6, (nz, j)
+
+
+def test_fused_step_pairs_refused_where_a_step_is_not_three_passes():
+    wl = inputs.Workload("pw", 1, 1, 64, 2, 4, 0.1, _all_terms(2, kappa=1.0))
+    plan = brahms.Plan(1, 1, 64, 2, brahms.params_from_workload(wl))
+    with pytest.raises(brahms.BrahmsError) as ei:
+        plan.set_schedule(0, 0, 1, 1)
+    assert ei.value.status == brahms.BRAHMS_E_UNSUPPORTED
+    plan.set_schedule(0, 0, 1, 0)
+    plan.destroy()

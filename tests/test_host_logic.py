@@ -22,7 +22,8 @@ def fake_tuner(monkeypatch, tmp_path):
     def install(times):
         def measure(nx, ny, nt, nf, params, schedule, device="cuda:0", steps=64, warmup=3):
             calls.append(dict(schedule))
-            return times.get((schedule["pass_order"], schedule["graph"]), 10.0)
+            return times.get((schedule["pass_order"], schedule["graph"], schedule["fuse_steps"]),
+                             times.get((schedule["pass_order"], schedule["graph"]), 10.0))
         monkeypatch.setattr(autotune, "measure", measure)
         return calls
     yield install
@@ -37,22 +38,35 @@ def test_tuner_takes_the_fastest_order_and_caches(fake_tuner, tmp_path):
     calls = fake_tuner({(0, 0): 1.0, (1, 0): 0.9, (0, 1): 0.95, (1, 1): 0.89})
     best = autotune.tune(32, 32, 32, 2, _params())
     # the graph is not 2 % faster than the best launch-by-launch order
-    assert best == {"pass_order": 1, "graph": 0, "merge_halves": 1}
-    assert len(calls) == len(autotune.CANDIDATES)
-    assert all(c["merge_halves"] == 1 for c in calls)   # constant dk: merged half-steps
+    assert best == {"pass_order": 1, "graph": 0, "merge_halves": 1, "fuse_steps": 0}
+    # constant dk: merged half-steps, with and without fused step pairs
+    assert len(calls) == 2 * len(autotune.CANDIDATES)
+    assert all(c["merge_halves"] == 1 for c in calls)
+    assert {c["fuse_steps"] for c in calls} == {0, 1}
     with open(os.path.join(str(tmp_path), "schedules.json")) as fh:
         disk = json.load(fh)
     (key, entry), = disk.items()
-    assert key == "v3:gfx950:32x32x32:nf2:m1" and entry["schedule"] == best
+    assert key == "v4:gfx950:32x32x32:nf2:m1" and entry["schedule"] == best
     autotune._memo.clear()
     assert autotune.tune(32, 32, 32, 2, _params()) == best     # from the disk cache
-    assert len(calls) == len(autotune.CANDIDATES)
+    assert len(calls) == 2 * len(autotune.CANDIDATES)
 
 
 def test_tuner_takes_the_graph_when_clearly_faster(fake_tuner):
     fake_tuner({(0, 0): 1.0, (1, 0): 1.1, (0, 1): 0.5, (1, 1): 0.6})
     assert autotune.tune(16, 16, 16, 3, _params(), refresh=True) == {
-        "pass_order": 0, "graph": 1, "merge_halves": 1}
+        "pass_order": 0, "graph": 1, "merge_halves": 1, "fuse_steps": 0}
+
+
+def test_tuner_takes_fused_step_pairs_when_faster(fake_tuner):
+    calls = fake_tuner({(0, 0, 0): 1.0, (2, 0, 1): 0.9})
+    assert autotune.tune(32, 32, 32, 3, _params(), refresh=True) == {
+        "pass_order": 2, "graph": 0, "merge_halves": 1, "fuse_steps": 1}
+    # a plane-wave grid (one pass per step) and a long tau axis never fuse
+    calls.clear()
+    autotune.tune(1, 1, 256, 2, _params(), refresh=True)
+    autotune.tune(8, 8, 1024, 2, _params(), refresh=True)
+    assert all(c["fuse_steps"] == 0 for c in calls)
 
 
 def test_tuner_keeps_literal_half_steps_where_merging_is_refused(fake_tuner):
@@ -66,7 +80,7 @@ def test_tuner_keeps_literal_half_steps_where_merging_is_refused(fake_tuner):
                            dk_map=np.ones((8, 8)))
     assert autotune.tune(8, 8, 8, 2, mapped)["merge_halves"] == 0
     assert autotune.tune(8, 8, 8, 2, _params(), merge_halves=False)["merge_halves"] == 0
-    assert all(c["merge_halves"] == 0 for c in calls)
+    assert all(c["merge_halves"] == 0 and c["fuse_steps"] == 0 for c in calls)
 
 
 def test_bench_refuses_more_than_one_gpu():
