@@ -287,6 +287,11 @@ brahms_status brahms_adjoint_backward(brahms_plan plan, void* const* grad, doubl
  *   one); 0 (default) keeps the literal N/2 - L - N/2.  Invalidates the
  *   binding.  Errors: BRAHMS_E_INVALID_ARG for another value,
  *   BRAHMS_E_UNSUPPORTED if a problem has a dk profile.
+ * brahms_batch_set_fuse_steps: 1 runs the launch groups whose steps take
+ *   three passes as fused step pairs (as the plan schedule field fuse_steps;
+ *   a problem's last step ends on its own second half-step inside the fused
+ *   launch).  Needs merged half-steps (BRAHMS_E_INVALID_ARG otherwise);
+ *   invalidates the binding.
  * brahms_batch_set_group_limits: per-problem launch-group sizes (n entries,
  *   0 = from the cache budget) that replace group_max; a group takes the
  *   limit of its first problem, so give problems of one shape the same one.
@@ -304,6 +309,7 @@ brahms_status brahms_batch_create(int n, const int* shapes, const brahms_params*
 brahms_status brahms_batch_set_schedule(brahms_batch batch, int group_max, const int* pass_order);
 brahms_status brahms_batch_set_group_limits(brahms_batch batch, const int* limits);
 brahms_status brahms_batch_set_merge_halves(brahms_batch batch, int merge_halves);
+brahms_status brahms_batch_set_fuse_steps(brahms_batch batch, int fuse_steps);
 brahms_status brahms_batch_workspace_size(brahms_batch batch, size_t* bytes);
 brahms_status brahms_batch_bind(brahms_batch batch, void* const* fields, void* workspace);
 brahms_status brahms_batch_run(brahms_batch batch);

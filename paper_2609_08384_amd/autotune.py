@@ -169,11 +169,13 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
       for a plain solve) and with one order for every problem (concurrent
       groups compete for the chip, so the best order alone need not be the
       best order together).
-    Merged half-steps are taken when every problem allows them.  Applies the
-    fastest choice to `batch`."""
+    Merged half-steps are taken when every problem allows them; fused step
+    pairs are timed against three passes per step on the fastest choice.
+    Applies the fastest choice to `batch`."""
     problems = batch.problems
     n = len(problems)
     merge = int(merge_halves and all(can_merge(prm) for (_, _, _, _, prm, _) in problems))
+    fuse = int(merge and any(can_fuse(nx, ny, nt) for (nx, ny, nt, _, _, _) in problems))
     tuned = [tune(nx, ny, nt, nf, prm, device, merge_halves=bool(merge))["pass_order"]
              for (nx, ny, nt, nf, prm, _) in problems]
     order_sets = {"per_shape": tuned, "all_0": [0] * n, "all_1": [1] * n}
@@ -190,6 +192,7 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
     for key, idx in shapes.items():
         sub = brahms.Batch([short[i] for i in idx])
         sub.set_merge_halves(merge)
+        sub.set_fuse_steps(fuse)
         sub.set_schedule(0, [tuned[i] for i in idx])
         times = []
         for lim in LIMIT_CANDIDATES:
@@ -203,6 +206,7 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
     # the whole batch
     probe = brahms.Batch(short)
     probe.set_merge_halves(merge)
+    probe.set_fuse_steps(fuse)
     candidates = []
     probe.set_schedule(0, tuned)
     probe.set_group_limits(limits)
@@ -212,10 +216,24 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
         for name, orders in order_sets.items():
             probe.set_schedule(gm, orders)
             candidates.append((_probe_time(probe, fields, device), f"group_max={gm}", gm, name))
-    probe.destroy()
     best = min(candidates, key=lambda c: c[0])
     _, label, gm, oname = best
+    if fuse:
+        # the same choice with three passes per step
+        probe.set_fuse_steps(0)
+        if gm is None:
+            probe.set_schedule(0, order_sets[oname])
+            probe.set_group_limits(limits)
+        else:
+            probe.set_group_limits(None)
+            probe.set_schedule(gm, order_sets[oname])
+        t3 = _probe_time(probe, fields, device)
+        candidates.append((t3, label + "/three_passes", gm, oname))
+        if t3 < best[0]:
+            fuse = 0
+    probe.destroy()
     batch.set_merge_halves(merge)
+    batch.set_fuse_steps(fuse)
     if gm is None:
         batch.set_schedule(0, order_sets[oname])
         batch.set_group_limits(limits)
@@ -223,5 +241,5 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
         batch.set_group_limits(None)
         batch.set_schedule(gm, order_sets[oname])
     return {"choice": label, "group_max": gm, "group_limits": limits if gm is None else None,
-            "pass_orders": order_sets[oname], "orders": oname, "merge_halves": merge,
+            "pass_orders": order_sets[oname], "orders": oname, "merge_halves": merge, "fuse_steps": fuse,
             "probe_ms": {f"{c[1]}/{c[3]}": c[0] for c in candidates}, "shape_probe_ms": shape_ms}

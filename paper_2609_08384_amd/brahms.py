@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "brahms_batch_set_schedule": [vp, i, ctypes.POINTER(i)],
         "brahms_batch_set_group_limits": [vp, ctypes.POINTER(i)],
         "brahms_batch_set_merge_halves": [vp, i],
+        "brahms_batch_set_fuse_steps": [vp, i],
         "brahms_batch_workspace_size": [vp, ctypes.POINTER(ctypes.c_size_t)],
         "brahms_batch_bind": [vp, ctypes.POINTER(vp), vp],
         "brahms_batch_run": [vp],
@@ -452,6 +453,14 @@ class Batch:
         """1: merged RK4 half-steps for every problem (constant dk only)."""
         _check(self._lib.brahms_batch_set_merge_halves(self._h, int(merge_halves)),
                "brahms_batch_set_merge_halves")
+        if self.fields is not None:
+            self.bind(self.fields)
+
+    def set_fuse_steps(self, fuse_steps: int):
+        """1: fused step pairs for the launch groups of three-pass steps
+        (needs merged half-steps)."""
+        _check(self._lib.brahms_batch_set_fuse_steps(self._h, int(fuse_steps)),
+               "brahms_batch_set_fuse_steps")
         if self.fields is not None:
             self.bind(self.fields)
 

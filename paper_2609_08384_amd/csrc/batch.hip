@@ -32,6 +32,7 @@ using namespace brahms;
 using brahms::detail::align_up;
 using brahms::detail::fail;
 using brahms::detail::kChunk;
+using brahms::detail::kTableRows;
 
 struct brahms_batch_s {
   int n = 0;
@@ -47,6 +48,7 @@ struct brahms_batch_s {
   int group_max = 0;                   // 0: choose from the cache budget
   std::vector<int> group_limit;        // per problem, overrides group_max (empty: none)
   bool merge = false;                  // merged RK4 half-steps (constant dk only)
+  bool fuse = false;                   // fused step pairs (groups of three-pass steps)
   // launch groups and descriptor placement (rebuilt when the schedule changes)
   struct Group {
     std::vector<int> members;
@@ -105,6 +107,16 @@ void make_groups(brahms_batch_s& b) {
   }
 }
 
+// Whether a group's steps run as fused step pairs: even steps take the
+// axes a, m, b of their passes, odd steps b, m, a, and each step's last
+// transform, the merged RK4 step and the next step's first transform are one
+// launch (which ends a member's last step without the next transform).
+bool group_fused(const brahms_batch_s& b, const brahms_batch_s::Group& g) {
+  const brahms_plan_s& p0 = *b.plans[g.members[0]];
+  return b.merge && b.fuse && !brahms::detail::long_tau(p0) &&
+         brahms::detail::step_passes(p0, true).n == 3;
+}
+
 size_t descriptor_bytes(brahms_batch_s& b) {
   size_t off = 0;
   for (auto& g : b.groups) {
@@ -136,6 +148,12 @@ void launch_batched(bool full, dim3 grid, hipStream_t st, const PassArgs* d, lon
 template <int N1, int N2, int AX, int NF>
 void launch_batched_nl_nf(int nl, bool full, dim3 grid, hipStream_t st, const PassArgs* d,
                           long long step) {
+  if constexpr (!long_tau_kind(AX)) {
+    if (nl == (NL_AFTER | NL_FUSE)) {
+      launch_batched<N1, N2, AX, NF, NL_AFTER | NL_FUSE>(full, grid, st, d, step, NF);
+      return;
+    }
+  }
   switch (nl) {
     case NL_BEFORE: launch_batched<N1, N2, AX, NF, NL_BEFORE>(full, grid, st, d, step, NF); break;
     case NL_AFTER: launch_batched<N1, N2, AX, NF, NL_AFTER>(full, grid, st, d, step, NF); break;
@@ -259,10 +277,13 @@ brahms_status upload_descriptors(brahms_batch_s& b) {
       const float2* rows = reinterpret_cast<const float2*>(p.ws + p.off_prop);
       const float2* nls = reinterpret_cast<const float2*>(p.ws + p.off_nl);
       const brahms::detail::StepPasses sp = brahms::detail::step_passes(p, true);
+      const bool fused = group_fused(b, g);
       for (int pass = 0; pass < sp.n; ++pass) {
-        const int ax = sp.ax[pass];
-        const int len = ax == AX_X ? p.nx : (ax == AX_Y ? p.ny : p.nt);
         for (int s = 0; s < kChunk; ++s) {
+          // fused step pairs: odd steps swap the first and last axes
+          int ax = sp.ax[pass];
+          if (fused && (s & 1) && pass != 1) ax = sp.ax[2 - pass];
+          const int len = ax == AX_X ? p.nx : (ax == AX_Y ? p.ny : p.nt);
           PassArgs a{};
           const float2* r = rows + size_t(s) * row_stride;
           a.axis_off = (ax == AX_X) ? 0 : (ax == AX_Y ? p.nx : p.nx + p.ny);
@@ -286,6 +307,13 @@ brahms_status upload_descriptors(brahms_batch_s& b) {
             a.tile_mul = brahms::detail::tile_multiplier(a.tiles);
           }
           a.nz = b.nsteps[g.members[k]];  // compared with the absolute step
+          if (fused && pass == 2) {
+            // the next step's tables along the same axis (row s + 1)
+            const float2* r2 = r + row_stride;
+            a.tw2 = r2 + p.nf * per_field + a.axis_off;
+            a.prop2 = r2;
+            a.consts2 = reinterpret_cast<const DftConsts*>(r2 + (p.nf + 1) * per_field);
+          }
           std::memcpy(desc.data() + g.desc_off + ((size_t(pass) * kChunk + s) * m + k) * sizeof(PassArgs),
                       &a, sizeof(PassArgs));
         }
@@ -301,6 +329,7 @@ brahms_status upload_descriptors(brahms_batch_s& b) {
         ta.n0 = (long long)c * kChunk;
         ta.merge_last = b.merge ? (long long)b.nsteps[g.members[k]] - 1 : -1;
         ta.count = std::max(0, std::min(kChunk, b.nsteps[g.members[k]] - c * kChunk));
+        if (group_fused(b, g) && ta.count > 0) ta.count += 1;   // the next step's row
         ta.nx = p.nx; ta.ny = p.ny; ta.nt = p.nt; ta.nf = p.nf;
         ta.dz = p.dz; ta.dx = p.dx; ta.dy = p.dy; ta.dt = p.dt; ta.dk_const = p.dk_const;
         for (int j = 0; j < p.nf; ++j) {
@@ -328,8 +357,9 @@ brahms_status enqueue_group(brahms_batch_s& b, const brahms_batch_s::Group& g, h
     const int per_field = p0.nx + p0.ny + p0.nt;
     const unsigned m = unsigned(g.members.size());
     const int chunks = (g.max_steps + kChunk - 1) / kChunk;
+    const bool fused = group_fused(b, g);
     for (int c = 0; c < chunks; ++c) {
-      const long total = long(kChunk) * ((g.nf + 1) * per_field + 1) + long(kChunk) * 2 * g.nf;
+      const long total = long(kTableRows) * ((g.nf + 1) * per_field + 1) + long(kTableRows) * 2 * g.nf;
       const TableArgs* targs =
           reinterpret_cast<const TableArgs*>(b.ws + b.off_targs + g.targs_off) + size_t(c) * m;
       hipLaunchKernelGGL(step_tables_batched, dim3(unsigned((total + 255) / 256), m), dim3(256), 0,
@@ -340,8 +370,13 @@ brahms_status enqueue_group(brahms_batch_s& b, const brahms_batch_s::Group& g, h
       for (int s = 0; s < cnt; ++s) {
         const long long step = (long long)c * kChunk + s;
         for (int pass = 0; pass < sp.n; ++pass) {
-          const int ax = sp.ax[pass];
-          const int nl = b.merge && step > 0 && pass == 0 ? (sp.nl[pass] & ~NL_BEFORE) : sp.nl[pass];
+          int ax = sp.ax[pass];
+          int nl = b.merge && step > 0 && pass == 0 ? (sp.nl[pass] & ~NL_BEFORE) : sp.nl[pass];
+          if (fused) {
+            if (pass == 0 && step > 0) continue;   // done by the previous fused pass
+            if (s & 1) ax = sp.ax[2 - pass];
+            if (pass == 2) nl = NL_AFTER | NL_FUSE;
+          }
           const PassArgs* d = reinterpret_cast<const PassArgs*>(b.ws + b.off_desc + g.desc_off) +
                               (size_t(pass) * kChunk + s) * m;
           if (long_tau_kind(ax)) dispatch_group_long(ax, nl, g, st, d, step);
@@ -480,6 +515,17 @@ brahms_status brahms_batch_set_merge_halves(brahms_batch b, int merge_halves) {
     for (brahms_plan p : b->plans)
       if (!p->dk.empty()) return fail(BRAHMS_E_UNSUPPORTED, "merge_halves needs a constant dk");
   b->merge = merge_halves != 0;
+  drop_graph(*b);
+  b->bound = false;
+  layout_batch(*b);
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_batch_set_fuse_steps(brahms_batch b, int fuse_steps) {
+  if (brahms_status st = check_batch(b)) return st;
+  if (fuse_steps != 0 && fuse_steps != 1) return fail(BRAHMS_E_INVALID_ARG, "fuse_steps must be 0 or 1");
+  if (fuse_steps && !b->merge) return fail(BRAHMS_E_INVALID_ARG, "fuse_steps needs merge_halves");
+  b->fuse = fuse_steps != 0;
   drop_graph(*b);
   b->bound = false;
   layout_batch(*b);

@@ -211,8 +211,14 @@ __device__ inline void line_fft(float2 (&v)[N1], int t, float2* lbuf, const floa
 #ifndef BRAHMS_NT_YT
 #define BRAHMS_NT_YT 0
 #endif
+// Blocks of kBlock threads per CU the pass kernels are compiled for: 3 is
+// 3 waves per SIMD, a budget of 168 VGPRs.  The three-field passes that
+// carry an RK4 step need 162-170; at 170 the allocation (granules of 8 out
+// of 512) rounds up to 176 and leaves room for 2 waves only, which cost the
+// fused step-pair pass ~15 % of its speed.  Kernels whose LDS already limits
+// them to fewer blocks keep their register count.
 #ifndef BRAHMS_MIN_BLOCKS
-#define BRAHMS_MIN_BLOCKS 1
+#define BRAHMS_MIN_BLOCKS 3
 #endif
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
@@ -273,9 +279,12 @@ __device__ __forceinline__ void map_factors(const float2* map, unsigned plane, u
 // FULL: every line of every block exists (no bounds masks).
 // ---------------------------------------------------------------------------
 // bx: tile index along the launch's x dimension; field0: first field
-// handled (y pass: the block's field).
+// handled (y pass: the block's field); next: a fused pass also applies the
+// next step's transform (false: the problem's last step, which ends on its
+// own second half-step).
 template <int N1, int N2, int AX, int NF, int NL, bool FULL>
-__device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx, int field0) {
+__device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx, int field0,
+                                               bool next = true) {
   using G = LineGeom<N1, N2>;
   constexpr int N = G::N;
   constexpr int NLM = NL & 3;                  // where the RK4 half-step goes
@@ -509,7 +518,7 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
 #pragma unroll
       for (int j = 0; j < NF; ++j) v[j][e] = y[j];
     }
-    if constexpr (FUSE) {
+    if constexpr (FUSE) if (next) {
       // the next step's first transform along this axis
       const DftConsts K2 = *args.consts2;
 #pragma unroll
@@ -550,7 +559,9 @@ __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass_batched(
   const unsigned inst = per_field ? blockIdx.z / unsigned(nf) : blockIdx.y;
   const PassArgs& a = descs[inst];
   if (step >= a.nz) return;
-  axis_pass_body<N1, N2, AX, NF, NL, FULL>(a, blockIdx.x, per_field ? int(blockIdx.z % unsigned(nf)) : 0);
+  // a fused pass ends the problem's last step without the next transform
+  axis_pass_body<N1, N2, AX, NF, NL, FULL>(a, blockIdx.x, per_field ? int(blockIdx.z % unsigned(nf)) : 0,
+                                           step + 1 < a.nz);
 }
 
 // ---------------------------------------------------------------------------

@@ -140,13 +140,15 @@ def test_whole_sweep_matches_oracle_and_single_runs():
             assert rel_l2(flat[g[key + f"f{j}_top_idx"]], g[key + f"f{j}_top"]) < 3e-5, (i, j)
             p = (np.abs(f.cpu().numpy().astype(np.complex128)) ** 2).sum(axis=(1, 2))
             assert rel_l2(p, g[key + f"f{j}_power"]) < 4e-5, (i, j)
-        alone = brahms.run_workload(w, device=DEV, pass_order=o, merge_halves=tuned["merge_halves"])
+        alone = brahms.run_workload(w, device=DEV, pass_order=o, merge_halves=tuned["merge_halves"],
+                                    fuse_steps=tuned["fuse_steps"])
         for a, b in zip(fs, alone):
             assert torch.equal(a, b), i
 
 
+@pytest.mark.parametrize("fuse", [0, 1])
 @pytest.mark.parametrize("group_max", [0, 1])
-def test_merged_batch_equals_plain_runs_and_oracle(group_max):
+def test_merged_batch_equals_plain_runs_and_oracle(group_max, fuse):
     """Merged half-steps in a batch (constant dk): each problem, with its own
     last step, bitwise equal to the same problem run alone with merged
     half-steps, and within the oracle tolerance; a batch with a dk profile
@@ -159,13 +161,14 @@ def test_merged_batch_equals_plain_runs_and_oracle(group_max):
     batch = brahms.Batch(probs)
     batch.set_schedule(group_max, orders)
     batch.set_merge_halves(1)
+    batch.set_fuse_steps(fuse)
     fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
     batch.bind(fields)
     batch.run()
     torch.cuda.synchronize()
     batch.destroy()
     for w, fs, o in zip(wls, fields, orders):
-        alone = brahms.run_workload(w, device=DEV, pass_order=o, merge_halves=1)
+        alone = brahms.run_workload(w, device=DEV, pass_order=o, merge_halves=1, fuse_steps=fuse)
         for a, b in zip(fs, alone):
             assert torch.equal(a, b), (w.nx, w.ny, w.nt, w.nz)
     for w, fs in list(zip(wls, fields))[:3]:
@@ -176,6 +179,9 @@ def test_merged_batch_equals_plain_runs_and_oracle(group_max):
     with pytest.raises(brahms.BrahmsError) as ei:
         b2.set_merge_halves(1)
     assert ei.value.status == brahms.BRAHMS_E_UNSUPPORTED
+    with pytest.raises(brahms.BrahmsError) as ei:
+        b2.set_fuse_steps(1)                 # needs merged half-steps
+    assert ei.value.status == brahms.BRAHMS_E_INVALID_ARG
     b2.destroy()
 
 

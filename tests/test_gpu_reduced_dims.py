@@ -19,11 +19,12 @@ DEV = "cuda:0"
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def _batch_run(wls, group_max=0, orders=None, merge=0):
+def _batch_run(wls, group_max=0, orders=None, merge=0, fuse=0):
     probs = [(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls]
     batch = brahms.Batch(probs)
     batch.set_schedule(group_max, orders)
     batch.set_merge_halves(merge)
+    batch.set_fuse_steps(fuse)
     fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
     batch.bind(fields)
     batch.run()
@@ -87,16 +88,24 @@ def test_plane_wave_pulses_match_oracle(merge):
     assert max(conv) > 0.5
 
 
-@pytest.mark.parametrize("merge", [0, 1])
+@pytest.mark.parametrize("merge,fuse", [(0, 0), (1, 0), (1, 1)])
 @pytest.mark.parametrize("group_max", [0, 1])
-def test_reduced_dims_batched_equal_single_runs(group_max, merge):
+def test_reduced_dims_batched_equal_single_runs(group_max, merge, fuse):
+    """CW and plane-wave problems (steps of two or one pass, never fused)
+    with a three-pass problem in one batch, each bitwise equal to the same
+    problem run alone."""
     wls = [inputs.bk_cw_instance(2.0, -4.0, n=64, nz=30), inputs.bk_cw_instance(3.0, -3.0, n=64, nz=17)]
     wls += inputs.plane_wave_pulse_sweep(count=3)
     for w in wls[2:]:
         w.nz = min(w.nz, 40)
+    wls.append(inputs.bk_cw_instance(3.0, -3.0, n=32, nz=21))
+    wls[-1].nt = 8
+    wls[-1].init = inputs.random_fields(np.random.default_rng(5), 2, 32, 32, 8, scale=0.5, smooth=4.0)
     orders = [k % 4 for k in range(len(wls))]
-    out = _batch_run(wls, group_max, orders, merge)
+    out = _batch_run(wls, group_max, orders, merge, fuse)
     for w, fs, o in zip(wls, out, orders):
-        alone = brahms.run_workload(w, device=DEV, pass_order=o, merge_halves=merge)
+        three = w.nt > 1 and not (w.nx == 1 and w.ny == 1)
+        alone = brahms.run_workload(w, device=DEV, pass_order=o, merge_halves=merge,
+                                    fuse_steps=fuse if three else 0)
         for a, b in zip(fs, alone):
             assert torch.equal(a, b), w.name
