@@ -519,22 +519,37 @@ def main():
     per_kernel = {k: {"avg_ms": round(v[0] / max(v[1], 1), 5), "launches": v[1],
                       "GBps": (round(bytes_per_launch / (v[0] / v[1] * 1e-3) / 1e9, 1)
                                if v[1] and k != "tables" else None)} for k, v in tim.items()}
+    for k, rec in per_kernel.items():
+        if k in modes:
+            rec["rk4"] = modes[k]
+            if modes[k] == "fused" and rec["launches"]:
+                n_axis = {"x_pass": wl.nx, "y_pass": wl.ny, "t_pass": wl.nt}[k]
+                tf = fused_pass_flops(wl.nf, wl.points, n_axis) / (rec["avg_ms"] * 1e-3) / 1e12
+                rec.update({"bound": "alu", "TFLOPs": round(tf, 2), "frac": round(tf / FP32_PEAK_TFLOPS, 4),
+                            "frac_of_unpacked_fp32_peak": round(tf / FP32_UNPACKED_TFLOPS, 4)})
+            elif rec["GBps"]:
+                rec.update({"bound": "hbm", "frac": round(rec["GBps"] / HBM_PEAK_GBS, 4)})
     step_bytes = (2 if merge and fuse else 3) * bytes_per_launch
     plan.destroy()
 
+    def progress(msg):
+        print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+    progress(f"{wl.name}: {value:.4g} grid-point z-steps/s, {wall / steps * 1e3:.4f} ms per step")
     extras = {}
     if not args.no_extras:
-        extras["adjoint"] = adjoint_ratio(dev)
-        extras["batch"] = batch_ratio(dev)
-        extras["reduced_dims"] = reduced_dims(dev)
-        extras["diagnostics"] = diagnostics_cost(dev, wl)
-        extras["dk_map"] = dk_map_cost(dev)
-        extras["paper_grids"] = paper_grids(dev)
+        for name, fn in (("adjoint", lambda: adjoint_ratio(dev)), ("batch", lambda: batch_ratio(dev)),
+                         ("reduced_dims", lambda: reduced_dims(dev)),
+                         ("diagnostics", lambda: diagnostics_cost(dev, wl)),
+                         ("dk_map", lambda: dk_map_cost(dev)), ("paper_grids", lambda: paper_grids(dev))):
+            extras[name] = fn()
+            progress(f"extra {name} done")
 
     cpu = None
     if not args.no_cpu_baseline:
         del fields, init
         torch.cuda.empty_cache()
+        progress(f"oracle on {args.cpu_steps} steps of the CPU sample")
         cpu = cpu_baseline(wl, args.cpu_steps)
 
     out = {
