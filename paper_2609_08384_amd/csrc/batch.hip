@@ -585,9 +585,20 @@ brahms_status brahms_batch_run(brahms_batch b) {
       if (graph) (void)hipGraphDestroy(graph);
       return st;
     }
-    HIP_TRY(e);
+    if (e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(BRAHMS_E_DEVICE, std::string("batch graph capture: ") + hipGetErrorString(e));
+    }
+    // keep the handles only once both exist, so that a failed instantiation
+    // leaves nothing for drop_graph to release twice
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return fail(BRAHMS_E_DEVICE, std::string("batch graph instantiation: ") + hipGetErrorString(ei));
+    }
     b->graph = graph;
-    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->exec = exec;
   }
   HIP_TRY(hipGraphLaunch(b->exec, b->stream));
   HIP_TRY(hipEventRecord(b->ev_out, b->stream));
@@ -607,6 +618,8 @@ brahms_status brahms_batch_groups(brahms_batch b, int* ngroups, int* members) {
 
 brahms_status brahms_batch_destroy(brahms_batch b) {
   if (b == nullptr) return fail(BRAHMS_E_INVALID_ARG, "batch is NULL");
+  // no launch of the graph may still run when it and the streams go
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
   drop_graph(*b);
   for (brahms_plan p : b->plans) brahms_plan_destroy(p);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);

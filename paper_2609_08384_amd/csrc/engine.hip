@@ -587,7 +587,9 @@ brahms_status build_chunk_graph(brahms_plan_s& p) {
     e = hipStreamEndCapture(p.capture_stream, &g);
     if (st == BRAHMS_OK && e == hipSuccess) {
       p.chunk_graph = g;
-      e = hipGraphInstantiate(&p.chunk_exec, g, nullptr, nullptr, 0);
+      hipGraphExec_t exec = nullptr;
+      e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+      if (e == hipSuccess) p.chunk_exec = exec;   // drop_chunk_graph releases only what exists
     } else if (g) {
       (void)hipGraphDestroy(g);
     }
