@@ -149,12 +149,12 @@ def test_dk_profile_matches_oracle():
         assert rel_l2(g[j], o[j]) < 5e-6
 
 
-@pytest.mark.parametrize("merge", [0, 1])
+@pytest.mark.parametrize("merge,fuse", [(0, 0), (1, 0), (1, 1)])
 @pytest.mark.parametrize("order", [0, 1, 2, 3])
-def test_shg32_full_run(order, merge):
+def test_shg32_full_run(order, merge, fuse):
     """SHG 32^3, 100 steps (the small benchmark workload): <= 1e-5 per field."""
     wl = inputs.shg32()
-    g, o = _gpu(wl, pass_order=order, merge=merge), _oracle(wl, merge=merge)
+    g, o = _gpu(wl, pass_order=order, merge=merge, fuse=fuse), _oracle(wl, merge=merge)
     for j in range(2):
         assert rel_l2(g[j], o[j]) < 1e-5, j
 
