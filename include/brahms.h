@@ -168,10 +168,11 @@ brahms_status brahms_plan_destroy(brahms_plan plan);
  *     transverse map (BRAHMS_E_UNSUPPORTED otherwise); calls run with literal
  *     half-steps while monitor records or snapshots are set; the adjoint
  *     always differentiates the literal half-steps.
- *   fuse_steps 1 (needs merge_halves 1; three passes per step, so tau <= 256
- *     and not nx = ny = 1): within one call, even steps (counted from the
- *     call's first) take the axes in pass_order's order a, m, b and odd steps
- *     in the order b, m, a.  The axis operators commute (Sec. 3.1), so this
+ *   fuse_steps 1 (needs merge_halves 1; not for nx = ny = 1 with tau <= 256,
+ *     whose steps are one pass): within one call, even steps (counted from
+ *     the call's first) take the axes in pass_order's order a, m, b and odd
+ *     steps in the order b, m, a (a long tau axis is m, its three passes in
+ *     the middle; x and y are a and b, y first for odd pass orders).  The axis operators commute (Sec. 3.1), so this
  *     is the same linear step; and each step's last transform, the merged RK4
  *     step and the next step's first transform are along one axis and run
  *     as one pass: two reads and writes of the fields per step instead of

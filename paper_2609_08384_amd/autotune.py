@@ -52,9 +52,10 @@ def can_merge(params: brahms.Params) -> bool:
 
 
 def can_fuse(nx: int, ny: int, nt: int) -> bool:
-    """Whether a plan of this shape takes three passes per step (and so
-    accepts fuse_steps = 1 with merged half-steps)."""
-    return nt <= 256 and not (nx == 1 and ny == 1)
+    """Whether a plan of this shape has x and y passes at the ends of a step
+    (and so accepts fuse_steps = 1 with merged half-steps): every shape but
+    plane waves with a single tau pass."""
+    return nt > 256 or not (nx == 1 and ny == 1)
 
 
 def _load() -> dict:

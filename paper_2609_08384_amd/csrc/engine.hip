@@ -186,10 +186,12 @@ hipError_t launch_long(int nl, int nf, const brahms_plan_s& p, PassArgs a) {
   a.tiles = 1;
   const long lines = long(p.nx) * p.ny * (p.nt / G::N);
   const bool full = lines % G::LPB == 0;
-  if constexpr (AX == AX_TAI) {
+  if (AX == AX_TAI && nl != NL_NONE) {
     const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
     launch_nl<N1, N2, AX_TAI>(nf, nl, full, grid, p.stream, a);
   } else {
+    // linear passes (the inverse b pass too, when fused step pairs carry
+    // the RK4 step on x and y): one field per block
     const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(nf));
     launch_pass<N1, N2, AX, 1, NL_NONE>(full, grid, p.stream, a);
   }
@@ -365,7 +367,7 @@ bool merging(const brahms_plan_s& p) {
 }
 
 bool fusing(const brahms_plan_s& p) {
-  return p.fuse && merging(p) && !long_tau(p) && step_passes(p, false).n == 3;
+  return p.fuse && merging(p) && (long_tau(p) || step_passes(p, false).n == 3);
 }
 
 brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count, int row0,
@@ -483,8 +485,16 @@ brahms_status launch_step(brahms_plan_s& p, int row, const StepIO& io, bool cont
 }
 
 brahms_status launch_fused_step(brahms_plan_s& p, int row, bool first, bool last, bool odd) {
-  // axes a, m, b of the schedule; odd steps run them as b, m, a
-  const int a0 = pass_axis(p, 0), mid = pass_axis(p, 1), b0 = pass_axis(p, 2);
+  // axes a, m, b of the schedule; odd steps run them as b, m, a.  A long
+  // tau axis is the middle one (its three passes), with x and y at the ends.
+  const bool lt = long_tau(p);
+  int a0 = pass_axis(p, 0), b0 = pass_axis(p, 2);
+  if (lt) {
+    a0 = (p.order & 1) ? int(AX_Y) : int(AX_X);
+    b0 = (p.order & 1) ? int(AX_X) : int(AX_Y);
+  }
+  const int mids[3] = {lt ? int(AX_TAF) : pass_axis(p, 1), int(AX_TB), int(AX_TAI)};
+  const int nmid = lt ? 3 : 1;
   const int lead = odd ? b0 : a0, tail = odd ? a0 : b0;
   auto in_place = [&](PassArgs& a) {
     for (int j = 0; j < 3; ++j) {
@@ -500,10 +510,10 @@ brahms_status launch_fused_step(brahms_plan_s& p, int row, bool first, bool last
     in_place(a);
     if (brahms_status st = timed_dispatch(p, lead, NL_BEFORE, a)) return st;
   }
-  {
-    PassArgs a = pass_args(p, row, mid);
+  for (int k = 0; k < nmid; ++k) {
+    PassArgs a = pass_args(p, row, mids[k]);
     in_place(a);
-    if (brahms_status st = timed_dispatch(p, mid, NL_NONE, a)) return st;
+    if (brahms_status st = timed_dispatch(p, mids[k], NL_NONE, a)) return st;
   }
   PassArgs a = pass_args(p, row, tail);
   in_place(a);
@@ -878,8 +888,8 @@ brahms_status brahms_plan_set_schedule(brahms_plan plan, const brahms_schedule* 
     return fail(BRAHMS_E_INVALID_ARG, "fuse_steps must be 0 or 1");
   if (sched->fuse_steps && !sched->merge_halves)
     return fail(BRAHMS_E_INVALID_ARG, "fuse_steps needs merge_halves");
-  if (sched->fuse_steps && (detail::long_tau(*plan) || detail::step_passes(*plan, false).n != 3))
-    return fail(BRAHMS_E_UNSUPPORTED, "fuse_steps needs three passes per step (tau <= 256, nx or ny > 1)");
+  if (sched->fuse_steps && !detail::long_tau(*plan) && detail::step_passes(*plan, false).n != 3)
+    return fail(BRAHMS_E_UNSUPPORTED, "fuse_steps needs an x and a y pass (not nx = ny = 1 with tau <= 256)");
   if (plan->order != sched->pass_order || plan->use_graph != (sched->graph != 0) ||
       plan->merge != (sched->merge_halves != 0) || plan->fuse != (sched->fuse_steps != 0))
     drop_chunk_graph(*plan);

@@ -133,7 +133,8 @@ brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count, int row0
 // map, and not while monitor records or snapshots are due (every step they
 // look at must end on its own second half-step).
 bool merging(const brahms_plan_s& p);
-// Whether a call fuses step pairs: merging, and three passes per step.
+// Whether a call fuses step pairs: merging, and x and y passes at the ends
+// of a step (three passes, or a long tau axis in the middle).
 bool fusing(const brahms_plan_s& p);
 // The passes of one z-step in order: axis (AX_*) and RK4 mode (NL_*) of
 // each.  Three passes in general; passes along an axis of length 1 are left

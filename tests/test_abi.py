@@ -201,9 +201,13 @@ def test_schedule_host_checks(lib):
     assert (out.merge_halves, out.fuse_steps) == (1, 1)
     sc.fuse_steps = 0
     lib.brahms_plan_destroy(h)
-    # a long tau axis takes five passes per step: no fused pairs
+    # a long tau axis sits between the x and y passes of fused pairs; plane
+    # waves with one tau pass per step have nothing to fuse
     st, h = _create(lib, 8, 8, 1024, 2, c)
     sc.fuse_steps = 1
+    assert lib.brahms_plan_set_schedule(h, ctypes.byref(sc)) == brahms.BRAHMS_OK
+    lib.brahms_plan_destroy(h)
+    st, h = _create(lib, 1, 1, 64, 2, c)
     assert lib.brahms_plan_set_schedule(h, ctypes.byref(sc)) == brahms.BRAHMS_E_UNSUPPORTED
     sc.fuse_steps = 0
     lib.brahms_plan_destroy(h)

@@ -61,10 +61,11 @@ def test_coupled_long_tau(nf, shape, profile, map_):
                          dk=(1.0 + rng.standard_normal(nz)) if profile else None,
                          dk_map=rng.uniform(-4, 4, (ny, nx)) if map_ else None)
     wl.init = _pulse_fields(rng, nf, nx, ny, nt, 0.8)
-    for m in ([0] if profile or map_ else [0, 1]):
-        out = brahms.run_workload(wl, device=DEV, merge_halves=m)
-        for a, r in zip(out, oracle_run(wl, merge=bool(m))):
-            assert rel_l2(a.cpu().numpy(), r.numpy()) < 1e-5, m
+    for m, f in ([(0, 0)] if profile or map_ else [(0, 0), (1, 0), (1, 1)]):
+        for order in ((0, 1) if f else (0,)):
+            out = brahms.run_workload(wl, device=DEV, pass_order=order, merge_halves=m, fuse_steps=f)
+            for a, r in zip(out, oracle_run(wl, merge=bool(m))):
+                assert rel_l2(a.cpu().numpy(), r.numpy()) < 1e-5, (m, f, order)
 
 
 def test_paper_grid_opg_64x64x1024():
@@ -80,10 +81,37 @@ def test_paper_grid_opg_64x64x1024():
     noise = [1e-6 * (rng.standard_normal((nt, ny, nx)) + 1j * rng.standard_normal((nt, ny, nx))) / np.sqrt(2)
              for _ in range(2)]
     wl.init = [inputs.to_c64(pump), inputs.to_c64(noise[0]), inputs.to_c64(noise[1])]
-    out = brahms.run_workload(wl, device=DEV)
-    ref = ssfm.propagate([to_torch(a) for a in wl.init], oracle_problem(wl), wl.nz)
-    for a, r in zip(out, ref):
-        assert rel_l2(a.cpu().numpy(), r.numpy()) < 1e-5
+    # literal half-steps, and fused step pairs (x and y passes at the ends,
+    # the three tau passes in the middle) against the oracle's merged loop
+    for m, f in ((0, 0), (1, 1)):
+        out = brahms.run_workload(wl, device=DEV, merge_halves=m, fuse_steps=f)
+        for a, r in zip(out, oracle_run(wl, merge=bool(m))):
+            assert rel_l2(a.cpu().numpy(), r.numpy()) < 1e-5, (m, f)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_long_tau_fused_graph_is_bitwise_eager(order):
+    """Fused step pairs on a long tau axis: 64-step graph replays give the
+    bits of launch-by-launch stepping over ragged calls."""
+    rng = np.random.default_rng(31)
+    nz = 300
+    wl = inputs.Workload("g", 4, 8, 512, 2, nz, 1.0 / nz, _fields_spec(2, 1.5, rng), dk_const=0.9)
+    wl.init = _pulse_fields(rng, 2, 4, 8, 512, 0.8)
+
+    def run(graph):
+        f = [torch.from_numpy(a).to(DEV) for a in wl.init]
+        plan = brahms.Plan(wl.nx, wl.ny, wl.nt, wl.nf, brahms.params_from_workload(wl))
+        plan.set_schedule(order, graph, 1, 1)
+        plan.bind(f)
+        for c in (70, 129, 64, 1, 36):
+            plan.step(c)
+        torch.cuda.synchronize()
+        out = [x.clone() for x in f]
+        plan.destroy()
+        return out
+
+    for a, b in zip(run(0), run(1)):
+        assert torch.equal(a, b)
 
 
 @pytest.mark.parametrize("merge", [0, 1])
