@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint and batched-sweep side measurements")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated side measurements to run (adjoint, batch, reduced_dims, "
+                         "diagnostics, dk_map, paper_grids) or 'all'")
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle z-steps in the CPU sample")
     ap.add_argument("--pass-order", default="auto", choices=["auto", "0", "1", "2", "3"],
                     help="plan schedule: autotuned (default) or a fixed pass order")
@@ -538,10 +541,13 @@ def main():
     progress(f"{wl.name}: {value:.4g} grid-point z-steps/s, {wall / steps * 1e3:.4f} ms per step")
     extras = {}
     if not args.no_extras:
+        wanted = None if args.extras == "all" else set(args.extras.split(","))
         for name, fn in (("adjoint", lambda: adjoint_ratio(dev)), ("batch", lambda: batch_ratio(dev)),
                          ("reduced_dims", lambda: reduced_dims(dev)),
                          ("diagnostics", lambda: diagnostics_cost(dev, wl)),
                          ("dk_map", lambda: dk_map_cost(dev)), ("paper_grids", lambda: paper_grids(dev))):
+            if wanted is not None and name not in wanted:
+                continue
             extras[name] = fn()
             progress(f"extra {name} done")
 
