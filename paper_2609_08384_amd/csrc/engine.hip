@@ -4,11 +4,14 @@
 // the fields, and one workspace holding the axis twiddles, the integrated
 // mismatch profile, and a ring of per-step tables (propagators and RK4
 // coefficients) that a small kernel refills every kChunk steps.  A z-step is
-// three launches on the caller's stream: X pass (RK4 half-step + x line
-// transforms), Y pass (y line transforms), T pass (tau line transforms + RK4
-// half-step), or the same in the order T, Y, X; five launches when the tau
-// axis is longer than 256.  With the graph schedule whole chunks are replayed
-// from a hipGraph.
+// three launches on the caller's stream, one per axis in the schedule's pass
+// order (e.g. X pass: RK4 half-step + x line transforms, Y pass: y line
+// transforms, T pass: tau line transforms + RK4 half-step); five launches
+// when the tau axis is longer than 256.  With merged half-steps one RK4 step
+// of size dz joins consecutive steps; with fused step pairs the steps
+// alternate their axis order and one launch ends a step and begins the next
+// (two launches per step, four with a long tau axis).  With the graph
+// schedule whole chunks are replayed from a hipGraph.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
