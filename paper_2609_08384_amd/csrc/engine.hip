@@ -375,6 +375,9 @@ bool fusing(const brahms_plan_s& p) {
 
 brahms_status refresh_tables(brahms_plan_s& p, long long n0, int count, int row0,
                              long long merge_last) {
+  if (count < 0 || row0 < 0 || row0 + count > kTableRows ||
+      (!p.dk_map.empty() && p.map_rows == kChunk && count > kChunk))
+    return fail(BRAHMS_E_INVALID_ARG, "table rows out of range");
   const int per_field = p.nx + p.ny + p.nt;
   TableArgs ta{};
   ta.row_stride = table_row_stride(p.nf, p.nx, p.ny, p.nt);
