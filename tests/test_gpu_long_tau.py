@@ -114,9 +114,9 @@ def test_long_tau_fused_graph_is_bitwise_eager(order):
         assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("merge", [0, 1])
+@pytest.mark.parametrize("merge,fuse", [(0, 0), (1, 0), (1, 1)])
 @pytest.mark.parametrize("group_max", [0, 1])
-def test_long_tau_in_batches(group_max, merge):
+def test_long_tau_in_batches(group_max, merge, fuse):
     """Long-tau problems (nt = 512, 1024, 4096) in a batch with an ordinary
     one: each bitwise equal to the same problem run alone, and one against
     the oracle."""
@@ -130,13 +130,15 @@ def test_long_tau_in_batches(group_max, merge):
     batch = brahms.Batch([(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls])
     batch.set_schedule(group_max)
     batch.set_merge_halves(merge)
+    batch.set_fuse_steps(fuse)   # fuses the ordinary group; long tau groups keep five passes
     fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
     batch.bind(fields)
     batch.run()
     torch.cuda.synchronize()
     batch.destroy()
     for w, fs in zip(wls, fields):
-        alone = brahms.run_workload(w, device=DEV, merge_halves=merge)
+        alone = brahms.run_workload(w, device=DEV, merge_halves=merge,
+                                    fuse_steps=fuse if w.nt <= 256 else 0)
         for a, b in zip(fs, alone):
             assert torch.equal(a, b), (w.nx, w.ny, w.nt)
     for a, r in zip(fields[1], oracle_run(wls[1], merge=bool(merge))):

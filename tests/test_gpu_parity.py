@@ -384,3 +384,29 @@ def test_fused_step_pairs_refused_where_a_step_is_not_three_passes():
     assert ei.value.status == brahms.BRAHMS_E_UNSUPPORTED
     plan.set_schedule(0, 0, 1, 0)
     plan.destroy()
+
+
+def test_snapshots_suspend_merged_and_fused_schedules():
+    """Snapshots look at the fields after single steps, so calls made while
+    they are set run literal half-steps and three passes: the same bits as a
+    plan with the literal schedule, and the snapshots match it too."""
+    rng = np.random.default_rng(44)
+    init = inputs.random_fields(rng, 3, 32, 16, 8, scale=0.6, smooth=4.0)
+    wl = _wl(32, 16, 8, 3, 40, 0.02, _all_terms(3, kappa=1.5), dk_const=1.1, init=init)
+    params = brahms.params_from_workload(wl)
+
+    def run(merge, fuse):
+        f = [torch.from_numpy(a).to(DEV) for a in init]
+        plan = brahms.Plan(wl.nx, wl.ny, wl.nt, wl.nf, params)
+        plan.set_schedule(0, 0, merge, fuse)
+        assert plan.get_schedule()["fuse_steps"] == fuse
+        plan.bind(f)
+        snaps = plan.set_snapshots([5, 17])
+        plan.step(30)
+        torch.cuda.synchronize()
+        out = [x.clone() for x in f] + [t.clone() for snap in snaps for t in snap]
+        plan.destroy()
+        return out
+
+    for a, b in zip(run(1, 1), run(0, 0)):
+        assert torch.equal(a, b)
