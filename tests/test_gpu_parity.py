@@ -410,3 +410,54 @@ def test_snapshots_suspend_merged_and_fused_schedules():
 
     for a, b in zip(run(1, 1), run(0, 0)):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("merge,fuse", [(0, 0), (1, 0), (1, 1)])
+def test_degenerate_calls_and_fields(merge, fuse):
+    """Zero steps leave the fields and z untouched; all-zero fields stay
+    exactly zero (every transform, propagator and RK4 product of zeros is
+    zero); both under every schedule."""
+    rng = np.random.default_rng(12)
+    init = inputs.random_fields(rng, 3, 16, 32, 8, scale=0.6, smooth=4.0)
+    wl = _wl(16, 32, 8, 3, 10, 0.02, _all_terms(3, kappa=1.5), dk_const=0.7, init=init)
+    f = [torch.from_numpy(a).to(DEV) for a in init]
+    plan = brahms.Plan(wl.nx, wl.ny, wl.nt, wl.nf, brahms.params_from_workload(wl))
+    plan.set_schedule(1, 0, merge, fuse)
+    plan.bind(f)
+    plan.step(0)
+    torch.cuda.synchronize()
+    assert plan.z == 0.0
+    for a, b in zip(f, init):
+        assert np.array_equal(a.cpu().numpy(), b)
+    for x in f:
+        x.zero_()
+    plan.step(7)
+    torch.cuda.synchronize()
+    assert abs(plan.z - 7 * wl.dz) < 1e-12
+    for x in f:
+        assert not torch.any(x != 0)
+    plan.destroy()
+
+
+def test_batch_member_with_no_steps_is_untouched():
+    """A batch member with a step count of 0 keeps its fields, with merged
+    half-steps and fused step pairs in the launches around it."""
+    rng = np.random.default_rng(13)
+    wls = []
+    for nz in (0, 9, 4):
+        init = inputs.random_fields(rng, 2, 16, 16, 16, scale=0.6, smooth=4.0)
+        wls.append(_wl(16, 16, 16, 2, nz, 0.05, _all_terms(2, kappa=1.0), dk_const=0.4, init=init))
+    batch = brahms.Batch([(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls])
+    batch.set_merge_halves(1)
+    batch.set_fuse_steps(1)
+    fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
+    batch.bind(fields)
+    batch.run()
+    torch.cuda.synchronize()
+    batch.destroy()
+    for a, b in zip(fields[0], wls[0].init):
+        assert np.array_equal(a.cpu().numpy(), b)
+    for w, fs in zip(wls[1:], fields[1:]):
+        alone = brahms.run_workload(w, device=DEV, pass_order=0, merge_halves=1, fuse_steps=1)
+        for a, b in zip(fs, alone):
+            assert torch.equal(a, b)
