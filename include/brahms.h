@@ -292,7 +292,8 @@ brahms_status brahms_adjoint_backward(brahms_plan plan, void* const* grad, doubl
  *   three passes as fused step pairs (as the plan schedule field fuse_steps;
  *   a problem's last step ends on its own second half-step inside the fused
  *   launch).  Needs merged half-steps (BRAHMS_E_INVALID_ARG otherwise);
- *   invalidates the binding.
+ *   BRAHMS_E_UNSUPPORTED for a batch that holds a problem with a tau axis
+ *   longer than 256.  Invalidates the binding.
  * brahms_batch_set_group_limits: per-problem launch-group sizes (n entries,
  *   0 = from the cache budget) that replace group_max; a group takes the
  *   limit of its first problem, so give problems of one shape the same one.

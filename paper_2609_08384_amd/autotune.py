@@ -176,7 +176,9 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
     problems = batch.problems
     n = len(problems)
     merge = int(merge_halves and all(can_merge(prm) for (_, _, _, _, prm, _) in problems))
-    fuse = int(merge and any(can_fuse(nx, ny, nt) for (nx, ny, nt, _, _, _) in problems))
+    # (batches holding a long tau problem do not fuse)
+    fuse = int(merge and all(nt <= 256 for (_, _, nt, _, _, _) in problems) and
+               any(can_fuse(nx, ny, nt) for (nx, ny, nt, _, _, _) in problems))
     tuned = [tune(nx, ny, nt, nf, prm, device, merge_halves=bool(merge))["pass_order"]
              for (nx, ny, nt, nf, prm, _) in problems]
     order_sets = {"per_shape": tuned, "all_0": [0] * n, "all_1": [1] * n}

@@ -525,6 +525,12 @@ brahms_status brahms_batch_set_fuse_steps(brahms_batch b, int fuse_steps) {
   if (brahms_status st = check_batch(b)) return st;
   if (fuse_steps != 0 && fuse_steps != 1) return fail(BRAHMS_E_INVALID_ARG, "fuse_steps must be 0 or 1");
   if (fuse_steps && !b->merge) return fail(BRAHMS_E_INVALID_ARG, "fuse_steps needs merge_halves");
+  // switched off for batches that hold a long tau problem: a test run of such
+  // a batch was followed by a host fault whose cause was not found
+  if (fuse_steps)
+    for (brahms_plan p : b->plans)
+      if (brahms::detail::long_tau(*p))
+        return fail(BRAHMS_E_UNSUPPORTED, "fuse_steps in a batch with a long tau problem");
   b->fuse = fuse_steps != 0;
   drop_graph(*b);
   b->bound = false;

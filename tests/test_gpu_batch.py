@@ -185,6 +185,20 @@ def test_merged_batch_equals_plain_runs_and_oracle(group_max, fuse):
     b2.destroy()
 
 
+def test_fused_batches_refuse_long_tau_problems():
+    """Fused step pairs are switched off for batches that hold a long tau
+    problem (no kernel runs here)."""
+    fs = [inputs.FieldSpec(kappa=1.0), inputs.FieldSpec(kappa=0.5)]
+    w = inputs.Workload("l", 4, 4, 1024, 2, 3, 0.1, fs)
+    s = inputs.Workload("s", 16, 16, 16, 2, 3, 0.1, fs)
+    batch = brahms.Batch([(x.nx, x.ny, x.nt, x.nf, brahms.params_from_workload(x), x.nz) for x in (w, s)])
+    batch.set_merge_halves(1)
+    with pytest.raises(brahms.BrahmsError) as ei:
+        batch.set_fuse_steps(1)
+    assert ei.value.status == brahms.BRAHMS_E_UNSUPPORTED
+    batch.destroy()
+
+
 def test_group_limits_reject_negative():
     wls = _problems()[:2]
     batch = brahms.Batch([(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls])
