@@ -302,9 +302,14 @@ brahms_status brahms_adjoint_backward(brahms_plan plan, void* const* grad, doubl
  * brahms_batch_bind: fields holds sum(nf_i) device pointers, problem-major,
  *   each in the field layout of brahms_plan_bind; workspace as for plans.
  * brahms_batch_run: propagate every problem nsteps[i] steps from z = 0
- *   (asynchronous; the first run also builds the graph).
+ *   (asynchronous, one graph launch on hip_stream; the first run also
+ *   builds the graph).  Descriptor uploads at bind also go on hip_stream and
+ *   wait for it.
  * brahms_batch_groups: number of launch groups and their sizes (members may
- *   be NULL or hold one int per group). */
+ *   be NULL or hold one int per group).
+ * brahms_batch_destroy: waits for hip_stream, then frees the batch; the
+ *   streams and events that captured its graph are kept for later batches on
+ *   the same device, not destroyed. */
 typedef struct brahms_batch_s* brahms_batch;
 brahms_status brahms_batch_create(int n, const int* shapes, const brahms_params* params,
                                   const int* nsteps, void* hip_stream, brahms_batch* out);

@@ -9,18 +9,26 @@
 // small grids fill the GPU.  Problems with fewer steps than the longest in
 // their group leave their blocks at once.  The whole run (tables and passes
 // of every group) is captured once into a hipGraph and replayed by
-// brahms_batch_run.  Launch groups are independent branches of that graph
-// (up to four side streams, groups dealt out largest first), so a
-// bandwidth-bound group of large grids and latency-bound groups of small
-// grids execute at the same time; within a branch groups run one after the
-// other, and the default group size (a state of at most 160 MB) keeps a
-// group's fields in the last-level cache while it is propagated.
+// brahms_batch_run.  Launch groups are independent and could be parallel
+// branches of that graph (up to four side streams, groups dealt out largest
+// first) so that a bandwidth-bound group of large grids and latency-bound
+// groups of small grids execute at the same time; that is switched off (see
+// kParallelBranches) and the groups run one after the other, largest first.
+// The default group size (a state of at most 160 MB) keeps a group's fields
+// in the last-level cache while it is propagated.
+//
+// The graph is launched on the caller's stream, so a run orders itself after
+// the caller's earlier work without cross-stream events.  The streams and
+// events used to capture it come from a per-device pool and go back to it
+// when the batch is destroyed: the library destroys no stream or event of a
+// batch while the process runs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <vector>
 
@@ -38,9 +46,9 @@ struct brahms_batch_s {
   int n = 0;
   std::vector<brahms_plan> plans;
   std::vector<int> nsteps;
-  hipStream_t caller = nullptr;
-  hipStream_t stream = nullptr;        // the batch's own stream (graph capture)
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipStream_t caller = nullptr;        // the caller's stream: uploads and graph launches
+  int device = -1;                     // device of the capture streams
+  hipStream_t stream = nullptr;        // capture stream (from the pool)
   char* ws = nullptr;
   bool bound = false;
   std::vector<size_t> plan_off;        // per problem: offset of its plan workspace
@@ -68,6 +76,77 @@ struct brahms_batch_s {
 };
 
 namespace {
+
+// Capture streams and events of one batch, kept for reuse by later batches
+// on the same device.
+struct CaptureSet {
+  int device;
+  hipStream_t stream;
+  hipStream_t side[brahms_batch_s::kBranches];
+  hipEvent_t fork;
+  hipEvent_t join[brahms_batch_s::kBranches];
+};
+std::mutex g_capture_mu;
+std::vector<CaptureSet> g_capture_pool;
+
+// Fills b's capture streams and events from the pool of the current device,
+// or creates them.  Returns false when HIP cannot create them.
+bool acquire_capture(brahms_batch_s& b) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  {
+    std::lock_guard<std::mutex> lock(g_capture_mu);
+    for (size_t k = 0; k < g_capture_pool.size(); ++k) {
+      if (g_capture_pool[k].device != dev) continue;
+      const CaptureSet c = g_capture_pool[k];
+      g_capture_pool.erase(g_capture_pool.begin() + long(k));
+      b.device = dev;
+      b.stream = c.stream;
+      b.fork = c.fork;
+      for (int j = 0; j < brahms_batch_s::kBranches; ++j) {
+        b.side[j] = c.side[j];
+        b.join[j] = c.join[j];
+      }
+      return true;
+    }
+  }
+  // on a failed creation the members made so far stay alive, unused
+  b.device = dev;
+  bool ok = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&b.fork, hipEventDisableTiming) == hipSuccess;
+  for (int j = 0; ok && j < brahms_batch_s::kBranches; ++j)
+    ok = hipStreamCreateWithFlags(&b.side[j], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&b.join[j], hipEventDisableTiming) == hipSuccess;
+  return ok;
+}
+
+// Hands b's capture streams and events back to the pool (a set with a
+// missing member is kept out of it; its members stay alive unused).
+void release_capture(brahms_batch_s& b) {
+  if (b.device < 0) return;
+  bool whole = b.stream != nullptr && b.fork != nullptr;
+  for (int j = 0; j < brahms_batch_s::kBranches; ++j)
+    whole = whole && b.side[j] != nullptr && b.join[j] != nullptr;
+  if (whole) {
+    CaptureSet c{};
+    c.device = b.device;
+    c.stream = b.stream;
+    c.fork = b.fork;
+    for (int j = 0; j < brahms_batch_s::kBranches; ++j) {
+      c.side[j] = b.side[j];
+      c.join[j] = b.join[j];
+    }
+    std::lock_guard<std::mutex> lock(g_capture_mu);
+    g_capture_pool.push_back(c);
+  }
+  b.device = -1;
+  b.stream = nullptr;
+  b.fork = nullptr;
+  for (int j = 0; j < brahms_batch_s::kBranches; ++j) {
+    b.side[j] = nullptr;
+    b.join[j] = nullptr;
+  }
+}
 
 constexpr size_t kCacheBudget = size_t(160) << 20;  // bytes of field state per group
 
@@ -341,9 +420,10 @@ brahms_status upload_descriptors(brahms_batch_s& b) {
       }
     }
   }
-  HIP_TRY(hipMemcpyAsync(b.ws + b.off_desc, desc.data(), desc.size(), hipMemcpyHostToDevice, b.stream));
-  HIP_TRY(hipMemcpyAsync(b.ws + b.off_targs, targ.data(), targ.size(), hipMemcpyHostToDevice, b.stream));
-  HIP_TRY(hipStreamSynchronize(b.stream));
+  // on the caller's stream, after any run still reading the old descriptors
+  HIP_TRY(hipMemcpyAsync(b.ws + b.off_desc, desc.data(), desc.size(), hipMemcpyHostToDevice, b.caller));
+  HIP_TRY(hipMemcpyAsync(b.ws + b.off_targs, targ.data(), targ.size(), hipMemcpyHostToDevice, b.caller));
+  HIP_TRY(hipStreamSynchronize(b.caller));
   return BRAHMS_OK;
 }
 
@@ -389,8 +469,16 @@ brahms_status enqueue_group(brahms_batch_s& b, const brahms_batch_s::Group& g, h
   return BRAHMS_OK;
 }
 
-// The whole run: forks from b.stream into the side streams (launch groups
-// dealt round-robin, largest first), and joins back.
+// Parallel graph branches (groups dealt round-robin over the side streams)
+// are switched off: a batch whose branched graph had just been destroyed was
+// followed, in several test runs, by a crash on the HIP runtime's own thread,
+// and the cause was not found.  Linear graphs, as plans use them, never
+// showed it.
+constexpr bool kParallelBranches = false;
+
+// The whole run, largest groups first: on b.stream one after the other, or,
+// with parallel branches, forked from b.stream into the side streams and
+// joined back.
 brahms_status enqueue_run(brahms_batch_s& b) {
   std::vector<size_t> order(b.groups.size());
   for (size_t k = 0; k < order.size(); ++k) order[k] = k;
@@ -399,6 +487,11 @@ brahms_status enqueue_run(brahms_batch_s& b) {
     return double(g.axis_len[0]) * g.axis_len[1] * g.axis_len[2] * g.members.size() * g.max_steps;
   };
   std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) { return work(a) > work(c); });
+  if (!kParallelBranches) {
+    for (size_t k = 0; k < order.size(); ++k)
+      if (brahms_status st = enqueue_group(b, b.groups[order[k]], b.stream)) return st;
+    return BRAHMS_OK;
+  }
   const int nb = std::min<int>(brahms_batch_s::kBranches, int(order.size()));
   HIP_TRY(hipEventRecord(b.fork, b.stream));
   for (int k = 0; k < nb; ++k) HIP_TRY(hipStreamWaitEvent(b.side[k], b.fork, 0));
@@ -412,6 +505,8 @@ brahms_status enqueue_run(brahms_batch_s& b) {
 }
 
 void drop_graph(brahms_batch_s& b) {
+  // no launch of the graph may still run when it goes
+  if (b.exec) (void)hipStreamSynchronize(b.caller);
   if (b.exec) (void)hipGraphExecDestroy(b.exec);
   if (b.graph) (void)hipGraphDestroy(b.graph);
   b.exec = nullptr;
@@ -475,18 +570,11 @@ brahms_status brahms_batch_create(int n, const int* shapes, const brahms_params*
     b->plans.push_back(p);
     b->nsteps.push_back(nsteps[i]);
   }
-  bool ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess &&
-            hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) == hipSuccess &&
-            hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) == hipSuccess &&
-            hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
-  for (int k = 0; ok && k < brahms_batch_s::kBranches; ++k)
-    ok = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking) == hipSuccess &&
-         hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) == hipSuccess;
-  if (!ok) {
+  if (!acquire_capture(*b)) {
     brahms_batch_destroy(b);
     return fail(BRAHMS_E_DEVICE, "could not create the batch streams or events");
   }
-  for (brahms_plan p : b->plans) p->stream = b->stream;
+  for (brahms_plan p : b->plans) p->stream = b->caller;
   layout_batch(*b);
   *out = b;
   return BRAHMS_OK;
@@ -580,8 +668,6 @@ brahms_status brahms_batch_bind(brahms_batch b, void* const* fields, void* works
 brahms_status brahms_batch_run(brahms_batch b) {
   if (brahms_status st = check_batch(b)) return st;
   if (!b->bound) return fail(BRAHMS_E_STATE, "brahms_batch_run before brahms_batch_bind");
-  HIP_TRY(hipEventRecord(b->ev_in, b->caller));
-  HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_in, 0));
   if (b->exec == nullptr) {
     HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     const brahms_status st = enqueue_run(*b);
@@ -606,9 +692,7 @@ brahms_status brahms_batch_run(brahms_batch b) {
     b->graph = graph;
     b->exec = exec;
   }
-  HIP_TRY(hipGraphLaunch(b->exec, b->stream));
-  HIP_TRY(hipEventRecord(b->ev_out, b->stream));
-  HIP_TRY(hipStreamWaitEvent(b->caller, b->ev_out, 0));
+  HIP_TRY(hipGraphLaunch(b->exec, b->caller));
   for (int i = 0; i < b->n; ++i) b->plans[i]->step = b->nsteps[i];
   return BRAHMS_OK;
 }
@@ -624,18 +708,9 @@ brahms_status brahms_batch_groups(brahms_batch b, int* ngroups, int* members) {
 
 brahms_status brahms_batch_destroy(brahms_batch b) {
   if (b == nullptr) return fail(BRAHMS_E_INVALID_ARG, "batch is NULL");
-  // no launch of the graph may still run when it and the streams go
-  if (b->stream) (void)hipStreamSynchronize(b->stream);
-  drop_graph(*b);
+  drop_graph(*b);   // waits for the caller's stream first
   for (brahms_plan p : b->plans) brahms_plan_destroy(p);
-  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
-  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
-  if (b->fork) (void)hipEventDestroy(b->fork);
-  for (int k = 0; k < brahms_batch_s::kBranches; ++k) {
-    if (b->join[k]) (void)hipEventDestroy(b->join[k]);
-    if (b->side[k]) (void)hipStreamDestroy(b->side[k]);
-  }
-  if (b->stream) (void)hipStreamDestroy(b->stream);
+  release_capture(*b);
   delete b;
   return BRAHMS_OK;
 }
