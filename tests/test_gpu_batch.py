@@ -187,6 +187,41 @@ def test_merged_batch_equals_plain_runs_and_oracle(group_max, fuse):
     b2.destroy()
 
 
+@pytest.mark.parametrize("fuse", [0, 1])
+def test_three_field_merged_batch_of_one_shape(fuse):
+    """Three-field problems of one shape in one launch group, with merged
+    half-steps and, if asked, fused step pairs: each bitwise equal to the same
+    problem run alone with that schedule, and one within the oracle
+    tolerance of the oracle's merged loop."""
+    rng = np.random.default_rng(31)
+    wls = []
+    for nz in (12, 7, 16):
+        fs = [inputs.FieldSpec(kappa=1.0 + 0.2 * j, diffraction=float(rng.uniform(0.5, 2.0)),
+                               tan_rho=float(rng.uniform(-0.5, 0.5)), delay=float(rng.uniform(-1, 1)),
+                               k2=float(rng.uniform(-2, 2))) for j in range(3)]
+        wl = inputs.Workload("b3", 16, 32, 32, 3, nz, 1.0 / nz, fs, dk_const=float(rng.uniform(-3, 3)))
+        wl.init = inputs.random_fields(rng, 3, 16, 32, 32, scale=0.7, smooth=8.0)
+        wls.append(wl)
+    probs = [(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls]
+    batch = brahms.Batch(probs)
+    batch.set_schedule(0, [2] * len(wls))
+    batch.set_merge_halves(1)
+    batch.set_fuse_steps(fuse)
+    assert batch.groups() == [len(wls)]
+    fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
+    batch.bind(fields)
+    batch.run()
+    torch.cuda.synchronize()
+    out = [[f.clone() for f in fs] for fs in fields]
+    for w, fs in zip(wls, out):
+        alone = brahms.run_workload(w, device=DEV, pass_order=2, merge_halves=1, fuse_steps=fuse)
+        for a, b in zip(fs, alone):
+            assert torch.equal(a, b), w.nz
+    for a, r in zip(out[0], oracle_run(wls[0], merge=True)):
+        assert rel_l2(a.cpu().numpy(), r.numpy()) < 1e-5
+    batch.destroy()
+
+
 def test_fused_batches_refuse_long_tau_problems():
     """Fused step pairs are switched off for batches that hold a long tau
     problem (no kernel runs here)."""
