@@ -273,8 +273,9 @@ brahms_status brahms_adjoint_backward(brahms_plan plan, void* const* grad, doubl
  * Problems of equal shape, field count and pass order share launches, in
  * groups of at most group_max problems (0 = sized so that a group's fields
  * fit a 160 MB cache budget); the whole run is captured once into a hipGraph
- * on the batch's own stream and replayed, ordered after work already queued
- * on the caller's stream and before work queued there afterwards.
+ * (on a capture stream of the library's) and replayed on the caller's stream
+ * hip_stream, so it is ordered after work already queued there and before
+ * work queued there afterwards.
  *
  * brahms_batch_create: n problems; shapes holds n x 4 ints (nx, ny, nt, nf),
  *   params n brahms_params, nsteps n step counts (each problem is propagated
