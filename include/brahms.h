@@ -127,6 +127,28 @@ brahms_status brahms_step(brahms_plan plan, int nsteps);
  * within 1e-9 max(1, |z_end|) of a multiple of dz and not before z. */
 brahms_status brahms_propagate(brahms_plan plan, double z_end);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): brahms_propagate
+ * with the plan's workspace taken from a static device array of the library
+ * (BRAHMS_NOALLOC_SCRATCH_BYTES bytes, one per GPU, held until the process
+ * ends) instead of a caller buffer.  It binds `fields` (nfields device
+ * pointers, the layout of brahms_plan_bind) and that array to the plan, then
+ * propagates to z_end as brahms_propagate does, with the same kernels: the
+ * result is bitwise the one brahms_plan_bind + brahms_propagate give.  The
+ * plan stays bound to the fields and the array afterwards.  The call
+ * allocates and frees no device memory (no hipMalloc, hipFree, graph capture
+ * or event creation; kernel timing is skipped during the call).
+ * Every call on one GPU shares that GPU's array and leaves its tables there:
+ * calls that overlap on one GPU (two plans on different streams, or another
+ * thread) race and give undefined results; serialise them.  Nothing in the
+ * array needs to start at zero (every table is written before it is read).
+ * Errors: BRAHMS_E_INVALID_ARG for NULL pointers, a z_end as for
+ * brahms_propagate, or a plan whose workspace (brahms_plan_workspace_size)
+ * exceeds BRAHMS_NOALLOC_SCRATCH_BYTES (checked before any device work);
+ * BRAHMS_E_STATE for a plan with the graph schedule; BRAHMS_E_DEVICE. */
+#define BRAHMS_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+brahms_status brahms_propagate_noalloc(brahms_plan plan, void* const* fields, double z_end);
+
 /* Current z = (step index) * dz. */
 brahms_status brahms_get_z(brahms_plan plan, double* z);
 

@@ -80,6 +80,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "brahms_plan_bind": [vp, ctypes.POINTER(vp), vp],
         "brahms_step": [vp, i],
         "brahms_propagate": [vp, d],
+        "brahms_propagate_noalloc": [vp, ctypes.POINTER(vp), d],
         "brahms_get_z": [vp, ctypes.POINTER(d)],
         "brahms_set_z": [vp, d],
         "brahms_plan_destroy": [vp],
@@ -244,6 +245,23 @@ class Plan:
 
     def propagate(self, z_end: float):
         _check(self._lib.brahms_propagate(self._h, float(z_end)), "brahms_propagate")
+
+    def propagate_noalloc(self, fields: Sequence[torch.Tensor], z_end: float):
+        """brahms_propagate_noalloc: bind `fields` with the library's static
+        device scratch as workspace and propagate to z_end (no device
+        allocation in the library or here)."""
+        if len(fields) != self.nf:
+            raise ValueError(f"need {self.nf} fields")
+        for f in fields:
+            if (f.dtype != torch.complex64 or not f.is_cuda or not f.is_contiguous()
+                    or tuple(f.shape) != (self.nt, self.ny, self.nx)):
+                raise ValueError("fields must be contiguous complex64 CUDA tensors of shape "
+                                 f"[{self.nt}, {self.ny}, {self.nx}]")
+        arr = (ctypes.c_void_p * self.nf)(*[f.data_ptr() for f in fields])
+        _check(self._lib.brahms_propagate_noalloc(self._h, arr, float(z_end)),
+               "brahms_propagate_noalloc")
+        self.workspace = None
+        self.fields = list(fields)
 
     @property
     def z(self) -> float:

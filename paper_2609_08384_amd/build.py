@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libbrahms.so")
 
-SOURCES = ["engine.hip", "adjoint.hip", "batch.hip", "diag.hip"]
+SOURCES = ["engine.hip", "adjoint.hip", "batch.hip", "diag.hip", "noalloc.hip"]
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",
     "--offload-arch=gfx950",
