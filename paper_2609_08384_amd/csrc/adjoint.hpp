@@ -171,7 +171,8 @@ __global__ __launch_bounds__(kBlock) void adjoint_pass(AdjArgs args) {
   }
   const unsigned idx0 = base + unsigned(t) * estride;
   const unsigned estep = unsigned(N2) * estride;
-  float2* lbuf = lds + li * G::LSTRIDE;
+  // a line's LDS row (lines of one lane exchange nothing: no row)
+  float2* lbuf = (N2 > 1) ? lds + li * G::LSTRIDE : lds;
   const DftConsts K = *args.consts;
   float2 co[NF][kNlCoef];
 #pragma unroll

@@ -421,7 +421,8 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
       for (int k = 0; k < 3; ++k) wt[k] = args.map[k * plane + xy0];
     }
   }
-  float2* lbuf = lds + li * G::LSTRIDE;
+  // a line's LDS row (lines of one lane exchange nothing: no row)
+  float2* lbuf = (N2 > 1) ? lds + li * G::LSTRIDE : lds;
   const DftConsts K = *args.consts;
 
   float2 v[NF][N1];
