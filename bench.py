@@ -8,8 +8,9 @@ complex64 state, larger than the 256 MB last-level cache), seeded synthetic
 input, fields resident in HBM before timing starts.
 
 Prints one JSON line: grid-point z-steps per second, the HBM roofline of the
-dominant kernel (event-timed launches), and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+whole z-step (its passes' algorithmic bytes over their event-timed
+durations, with every pass kind and the dominant kernel listed beside it),
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -428,7 +429,19 @@ def cpu_baseline(wl, nsteps):
             "cores": torch.get_num_threads(), "kind": "oracle",
             "sample": f"{wl.name}: {nsteps} z-steps of the full {wl.nx}x{wl.ny}x{wl.nt} grid, "
                       f"{wl.nf} fields, complex128, {dt:.1f} s",
-            "cpu": platform.processor() or platform.machine()}
+            "cpu": cpu_model(), "os_cores": os.cpu_count()}
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo), or what platform reports."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 def main():
@@ -493,32 +506,12 @@ def main():
     tim = plan.timing_read()
     plan.timing_enable(False)
     passes = {k: v for k, v in tim.items() if k != "tables"}
-    dom = max(passes, key=lambda k: passes[k][0])
-    dom_ms, dom_n = passes[dom]
-    avg_ms = dom_ms / max(dom_n, 1)
     # algorithmic bytes of one pass launch: every field read once and written
     # once, 2 * 8 B per complex64 value
     bytes_per_launch = 2 * 8 * wl.nf * wl.points
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     order, merge, fuse = (int(schedule["pass_order"]), int(schedule.get("merge_halves", 0)),
                           int(schedule.get("fuse_steps", 0)))
     modes = nl_of_pass(order, merge, fuse)
-    traffic = measured_traffic(wl.name, dom, order, merge, fuse)
-    if modes[dom] == "fused":
-        # two axis transforms and the RK4 step per value read and written:
-        # bound by FP32 vector issue, not by HBM
-        axis_len = {"x_pass": wl.nx, "y_pass": wl.ny, "t_pass": wl.nt}[dom]
-        flops = fused_pass_flops(wl.nf, wl.points, axis_len)
-        tflops = flops / (avg_ms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "achieved": round(tflops, 2), "peak": FP32_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
-                    "frac_of_unpacked_fp32_peak": round(tflops / FP32_UNPACKED_TFLOPS, 4),
-                    "hbm_GBps": round(achieved, 1), "algorithmic_flops_per_launch": flops}
-    else:
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
-    roofline.update({"kernel": dom, "kernel_rk4": modes[dom], "avg_launch_ms": round(avg_ms, 5),
-                     "algorithmic_bytes_per_launch": bytes_per_launch})
     per_kernel = {k: {"avg_ms": round(v[0] / max(v[1], 1), 5), "launches": v[1],
                       "GBps": (round(bytes_per_launch / (v[0] / v[1] * 1e-3) / 1e9, 1)
                                if v[1] and k != "tables" else None)} for k, v in tim.items()}
@@ -529,10 +522,62 @@ def main():
                 n_axis = {"x_pass": wl.nx, "y_pass": wl.ny, "t_pass": wl.nt}[k]
                 tf = fused_pass_flops(wl.nf, wl.points, n_axis) / (rec["avg_ms"] * 1e-3) / 1e12
                 rec.update({"bound": "alu", "TFLOPs": round(tf, 2), "frac": round(tf / FP32_PEAK_TFLOPS, 4),
-                            "frac_of_unpacked_fp32_peak": round(tf / FP32_UNPACKED_TFLOPS, 4)})
+                            "frac_of_unpacked_fp32_peak": round(tf / FP32_UNPACKED_TFLOPS, 4),
+                            "hbm_frac": round(rec["GBps"] / HBM_PEAK_GBS, 4)})
             elif rec["GBps"]:
                 rec.update({"bound": "hbm", "frac": round(rec["GBps"] / HBM_PEAK_GBS, 4)})
-    step_bytes = (2 if merge and fuse else 3) * bytes_per_launch
+    # the dominant kernel: the pass kind with the largest share of the step
+    # time, the fused passes of the two alternating axes counted as one kind
+    kinds = {}
+    for k, (ms, n) in passes.items():
+        kind = "fused_pass" if modes.get(k) == "fused" else k
+        t = kinds.setdefault(kind, [0.0, 0, []])
+        t[0] += ms
+        t[1] += n
+        t[2].append(k)
+    dom = max(kinds, key=lambda k: kinds[k][0])
+    dom_ms, dom_n, dom_members = kinds[dom]
+    avg_ms = dom_ms / max(dom_n, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    if dom == "fused_pass":
+        axis_len = {"x_pass": wl.nx, "y_pass": wl.ny, "t_pass": wl.nt}[dom_members[0]]
+        flops = fused_pass_flops(wl.nf, wl.points, axis_len)
+        tflops = flops / (avg_ms * 1e-3) / 1e12
+        dominant = {"kernel": dom, "axes": dom_members, "bound": "alu", "achieved": round(tflops, 2),
+                    "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
+                    "frac_of_unpacked_fp32_peak": round(tflops / FP32_UNPACKED_TFLOPS, 4),
+                    "hbm_GBps": round(achieved, 1), "algorithmic_flops_per_launch": flops,
+                    "avg_launch_ms": round(avg_ms, 5), "share_of_step_time": round(dom_ms / sum(
+                        v[0] for v in passes.values()), 4)}
+    else:
+        dominant = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_ms": round(avg_ms, 5)}
+    # the whole z-step against the HBM roofline: the passes of one step each
+    # read and write every field once (the design's pass model, 16 nf P bytes
+    # per grid point with P passes per step), timed as the event-timed run's
+    # summed pass durations per step
+    long_t = wl.nt > 256
+    p_step = (4 if long_t else 2) if (merge and fuse) else (5 if long_t else 3)
+    step_bytes = p_step * bytes_per_launch
+    timed_steps = max(1, tsteps)
+    step_ms = sum(v[0] for v in tim.values()) / timed_steps
+    step_gbs = step_bytes / (step_ms * 1e-3) / 1e9
+    traffic = None
+    pass_traffic = {k: measured_traffic(wl.name, k, order, merge, fuse) for k in passes if passes[k][1]}
+    if pass_traffic and all(v is not None for v in pass_traffic.values()):
+        # launches per step of each pass kind in the steady state
+        traffic = int(round(sum(pass_traffic[k] * passes[k][1] for k in pass_traffic) / timed_steps))
+    roofline = {"bound": "hbm", "achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(step_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": f"whole z-step ({p_step} pass launches)", "unit_of_work": "one z-step",
+                "algorithmic_bytes_per_step": step_bytes, "step_ms_event": round(step_ms, 5),
+                "passes": {k: {kk: vv for kk, vv in per_kernel[k].items()} for k in passes},
+                "dominant_kernel": dominant}
+    bytes_per_pt = {"pass_model": 16 * wl.nf * p_step, "compulsory": 16 * wl.nf,
+                    "measured": None if traffic is None else round(traffic / wl.points, 3)}
+    if traffic is not None:
+        bytes_per_pt["measured_over_pass_model"] = round(traffic / wl.points / (16 * wl.nf * p_step), 4)
+        bytes_per_pt["measured_over_compulsory"] = round(traffic / wl.points / (16 * wl.nf), 4)
     plan.destroy()
 
     def progress(msg):
@@ -577,7 +622,9 @@ def main():
                    "parallelism": "single GPU", "schedule": schedule},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "hbm_frac_step": round(step_bytes / (wall / steps) / 1e9 / HBM_PEAK_GBS, 4),
+        "field_point_steps_per_s": value * wl.nf,
+        "bytes_per_point_step": bytes_per_pt,
+        "hbm_frac_step_wall": round(step_bytes / (wall / steps) / 1e9 / HBM_PEAK_GBS, 4),
         "event_ms_per_step": ev_ms / steps,
         "per_kernel": per_kernel,
         "fields_finite": finite,

@@ -51,7 +51,8 @@ extern "C" {
 typedef enum {
   BRAHMS_OK = 0,
   BRAHMS_E_INVALID_ARG = 1,  /* bad size, pointer, parameter or step count   */
-  BRAHMS_E_UNSUPPORTED = 2,  /* an axis length the transforms do not handle  */
+  BRAHMS_E_UNSUPPORTED = 2,  /* an axis length the transforms do not handle, or
+                                a feature combination that is not provided  */
   BRAHMS_E_DEVICE = 3,       /* a HIP runtime error                          */
   BRAHMS_E_NONFINITE = 4,    /* a field became NaN/Inf (dz too large, Sec. 3.2) */
   BRAHMS_E_STATE = 5         /* call out of order (e.g. step before bind)    */
@@ -96,8 +97,11 @@ typedef struct {
 } brahms_params;
 
 /* Create a plan for an nx x ny x nt grid with nfields in {2, 3}.
- * Axis lengths must be 1, 2, 4, 8, 16, 32, 64, 96, 128 or 256
- * (BRAHMS_E_UNSUPPORTED otherwise).  The parameters are copied.
+ * Axis lengths must be 2^a or 3 * 2^a up to 256 (1, 2, 3, 4, 6, 8, 12, 16,
+ * 24, 32, 48, 64, 96, 128, 192, 256); tau may also be 512, 1024, 2048 or
+ * 4096.  BRAHMS_E_UNSUPPORTED otherwise: a prime factor other than 2 and 3,
+ * a factor 3^2 (no register split of the line transform), x or y above 256.
+ * The parameters are copied.
  * Errors: BRAHMS_E_INVALID_ARG for a non-positive size, nf outside {2, 3},
  * NULL params/out, dz <= 0, a non-finite coefficient, dk != NULL with
  * n_dk < 1, or dk_map_scale without dk_map or with n_dk_map_scale < 1. */
@@ -289,6 +293,22 @@ brahms_status brahms_adjoint_forward(brahms_plan plan, int nsteps, int checkpoin
                                      void* adj_workspace);
 brahms_status brahms_adjoint_backward(brahms_plan plan, void* const* grad, double* grad_dk);
 
+/* The adjoint in one call: the vector-Jacobian product of nsteps steps from
+ * the plan's current step n0 for a given cotangent.  fields_in (nf device
+ * buffers) is copied into the plan's bound fields, which are advanced as by
+ * brahms_adjoint_forward (they end at z = (n0 + nsteps) dz, the forward
+ * output); grad_out (dJ/dA at z_end) is copied into grad_in, which then
+ * receives dJ/dA at z0 as by brahms_adjoint_backward, and grad_dk as there.
+ * Buffers may alias (fields_in = the bound fields, grad_in = grad_out).
+ * The split calls above serve the usual case where the cotangent depends on
+ * the forward output (a loss of the fields at z_end): there one forward with
+ * checkpoints serves both the loss and the reverse sweep, where this call
+ * would repeat it.  adj_workspace as for brahms_adjoint_forward.  Errors as
+ * for the two calls it combines. */
+brahms_status brahms_adjoint(brahms_plan plan, int nsteps, int checkpoint_every, const void* const* fields_in,
+                             const void* const* grad_out, void* const* grad_in, double* grad_dk,
+                             void* adj_workspace);
+
 /* Batched sweeps: many independent problems (each its own grid, fields and
  * parameters, e.g. a scan of dk or of the focusing, as the parameter-sweep
  * tab of Sec. 4.4 runs them one after another) propagated together.
@@ -328,6 +348,12 @@ brahms_status brahms_adjoint_backward(brahms_plan plan, void* const* grad, doubl
  *   (asynchronous, one graph launch on hip_stream; the first run also
  *   builds the graph).  Descriptor uploads at bind also go on hip_stream and
  *   wait for it.
+ * brahms_batch_run_steps: a run with per-problem step counts nsteps[i] (n
+ *   entries, each between 0 and the count given at create): the counts go
+ *   into the descriptors (uploaded on hip_stream, after any run still reading
+ *   them) and the same graph is replayed; problems past their count leave
+ *   their launches at once.  Errors: BRAHMS_E_INVALID_ARG for a count out of
+ *   range, BRAHMS_E_STATE before bind.
  * brahms_batch_groups: number of launch groups and their sizes (members may
  *   be NULL or hold one int per group).
  * brahms_batch_destroy: waits for hip_stream, then frees the batch; the
@@ -343,6 +369,7 @@ brahms_status brahms_batch_set_fuse_steps(brahms_batch batch, int fuse_steps);
 brahms_status brahms_batch_workspace_size(brahms_batch batch, size_t* bytes);
 brahms_status brahms_batch_bind(brahms_batch batch, void* const* fields, void* workspace);
 brahms_status brahms_batch_run(brahms_batch batch);
+brahms_status brahms_batch_run_steps(brahms_batch batch, const int* nsteps);
 brahms_status brahms_batch_groups(brahms_batch batch, int* ngroups, int* members);
 brahms_status brahms_batch_destroy(brahms_batch batch);
 

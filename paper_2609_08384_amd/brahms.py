@@ -29,7 +29,7 @@ BRAHMS_CHECK_FINITE = 1
 STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_UNSUPPORTED", 3: "E_DEVICE",
                 4: "E_NONFINITE", 5: "E_STATE"}
 
-SUPPORTED_LENGTHS = (1, 2, 4, 8, 16, 32, 64, 96, 128, 256)
+SUPPORTED_LENGTHS = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256)
 TIMING_KINDS = 4
 TIMING_NAMES = ("x_pass", "y_pass", "t_pass", "tables")
 
@@ -89,6 +89,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "brahms_adjoint_workspace_size": [vp, i, i, ctypes.POINTER(ctypes.c_size_t)],
         "brahms_adjoint_forward": [vp, i, i, vp],
         "brahms_adjoint_backward": [vp, ctypes.POINTER(vp), ctypes.POINTER(d)],
+        "brahms_adjoint": [vp, i, i, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                           ctypes.POINTER(d), vp],
         "brahms_batch_create": [i, ctypes.POINTER(i), ctypes.POINTER(ParamsC), ctypes.POINTER(i), vp,
                                 ctypes.POINTER(vp)],
         "brahms_batch_set_schedule": [vp, i, ctypes.POINTER(i)],
@@ -98,6 +100,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "brahms_batch_workspace_size": [vp, ctypes.POINTER(ctypes.c_size_t)],
         "brahms_batch_bind": [vp, ctypes.POINTER(vp), vp],
         "brahms_batch_run": [vp],
+        "brahms_batch_run_steps": [vp, ctypes.POINTER(i)],
         "brahms_batch_groups": [vp, ctypes.POINTER(i), ctypes.POINTER(i)],
         "brahms_batch_destroy": [vp],
         "brahms_timing_enable": [vp, i],
@@ -116,6 +119,17 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.brahms_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
+
+
+def _device_bytes(nbytes: int, device, stream=None) -> torch.Tensor:
+    """A uint8 device tensor of nbytes for a workspace used by library work on
+    `stream`: allocated while that stream is current, so that torch's caching
+    allocator does not hand the memory to other work before the work queued
+    on that stream is done."""
+    if stream is None:
+        return torch.empty(nbytes, dtype=torch.uint8, device=device)
+    with torch.cuda.stream(stream):
+        return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
 def _check(status: int, where: str):
@@ -229,8 +243,7 @@ class Plan:
                 raise ValueError("fields must be contiguous complex64 CUDA tensors of shape "
                                  f"[{self.nt}, {self.ny}, {self.nx}]")
         if workspace is None:
-            workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8,
-                                    device=fields[0].device)
+            workspace = _device_bytes(self.workspace_bytes + 256, fields[0].device, self.stream)
         ptr = workspace.data_ptr()
         aligned = (ptr + 255) // 256 * 256
         arr = (ctypes.c_void_p * self.nf)(*[f.data_ptr() for f in fields])
@@ -303,7 +316,7 @@ class Plan:
     def adjoint_forward(self, nsteps: int, checkpoint_every: int):
         """Advance nsteps like step(), keeping checkpoints for the backward."""
         nbytes = self.adjoint_workspace_bytes(nsteps, checkpoint_every)
-        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.fields[0].device)
+        ws = _device_bytes(nbytes + 256, self.fields[0].device, self.stream)
         aligned = (ws.data_ptr() + 255) // 256 * 256
         _check(self._lib.brahms_adjoint_forward(self._h, int(nsteps), int(checkpoint_every),
                                                 ctypes.c_void_p(aligned)),
@@ -325,6 +338,29 @@ class Plan:
         _check(self._lib.brahms_adjoint_backward(
             self._h, arr, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
             "brahms_adjoint_backward")
+        return out
+
+    def adjoint(self, nsteps: int, checkpoint_every: int, fields_in: Sequence[torch.Tensor],
+                grad_out: Sequence[torch.Tensor], grad_in: Sequence[torch.Tensor]):
+        """brahms_adjoint: dJ/dA at the current z into grad_in (and returns
+        dJ/ddk) for the cotangent grad_out at z + nsteps dz, with the
+        forward from fields_in run in the bound fields."""
+        import numpy as np
+        for t in list(fields_in) + list(grad_out) + list(grad_in):
+            if (t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous()
+                    or tuple(t.shape) != (self.nt, self.ny, self.nx)):
+                raise ValueError("buffers must be contiguous complex64 CUDA tensors in field layout")
+        nbytes = self.adjoint_workspace_bytes(nsteps, checkpoint_every)
+        ws = _device_bytes(nbytes + 256, self.fields[0].device, self.stream)
+        aligned = (ws.data_ptr() + 255) // 256 * 256
+        n_dk = len(self.params.dk) if self.params.dk is not None else 1
+        out = np.zeros(n_dk, dtype=np.float64)
+        arr = lambda ts: (ctypes.c_void_p * self.nf)(*[t.data_ptr() for t in ts])  # noqa: E731
+        _check(self._lib.brahms_adjoint(self._h, int(nsteps), int(checkpoint_every), arr(fields_in),
+                                        arr(grad_out), arr(grad_in),
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        ctypes.c_void_p(aligned)), "brahms_adjoint")
+        self.adjoint_workspace = ws
         return out
 
     def timing_enable(self, enable: bool = True):
@@ -436,6 +472,7 @@ class Batch:
 
     def __init__(self, problems, stream: Optional[torch.cuda.Stream] = None):
         self._lib = load_library()
+        self.stream = stream
         self.problems = list(problems)
         n = len(self.problems)
         shapes = (ctypes.c_int * (4 * n))()
@@ -510,15 +547,21 @@ class Batch:
                 ptrs.append(f.data_ptr())
         nbytes = self.workspace_bytes()
         if self.workspace is None or self.workspace.numel() < nbytes + 256:
-            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=fields[0][0].device)
+            self.workspace = _device_bytes(nbytes + 256, fields[0][0].device, self.stream)
         aligned = (self.workspace.data_ptr() + 255) // 256 * 256
         arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
         _check(self._lib.brahms_batch_bind(self._h, arr, ctypes.c_void_p(aligned)), "brahms_batch_bind")
         self.fields = [list(fs) for fs in fields]
         return self
 
-    def run(self):
-        _check(self._lib.brahms_batch_run(self._h), "brahms_batch_run")
+    def run(self, nsteps: Optional[Sequence[int]] = None):
+        """Propagate every problem from z = 0: nsteps[i] steps (each at most
+        the count given at creation), or the counts given at creation."""
+        if nsteps is None:
+            _check(self._lib.brahms_batch_run(self._h), "brahms_batch_run")
+        else:
+            arr = (ctypes.c_int * len(self.problems))(*[int(v) for v in nsteps])
+            _check(self._lib.brahms_batch_run_steps(self._h, arr), "brahms_batch_run_steps")
 
     def groups(self):
         n = ctypes.c_int()

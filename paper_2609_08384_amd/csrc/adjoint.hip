@@ -24,6 +24,7 @@
 
 #include "../../include/brahms.h"
 #include "adjoint.hpp"
+#include "launch.hpp"
 #include "plan.hpp"
 
 using namespace brahms;
@@ -48,27 +49,11 @@ struct AdjLayout {
 
 constexpr int kSetRows = kChunk / 2;   // table rows of the second set start here
 
-template <int N1, int N2>
-int blocks_of(int axis, const brahms_plan_s& p) {
-  using G = LineGeom<N1, N2>;
-  const long lines = axis == AX_X ? long(p.ny) * p.nt : long(p.nx) * p.ny;
-  return int((lines + G::LPB - 1) / G::LPB);
-}
-
 int pass_blocks(int axis, const brahms_plan_s& p) {
   const int n = axis == AX_X ? p.nx : p.nt;
-  switch (n) {
-    case 1: return blocks_of<1, 1>(axis, p);
-    case 2: return blocks_of<2, 1>(axis, p);
-    case 4: return blocks_of<4, 1>(axis, p);
-    case 8: return blocks_of<4, 2>(axis, p);
-    case 16: return blocks_of<4, 4>(axis, p);
-    case 32: return blocks_of<8, 4>(axis, p);
-    case 64: return blocks_of<8, 8>(axis, p);
-    case 96: return blocks_of<24, 4>(axis, p);
-    case 128: return blocks_of<16, 8>(axis, p);
-    default: return blocks_of<16, 16>(axis, p);
-  }
+  const long lines = axis == AX_X ? long(p.ny) * p.nt : long(p.nx) * p.ny;
+  const int lpb = lines_per_block(n);
+  return int((lines + lpb - 1) / lpb);
 }
 
 AdjLayout adj_layout(const brahms_plan_s& p, int nsteps, int every) {
@@ -101,53 +86,13 @@ float2* state_field(char* base, const AdjLayout& L, const brahms_plan_s& p, int 
   return reinterpret_cast<float2*>(base + (size_t(slot) * p.nf + j) * align_up(L.field_bytes));
 }
 
-template <int N1, int N2, int AX, int NF, int AT>
-void launch_adj(const brahms_plan_s& p, const AdjArgs& a) {
-  using G = LineGeom<N1, N2>;
-  const long lines = AX == AX_X ? long(p.ny) * p.nt : long(p.nx) * p.ny;
-  const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
-  AdjArgs b = a;
-  b.tile_mul = AX == AX_T ? brahms::detail::tile_multiplier(grid.x) : 1u;
-  if (lines % G::LPB == 0)
-    hipLaunchKernelGGL((adjoint_pass<N1, N2, AX, NF, AT, true>), grid, dim3(kBlock), 0, p.stream, b);
-  else
-    hipLaunchKernelGGL((adjoint_pass<N1, N2, AX, NF, AT, false>), grid, dim3(kBlock), 0, p.stream, b);
-}
-
-template <int N1, int N2>
-void launch_adj_axis(int axis, int at, const brahms_plan_s& p, const AdjArgs& a) {
-  if (axis == AX_X) {
-    if (p.nf == 3) {
-      if (at == VJP_FIRST) launch_adj<N1, N2, AX_X, 3, VJP_FIRST>(p, a);
-      else launch_adj<N1, N2, AX_X, 3, VJP_LAST>(p, a);
-    } else {
-      if (at == VJP_FIRST) launch_adj<N1, N2, AX_X, 2, VJP_FIRST>(p, a);
-      else launch_adj<N1, N2, AX_X, 2, VJP_LAST>(p, a);
-    }
-  } else {
-    if (p.nf == 3) {
-      if (at == VJP_FIRST) launch_adj<N1, N2, AX_T, 3, VJP_FIRST>(p, a);
-      else launch_adj<N1, N2, AX_T, 3, VJP_LAST>(p, a);
-    } else {
-      if (at == VJP_FIRST) launch_adj<N1, N2, AX_T, 2, VJP_FIRST>(p, a);
-      else launch_adj<N1, N2, AX_T, 2, VJP_LAST>(p, a);
-    }
-  }
-}
-
 hipError_t dispatch_adj(int axis, int at, const brahms_plan_s& p, const AdjArgs& a) {
   const int n = axis == AX_X ? p.nx : p.nt;
   switch (n) {
-    case 1: launch_adj_axis<1, 1>(axis, at, p, a); break;
-    case 2: launch_adj_axis<2, 1>(axis, at, p, a); break;
-    case 4: launch_adj_axis<4, 1>(axis, at, p, a); break;
-    case 8: launch_adj_axis<4, 2>(axis, at, p, a); break;
-    case 16: launch_adj_axis<4, 4>(axis, at, p, a); break;
-    case 32: launch_adj_axis<8, 4>(axis, at, p, a); break;
-    case 64: launch_adj_axis<8, 8>(axis, at, p, a); break;
-    case 96: launch_adj_axis<24, 4>(axis, at, p, a); break;
-    case 128: launch_adj_axis<16, 8>(axis, at, p, a); break;
-    case 256: launch_adj_axis<16, 16>(axis, at, p, a); break;
+#define BRAHMS_CASE_(N, N1, N2) \
+  case N: brahms::detail::launch_adj_axis<N1, N2>(axis, at, p, a); break;
+    BRAHMS_LENGTHS(BRAHMS_CASE_)
+#undef BRAHMS_CASE_
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -318,6 +263,41 @@ brahms_status brahms_adjoint_forward(brahms_plan plan, int nsteps, int checkpoin
   p.adj_last_recorded = true;
   p.adj_ready = true;
   return BRAHMS_OK;
+}
+
+brahms_status brahms_adjoint(brahms_plan plan, int nsteps, int checkpoint_every, const void* const* fields_in,
+                             const void* const* grad_out, void* const* grad_in, double* grad_dk,
+                             void* adj_workspace) {
+  if (brahms_status st = check_plan(plan)) return st;
+  brahms_plan_s& p = *plan;
+  if (!p.bound) return fail(BRAHMS_E_STATE, "brahms_adjoint before brahms_plan_bind");
+  if (fields_in == nullptr || grad_out == nullptr || grad_in == nullptr)
+    return fail(BRAHMS_E_INVALID_ARG, "fields_in, grad_out and grad_in must not be NULL");
+  for (int j = 0; j < p.nf; ++j)
+    if (fields_in[j] == nullptr || grad_out[j] == nullptr || grad_in[j] == nullptr)
+      return fail(BRAHMS_E_INVALID_ARG, "NULL field or cotangent pointer");
+  // the forward runs in the plan's bound fields, from fields_in
+  float2* dst[3] = {nullptr, nullptr, nullptr};
+  float2* src[3] = {nullptr, nullptr, nullptr};
+  bool copy = false;
+  for (int j = 0; j < p.nf; ++j) {
+    dst[j] = p.fields[j];
+    src[j] = static_cast<float2*>(const_cast<void*>(fields_in[j]));
+    copy = copy || dst[j] != src[j];
+  }
+  if (copy)
+    if (brahms_status st = copy_state(p, dst, src)) return st;
+  if (brahms_status st = brahms_adjoint_forward(plan, nsteps, checkpoint_every, adj_workspace)) return st;
+  // the reverse sweep works in place in grad_in, from grad_out
+  copy = false;
+  for (int j = 0; j < p.nf; ++j) {
+    dst[j] = static_cast<float2*>(grad_in[j]);
+    src[j] = static_cast<float2*>(const_cast<void*>(grad_out[j]));
+    copy = copy || dst[j] != src[j];
+  }
+  if (copy)
+    if (brahms_status st = copy_state(p, dst, src)) return st;
+  return brahms_adjoint_backward(plan, grad_in, grad_dk);
 }
 
 brahms_status brahms_adjoint_backward(brahms_plan plan, void* const* grad, double* grad_dk) {

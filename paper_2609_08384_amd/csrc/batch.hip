@@ -34,6 +34,7 @@
 
 #include "../../include/brahms.h"
 #include "kernels.hpp"
+#include "launch.hpp"
 #include "plan.hpp"
 
 using namespace brahms;
@@ -45,7 +46,8 @@ using brahms::detail::kTableRows;
 struct brahms_batch_s {
   int n = 0;
   std::vector<brahms_plan> plans;
-  std::vector<int> nsteps;
+  std::vector<int> nsteps;             // steps of the next run, per problem
+  std::vector<int> capacity;           // steps the layout and graph are built for
   hipStream_t caller = nullptr;        // the caller's stream: uploads and graph launches
   int device = -1;                     // device of the capture streams
   hipStream_t stream = nullptr;        // capture stream (from the pool)
@@ -180,7 +182,7 @@ void make_groups(brahms_batch_s& b) {
       g.nf = p0.nf;
       g.order = p0.order;
       g.max_steps = 0;
-      for (int m : g.members) g.max_steps = std::max(g.max_steps, b.nsteps[m]);
+      for (int m : g.members) g.max_steps = std::max(g.max_steps, b.capacity[m]);
       b.groups.push_back(g);
     }
   }
@@ -216,96 +218,21 @@ size_t table_arg_bytes(brahms_batch_s& b) {
   return off;
 }
 
-template <int N1, int N2, int AX, int NF, int NL>
-void launch_batched(bool full, dim3 grid, hipStream_t st, const PassArgs* d, long long step, int nf) {
-  if (full)
-    hipLaunchKernelGGL((axis_pass_batched<N1, N2, AX, NF, NL, true>), grid, dim3(kBlock), 0, st, d, step, nf);
-  else
-    hipLaunchKernelGGL((axis_pass_batched<N1, N2, AX, NF, NL, false>), grid, dim3(kBlock), 0, st, d, step, nf);
-}
-
-template <int N1, int N2, int AX, int NF>
-void launch_batched_nl_nf(int nl, bool full, dim3 grid, hipStream_t st, const PassArgs* d,
-                          long long step) {
-  if constexpr (!long_tau_kind(AX)) {
-    if (nl == (NL_AFTER | NL_FUSE)) {
-      launch_batched<N1, N2, AX, NF, NL_AFTER | NL_FUSE>(full, grid, st, d, step, NF);
-      return;
-    }
-  }
-  switch (nl) {
-    case NL_BEFORE: launch_batched<N1, N2, AX, NF, NL_BEFORE>(full, grid, st, d, step, NF); break;
-    case NL_AFTER: launch_batched<N1, N2, AX, NF, NL_AFTER>(full, grid, st, d, step, NF); break;
-    default: launch_batched<N1, N2, AX, NF, NL_BOTH>(full, grid, st, d, step, NF); break;
-  }
-}
-
-template <int N1, int N2, int AX>
-void launch_batched_nl(int nf, int nl, bool full, dim3 grid, hipStream_t st, const PassArgs* d,
-                       long long step) {
-  if (nf == 3) launch_batched_nl_nf<N1, N2, AX, 3>(nl, full, grid, st, d, step);
-  else launch_batched_nl_nf<N1, N2, AX, 2>(nl, full, grid, st, d, step);
-}
-
-template <int N1, int N2>
-void launch_group_pass(int axis, int nl, const brahms_batch_s::Group& g, hipStream_t st,
-                       const PassArgs* d, long long step) {
-  using G = LineGeom<N1, N2>;
-  const unsigned m = unsigned(g.members.size());
-  const int nx = g.axis_len[0], ny = g.axis_len[1], nt = g.axis_len[2];
-  if (axis == AX_X) {
-    const long lines = long(ny) * nt;
-    if (nl == NL_NONE) {
-      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(g.nf) * m);
-      launch_batched<N1, N2, AX_X, 1, NL_NONE>(lines % G::LPB == 0, grid, st, d, step, g.nf);
-    } else {
-      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), m);
-      launch_batched_nl<N1, N2, AX_X>(g.nf, nl, lines % G::LPB == 0, grid, st, d, step);
-    }
-  } else if (axis == AX_Y) {
-    const long lines = long(nx) * nt;
-    if (nl == NL_NONE) {
-      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(g.nf) * m);
-      launch_batched<N1, N2, AX_Y, 1, NL_NONE>(lines % G::LPB == 0, grid, st, d, step, g.nf);
-    } else {
-      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), m);
-      launch_batched_nl<N1, N2, AX_Y>(g.nf, nl, lines % G::LPB == 0, grid, st, d, step);
-    }
-  } else {
-    const long lines = long(nx) * ny;
-    if (nl == NL_NONE) {
-      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(g.nf) * m);
-      launch_batched<N1, N2, AX_T, 1, NL_NONE>(lines % G::LPB == 0, grid, st, d, step, g.nf);
-    } else {
-      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), m);
-      launch_batched_nl<N1, N2, AX_T>(g.nf, nl, lines % G::LPB == 0, grid, st, d, step);
-    }
-  }
-}
-
-// The three passes of a long tau axis (nt = A B) over a group.
-template <int N1, int N2, int AX>
-void launch_group_long(int nl, const brahms_batch_s::Group& g, hipStream_t st, const PassArgs* d,
-                       long long step) {
-  using G = LineGeom<N1, N2>;
-  const unsigned m = unsigned(g.members.size());
-  const long lines = long(g.axis_len[0]) * g.axis_len[1] * (g.axis_len[2] / G::N);
-  const bool full = lines % G::LPB == 0;
-  if constexpr (AX == AX_TAI) {
-    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), m);
-    launch_batched_nl<N1, N2, AX_TAI>(g.nf, nl, full, grid, st, d, step);
-  } else {
-    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(g.nf) * m);
-    launch_batched<N1, N2, AX, 1, NL_NONE>(full, grid, st, d, step, g.nf);
-  }
+brahms::detail::GroupGeom geom_of(const brahms_batch_s::Group& g) {
+  return brahms::detail::GroupGeom{unsigned(g.members.size()), g.axis_len[0], g.axis_len[1], g.axis_len[2],
+                                   g.nf};
 }
 
 template <int AX>
 void dispatch_group_long_len(int len, int nl, const brahms_batch_s::Group& g, hipStream_t st,
                              const PassArgs* d, long long step) {
-  if (len == 16) launch_group_long<4, 4, AX>(nl, g, st, d, step);
-  else if (len == 32) launch_group_long<8, 4, AX>(nl, g, st, d, step);
-  else launch_group_long<8, 8, AX>(nl, g, st, d, step);
+  switch (len) {
+#define BRAHMS_CASE_(N, N1, N2) \
+  case N: brahms::detail::launch_group_long<N1, N2, AX>(nl, geom_of(g), st, d, step); break;
+    BRAHMS_LONG_SUBLENGTHS(BRAHMS_CASE_)
+#undef BRAHMS_CASE_
+    default: break;
+  }
 }
 
 void dispatch_group_long(int axis, int nl, const brahms_batch_s::Group& g, hipStream_t st,
@@ -320,26 +247,11 @@ void dispatch_group_long(int axis, int nl, const brahms_batch_s::Group& g, hipSt
 void dispatch_group_pass(int len, int axis, int nl, const brahms_batch_s::Group& g, hipStream_t st,
                          const PassArgs* d, long long step) {
   switch (len) {
-    case 1: launch_group_pass<1, 1>(axis, nl, g, st, d, step); break;
-    case 2: launch_group_pass<2, 1>(axis, nl, g, st, d, step); break;
-    case 4: launch_group_pass<4, 1>(axis, nl, g, st, d, step); break;
-    case 8: launch_group_pass<4, 2>(axis, nl, g, st, d, step); break;
-    case 16: launch_group_pass<4, 4>(axis, nl, g, st, d, step); break;
-    case 32: launch_group_pass<8, 4>(axis, nl, g, st, d, step); break;
-    case 64: launch_group_pass<8, 8>(axis, nl, g, st, d, step); break;
-    case 96: launch_group_pass<24, 4>(axis, nl, g, st, d, step); break;
-    case 128: launch_group_pass<16, 8>(axis, nl, g, st, d, step); break;
-    default: launch_group_pass<16, 16>(axis, nl, g, st, d, step); break;
-  }
-}
-
-int lpb_of(int len) {
-  switch (len) {
-    case 1: case 2: case 4: return kBlock;
-    case 8: return kBlock / 2;
-    case 16: case 32: case 96: return kBlock / 4;
-    case 64: case 128: return kBlock / 8;
-    default: return kBlock / 16;
+#define BRAHMS_CASE_(N, N1, N2) \
+  case N: brahms::detail::launch_group_pass<N1, N2>(axis, nl, geom_of(g), st, d, step); break;
+    BRAHMS_LENGTHS(BRAHMS_CASE_)
+#undef BRAHMS_CASE_
+    default: break;
   }
 }
 
@@ -381,7 +293,7 @@ brahms_status upload_descriptors(brahms_batch_s& b) {
           a.tiles = 1;
           if (ax == AX_T) {
             const long lines = long(p.nx) * p.ny;
-            const int lpb = lpb_of(len);
+            const int lpb = lines_per_block(len);
             a.tiles = unsigned((lines + lpb - 1) / lpb);
             a.tile_mul = brahms::detail::tile_multiplier(a.tiles);
           }
@@ -569,6 +481,7 @@ brahms_status brahms_batch_create(int n, const int* shapes, const brahms_params*
     }
     b->plans.push_back(p);
     b->nsteps.push_back(nsteps[i]);
+    b->capacity.push_back(nsteps[i]);
   }
   if (!acquire_capture(*b)) {
     brahms_batch_destroy(b);
@@ -695,6 +608,25 @@ brahms_status brahms_batch_run(brahms_batch b) {
   HIP_TRY(hipGraphLaunch(b->exec, b->caller));
   for (int i = 0; i < b->n; ++i) b->plans[i]->step = b->nsteps[i];
   return BRAHMS_OK;
+}
+
+brahms_status brahms_batch_run_steps(brahms_batch b, const int* nsteps) {
+  if (brahms_status st = check_batch(b)) return st;
+  if (!b->bound) return fail(BRAHMS_E_STATE, "brahms_batch_run_steps before brahms_batch_bind");
+  if (nsteps == nullptr) return fail(BRAHMS_E_INVALID_ARG, "nsteps is NULL");
+  bool changed = false;
+  for (int i = 0; i < b->n; ++i) {
+    if (nsteps[i] < 0 || nsteps[i] > b->capacity[i])
+      return fail(BRAHMS_E_INVALID_ARG, "step counts must lie in 0 .. the counts given at create");
+    changed = changed || nsteps[i] != b->nsteps[i];
+  }
+  if (changed) {
+    // new per-problem counts in the descriptors (after any run still reading
+    // them: the upload waits on the caller's stream); the graph stays
+    b->nsteps.assign(nsteps, nsteps + b->n);
+    if (brahms_status st = upload_descriptors(*b)) return st;
+  }
+  return brahms_batch_run(b);
 }
 
 brahms_status brahms_batch_groups(brahms_batch b, int* ngroups, int* members) {

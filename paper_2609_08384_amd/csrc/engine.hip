@@ -22,6 +22,7 @@
 
 #include "../../include/brahms.h"
 #include "kernels.hpp"
+#include "launch.hpp"
 #include "plan.hpp"
 
 using namespace brahms;
@@ -54,159 +55,28 @@ using brahms::detail::check_plan;
 
 namespace {
 
-bool supported_length(int n) {
-  switch (n) {
-    case 1: case 2: case 4: case 8: case 16: case 32: case 64: case 96: case 128: case 256:
-      return true;
-    default:
-      return false;
-  }
-}
-
 // tau axes longer than one line transform: nt = A B, transformed in three
 // passes (b transforms, a transforms with the propagator, inverse b)
 bool supported_long_tau(int n) { return n == 512 || n == 1024 || n == 2048 || n == 4096; }
 
-}  // namespace
-
-namespace {
-
-// ---------------------------------------------------------------------------
-// kernel dispatch: each supported axis length maps to a (N1, N2) split with
-// N2 threads per line and N1 values per thread.
-// ---------------------------------------------------------------------------
-template <int N1, int N2, int AX, int NF, int NL>
-void launch_pass(bool full, dim3 grid, hipStream_t st, const PassArgs& a) {
-  if (full) hipLaunchKernelGGL((axis_pass<N1, N2, AX, NF, NL, true>), grid, dim3(kBlock), 0, st, a);
-  else hipLaunchKernelGGL((axis_pass<N1, N2, AX, NF, NL, false>), grid, dim3(kBlock), 0, st, a);
-}
-
-using brahms::detail::tile_multiplier;
-
-template <int N1, int N2, int AX, int NF>
-void launch_nl_nf(int nl, bool full, dim3 grid, hipStream_t st, const PassArgs& a) {
-  if constexpr (!long_tau_kind(AX)) {
-    if (nl == (NL_AFTER | NL_FUSE)) {
-      launch_pass<N1, N2, AX, NF, NL_AFTER | NL_FUSE>(full, grid, st, a);
-      return;
-    }
-  }
-  switch (nl) {
-    case NL_BEFORE: launch_pass<N1, N2, AX, NF, NL_BEFORE>(full, grid, st, a); break;
-    case NL_AFTER: launch_pass<N1, N2, AX, NF, NL_AFTER>(full, grid, st, a); break;
-    case NL_BEFORE | NL_MAP: launch_pass<N1, N2, AX, NF, NL_BEFORE | NL_MAP>(full, grid, st, a); break;
-    default: launch_pass<N1, N2, AX, NF, NL_AFTER | NL_MAP>(full, grid, st, a); break;
-  }
-}
-
-template <int N1, int N2, int AX>
-void launch_nl(int nf, int nl, bool full, dim3 grid, hipStream_t st, const PassArgs& a) {
-  if (nf == 3) launch_nl_nf<N1, N2, AX, 3>(nl, full, grid, st, a);
-  else launch_nl_nf<N1, N2, AX, 2>(nl, full, grid, st, a);
-}
-
-// Half-step modes without the transverse map: y passes that carry a
-// half-step (nt = 1) and the single tau pass of a plane wave (NL_BOTH).
-template <int N1, int N2, int AX, int NF>
-void launch_plain_nl_nf(int nl, bool full, dim3 grid, hipStream_t st, const PassArgs& a) {
-  switch (nl) {
-    case NL_BEFORE: launch_pass<N1, N2, AX, NF, NL_BEFORE>(full, grid, st, a); break;
-    case NL_AFTER: launch_pass<N1, N2, AX, NF, NL_AFTER>(full, grid, st, a); break;
-    case NL_AFTER | NL_FUSE: launch_pass<N1, N2, AX, NF, NL_AFTER | NL_FUSE>(full, grid, st, a); break;
-    default: launch_pass<N1, N2, AX, NF, NL_BOTH>(full, grid, st, a); break;
-  }
-}
-
-template <int N1, int N2, int AX>
-void launch_plain_nl(int nf, int nl, bool full, dim3 grid, hipStream_t st, const PassArgs& a) {
-  if (nf == 3) launch_plain_nl_nf<N1, N2, AX, 3>(nl, full, grid, st, a);
-  else launch_plain_nl_nf<N1, N2, AX, 2>(nl, full, grid, st, a);
-}
-
-// One pass along `axis`; nl says where the RK4 half-step goes.  Linear
-// passes (NL_NONE) take one field per block.
-template <int N1, int N2>
-hipError_t launch_axis(int axis, int nl, int nf, const brahms_plan_s& p, PassArgs a) {
-  using G = LineGeom<N1, N2>;
-  a.tile_mul = 1;
-  a.tiles = 1;
-  if (axis == AX_X) {
-    const long lines = long(p.ny) * p.nt;
-    if (nl == NL_NONE) {
-      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(nf));
-      launch_pass<N1, N2, AX_X, 1, NL_NONE>(lines % G::LPB == 0, grid, p.stream, a);
-    } else {
-      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
-      launch_nl<N1, N2, AX_X>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
-    }
-  } else if (axis == AX_Y) {
-    const long lines = long(p.nx) * p.nt;
-    if (nl == NL_NONE) {
-      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(nf));
-      launch_pass<N1, N2, AX_Y, 1, NL_NONE>(lines % G::LPB == 0, grid, p.stream, a);
-    } else {
-      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
-      launch_plain_nl<N1, N2, AX_Y>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
-    }
-  } else {
-    const long lines = long(p.nx) * p.ny;
-    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
-    a.tile_mul = tile_multiplier(grid.x);
-    a.tiles = grid.x;
-    if (nl == NL_NONE) {
-      // linear tau pass (orders 2 and 3): one field per block
-      const dim3 gridf(grid.x, 1, unsigned(nf));
-      launch_pass<N1, N2, AX_T, 1, NL_NONE>(lines % G::LPB == 0, gridf, p.stream, a);
-    } else if (nl == NL_BOTH) {
-      launch_plain_nl<N1, N2, AX_T>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
-    } else {
-      launch_nl<N1, N2, AX_T>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
-    }
-  }
-  return hipGetLastError();
-}
-
+// One pass along an axis of length n (a supported line length).
 hipError_t dispatch_axis(int n, int axis, int nl, int nf, const brahms_plan_s& p, PassArgs a) {
   switch (n) {
-    case 1: return launch_axis<1, 1>(axis, nl, nf, p, a);
-    case 2: return launch_axis<2, 1>(axis, nl, nf, p, a);
-    case 4: return launch_axis<4, 1>(axis, nl, nf, p, a);
-    case 8: return launch_axis<4, 2>(axis, nl, nf, p, a);
-    case 16: return launch_axis<4, 4>(axis, nl, nf, p, a);
-    case 32: return launch_axis<8, 4>(axis, nl, nf, p, a);
-    case 64: return launch_axis<8, 8>(axis, nl, nf, p, a);
-    case 96: return launch_axis<24, 4>(axis, nl, nf, p, a);
-    case 128: return launch_axis<16, 8>(axis, nl, nf, p, a);
-    case 256: return launch_axis<16, 16>(axis, nl, nf, p, a);
+#define BRAHMS_CASE_(N, N1, N2) \
+  case N: return brahms::detail::launch_axis<N1, N2>(axis, nl, nf, p, a);
+    BRAHMS_LENGTHS(BRAHMS_CASE_)
+#undef BRAHMS_CASE_
     default: return hipErrorInvalidValue;
   }
-}
-
-template <int N1, int N2, int AX>
-hipError_t launch_long(int nl, int nf, const brahms_plan_s& p, PassArgs a) {
-  using G = LineGeom<N1, N2>;
-  a.tile_mul = 1;
-  a.tiles = 1;
-  const long lines = long(p.nx) * p.ny * (p.nt / G::N);
-  const bool full = lines % G::LPB == 0;
-  if (AX == AX_TAI && nl != NL_NONE) {
-    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
-    launch_nl<N1, N2, AX_TAI>(nf, nl, full, grid, p.stream, a);
-  } else {
-    // linear passes (the inverse b pass too, when fused step pairs carry
-    // the RK4 step on x and y): one field per block
-    const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(nf));
-    launch_pass<N1, N2, AX, 1, NL_NONE>(full, grid, p.stream, a);
-  }
-  return hipGetLastError();
 }
 
 template <int AX>
 hipError_t dispatch_long_len(int len, int nl, int nf, const brahms_plan_s& p, const PassArgs& a) {
   switch (len) {
-    case 16: return launch_long<4, 4, AX>(nl, nf, p, a);
-    case 32: return launch_long<8, 4, AX>(nl, nf, p, a);
-    case 64: return launch_long<8, 8, AX>(nl, nf, p, a);
+#define BRAHMS_CASE_(N, N1, N2) \
+  case N: return brahms::detail::launch_long<N1, N2, AX>(nl, nf, p, a);
+    BRAHMS_LONG_SUBLENGTHS(BRAHMS_CASE_)
+#undef BRAHMS_CASE_
     default: return hipErrorInvalidValue;
   }
 }
@@ -722,11 +592,11 @@ brahms_status brahms_plan_create(int nx, int ny, int nt, int nfields, const brah
     return fail(BRAHMS_E_INVALID_ARG, "dk profile given with n_dk < 1");
   if (params->dk_map_scale != nullptr && (params->dk_map == nullptr || params->n_dk_map_scale < 1))
     return fail(BRAHMS_E_INVALID_ARG, "dk_map_scale needs dk_map and n_dk_map_scale >= 1");
-  if (!supported_length(nx) || !supported_length(ny) ||
-      !(supported_length(nt) || supported_long_tau(nt)))
+  if (!brahms::line_length(nx) || !brahms::line_length(ny) ||
+      !(brahms::line_length(nt) || supported_long_tau(nt)))
     return fail(BRAHMS_E_UNSUPPORTED,
-                "axis lengths must be one of 1, 2, 4, 8, 16, 32, 64, 96, 128, 256 "
-                "(tau also 512, 1024, 2048, 4096)");
+                "axis lengths must be 2^a or 3 * 2^a up to 256 (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, "
+                "64, 96, 128, 192, 256; tau also 512, 1024, 2048, 4096)");
   auto* p = new brahms_plan_s();
   p->nx = nx; p->ny = ny; p->nt = nt; p->nf = nfields;
   p->dz = params->dz;

@@ -1,0 +1,6 @@
+// Pass launchers of plans, batches and the adjoint for line lengths
+// 12x2 8x4 (N1 x N2; see launch.hpp and lengths.hpp).
+#include "launch_impl.hpp"
+
+BRAHMS_INSTANTIATE_LENGTH(12, 2)
+BRAHMS_INSTANTIATE_LENGTH(8, 4)

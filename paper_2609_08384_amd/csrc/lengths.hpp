@@ -1,0 +1,44 @@
+// Axis lengths of the line transforms and their register/lane splits.
+//
+// A line of length N = N1 N2 is transformed by N2 lanes holding N1 values
+// each (see line_fft in kernels.hpp): an N1-point register DFT per lane, one
+// exchange through LDS, N2-point register DFTs.  N2 divides N1 (the second
+// stage deals N1 / N2 groups to every lane) and kBlock = 256 (a block holds
+// 256 / N2 lines); N1 and N2 are products of 2s and 3s that divide 48 (the
+// angles of the register DFTs' constant twiddles).  These conditions admit
+// every length 2^a 3^b <= 256 with b <= 1; lengths with 3^2 or more, and
+// x or y axes above 256, have no split (BRAHMS_E_UNSUPPORTED).  A tau axis of
+// 512, 1024, 2048 or 4096 takes three passes of sub-lengths 16, 32 or 64
+// (a four-step transform, AX_TAF / AX_TB / AX_TAI in kernels.hpp).
+#pragma once
+
+// X(N, N1, N2) for every supported length of one line transform.
+#define BRAHMS_LENGTHS(X)                                                                     \
+  X(1, 1, 1) X(2, 2, 1) X(3, 3, 1) X(4, 4, 1) X(6, 6, 1) X(8, 4, 2) X(12, 6, 2) X(16, 4, 4)  \
+  X(24, 12, 2) X(32, 8, 4) X(48, 12, 4) X(64, 8, 8) X(96, 24, 4) X(128, 16, 8) X(192, 24, 8) \
+  X(256, 16, 16)
+
+// X(N, N1, N2) for the sub-transform lengths of a long tau axis.
+#define BRAHMS_LONG_SUBLENGTHS(X) X(16, 4, 4) X(32, 8, 4) X(64, 8, 8)
+
+namespace brahms {
+
+// Whether n is the length of one line transform.
+inline bool line_length(int n) {
+#define BRAHMS_CASE_(N, N1, N2) \
+  if (n == N) return true;
+  BRAHMS_LENGTHS(BRAHMS_CASE_)
+#undef BRAHMS_CASE_
+  return false;
+}
+
+// Lines per block of the transform of length n (256 / N2), or 0.
+inline int lines_per_block(int n) {
+#define BRAHMS_CASE_(N, N1, N2) \
+  if (n == N) return 256 / N2;
+  BRAHMS_LENGTHS(BRAHMS_CASE_)
+#undef BRAHMS_CASE_
+  return 0;
+}
+
+}  // namespace brahms

@@ -3,7 +3,9 @@
 its gradients with respect to the input fields and the dk profile, from the
 oracle's own adjoint (oracle/adjoint.py, reverse-mode through the FP64 loop).
 Stores J, the full dJ/ddk, dJ/dF_in at 4096 uniform and 4096 largest points,
-and the transverse-summed |dJ/dF_in|^2 per tau.
+the transverse-summed |dJ/dF_in|^2 per tau, its squared norm and a count
+sketch of the whole gradient (tests/sketch.py; SKETCH_BUCKETS buckets, seed
+SKETCH_SEED).
 Usage: python -m tests.golden.make_adjoint_golden [threads]
 """
 import os
@@ -21,7 +23,11 @@ if ROOT not in sys.path:
 from oracle import adjoint as oadj  # noqa: E402
 from paper_2609_08384_amd import inputs  # noqa: E402
 from tests.golden.make_golden import sample_points  # noqa: E402
+from tests.sketch import count_sketch  # noqa: E402
 from tests.util import oracle_problem  # noqa: E402
+
+SKETCH_BUCKETS = 16384
+SKETCH_SEED = 8000
 
 
 def main():
@@ -38,7 +44,9 @@ def main():
     top = torch.topk(gf.abs(), 4096).indices.sort().values
     np.savez_compressed(os.path.join(HERE, "shg_adjoint_grad.npz"), J=np.array(j), grad_dk=gdk.numpy(),
                         uniform_idx=uni, gF_uniform=gf[uni].numpy(), top_idx=top.numpy(),
-                        gF_top=gf[top].numpy(), gF_power=(g[0].abs() ** 2).sum(dim=(1, 2)).numpy())
+                        gF_top=gf[top].numpy(), gF_power=(g[0].abs() ** 2).sum(dim=(1, 2)).numpy(),
+                        gF_norm2=np.array(float((g[0].abs() ** 2).sum())),
+                        gF_sketch=count_sketch(g[0], SKETCH_BUCKETS, SKETCH_SEED).astype(np.complex64))
     print("wrote shg_adjoint_grad.npz", flush=True)
 
 

@@ -6,8 +6,13 @@ fields of a workload and stores, per field:
     4096 points of largest oracle amplitude,
   * the power trace P(tau) = sum_xy |A|^2 (the output quantity of Sec. 6),
   * the fluence map sum_tau |A|^2 summed over 4 x 4 transverse blocks,
-  * the energies and Manley-Rowe combinations.
-Usage: python -m tests.golden.make_golden <workload> [nsteps] [threads]
+  * the energies and Manley-Rowe combinations,
+  * a count sketch of the whole field (tests/sketch.py, SKETCH_BUCKETS
+    buckets, seed SKETCH_SEED + field index), from which the GPU tests
+    estimate the whole-field relative L2 error;
+and, at each step listed after --snap, the energies and the field sketches
+(keys s<step>_energies, s<step>_f<j>_sketch).
+Usage: python -m tests.golden.make_golden <workload> [nsteps] [threads] [--snap=n1,n2,...]
 """
 from __future__ import annotations
 
@@ -25,11 +30,20 @@ if ROOT not in sys.path:
 
 from oracle import ssfm  # noqa: E402
 from paper_2609_08384_amd import inputs  # noqa: E402
+from tests.sketch import count_sketch  # noqa: E402
 from tests.util import oracle_problem, to_torch  # noqa: E402
 
 WORKLOADS = {"sfg128": inputs.sfg128, "opg256": inputs.opg256, "shg_adjoint": inputs.shg_adjoint,
              "shg32": inputs.shg32, "shg_thermal": inputs.shg_thermal}
 NSAMPLE = 4096
+SKETCH_BUCKETS = 16384
+SKETCH_SEED = 7000
+
+
+def sketches(fields):
+    # stored in complex64: its rounding (6e-8 relative) is far below the tolerances
+    return {f"f{j}_sketch": count_sketch(a, SKETCH_BUCKETS, SKETCH_SEED + j).astype(np.complex64)
+            for j, a in enumerate(fields)}
 
 
 def sample_points(shape, seed=1234):
@@ -56,15 +70,22 @@ def summarize(fields, prob):
         out[f"f{j}_fluence"] = flu.reshape(ny // by, by, nx // bx, bx).sum(dim=(1, 3)).numpy()
     out["energies"] = np.array(ssfm.energies(fields, prob))
     out["manley_rowe"] = np.array(ssfm.manley_rowe(fields, prob))
+    out.update(sketches(fields))
     return out
 
 
 def main():
-    name = sys.argv[1]
+    args = [a for a in sys.argv[1:] if not a.startswith("--snap")]
+    snaps = set()
+    for a in sys.argv[1:]:
+        if a.startswith("--snap="):
+            snaps = {int(v) for v in a.split("=", 1)[1].split(",") if v}
+    name = args[0]
     wl = WORKLOADS[name]()
-    nsteps = int(sys.argv[2]) if len(sys.argv) > 2 else wl.nz
-    if len(sys.argv) > 3:
-        torch.set_num_threads(int(sys.argv[3]))
+    nsteps = int(args[1]) if len(args) > 1 else wl.nz
+    if len(args) > 2:
+        torch.set_num_threads(int(args[2]))
+    extra = {}
     prob = oracle_problem(wl)
     orc = ssfm.Oracle(prob)
     a = [to_torch(x) for x in wl.init]
@@ -72,11 +93,16 @@ def main():
     t0 = time.time()
     for n in range(nsteps):
         a = orc.step(a, n)
+        if n + 1 in snaps:
+            extra[f"s{n + 1}_energies"] = np.array(ssfm.energies(a, prob))
+            for k, v in sketches(a).items():
+                extra[f"s{n + 1}_{k}"] = v
         if n % 10 == 9 or n == nsteps - 1:
             print(f"{name}: step {n + 1}/{nsteps} {time.time() - t0:.0f}s", flush=True)
     res = summarize(a, prob)
     res["manley_rowe_in"] = mr0
     res["nsteps"] = np.array(nsteps)
+    res.update(extra)
     path = os.path.join(HERE, f"{name}_{nsteps}.npz")
     np.savez_compressed(path, **res)
     print("wrote", path, flush=True)

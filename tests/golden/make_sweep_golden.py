@@ -4,7 +4,10 @@ sweep (2 fields, grids 64^3 .. 128 x 128 x 256, 200-600 steps each).
 Runs only the FP64 oracle (oracle/ssfm.py) on each instance's complex64
 entrance fields and stores, per instance and field, the complex values at 512
 seeded uniformly random points and at the 512 points of largest oracle
-amplitude, the power trace P(tau) and the energies.
+amplitude, the power trace P(tau), the energies, and a count sketch of the
+whole field (tests/sketch.py; SKETCH_BUCKETS buckets, seed
+SKETCH_SEED + 16 i + j) from which the GPU test estimates the whole-field
+relative L2 error.
 
 The instances take hours of CPU time in total, so the work can be split over
 several processes: each call handles the instances i with i % parts == part
@@ -30,10 +33,13 @@ if ROOT not in sys.path:
 
 from oracle import ssfm  # noqa: E402
 from paper_2609_08384_amd import inputs  # noqa: E402
+from tests.sketch import count_sketch  # noqa: E402
 from tests.util import oracle_problem, to_torch  # noqa: E402
 
 COUNT = 64
 NSAMPLE = 512
+SKETCH_BUCKETS = 4096
+SKETCH_SEED = 9000
 OUT = os.path.join(HERE, "shg_sweep_64.npz")
 
 
@@ -56,6 +62,7 @@ def run_instance(i, wl):
         res[f"f{j}_top_idx"] = top.numpy()
         res[f"f{j}_top"] = flat[top].numpy()
         res[f"f{j}_power"] = (a.abs() ** 2).sum(dim=(1, 2)).numpy()
+        res[f"f{j}_sketch"] = count_sketch(a, SKETCH_BUCKETS, SKETCH_SEED + 16 * i + j).astype(np.complex64)
     return res
 
 

@@ -346,6 +346,21 @@ void scenario_reduced_dims() {
   }
 }
 
+// axis lengths 3 * 2^a in batches and plans
+void scenario_three_lengths() {
+  Rng r(61);
+  std::vector<Problem> ps;
+  const int spec[4][5] = {{24, 12, 6, 3, 9}, {24, 12, 6, 3, 5}, {192, 3, 4, 2, 7}, {6, 48, 12, 2, 11}};
+  for (auto& s : spec) ps.push_back(make_problem(r, s[0], s[1], s[2], s[3], s[4], false, r.uniform(-3, 3)));
+  for (int merge : {0, 1}) {
+    std::vector<int> orders;
+    for (size_t k = 0; k < ps.size(); ++k) orders.push_back(int(k % 4));
+    const BatchRun br = run_batch(ps, 0, &orders, nullptr, merge, merge);
+    compare_with_plans(ps, br, orders, merge, merge, "3 * 2^a batch");
+    std::printf("3 * 2^a lengths merge=%d: ok\n", merge);
+  }
+}
+
 // the autotuner's sequence on one batch: repeated schedule changes, binds and
 // runs before the final destroy
 void scenario_tuner_sequence() {
@@ -434,6 +449,7 @@ int main(int argc, char** argv) {
   else if (s == "reduced_dims") scenario_reduced_dims();
   else if (s == "tuner_sequence") scenario_tuner_sequence();
   else if (s == "plans") scenario_plans();
+  else if (s == "three_lengths") scenario_three_lengths();
   else {
     std::fprintf(stderr, "unknown scenario %s\n", s.c_str());
     return 2;

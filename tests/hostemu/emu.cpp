@@ -244,12 +244,14 @@ namespace emu {
 
 long long g_launches = 0;
 
-void launch(hipStream_t st, dim3 grid, dim3 block, const char* name, std::function<void()> body,
+void launch(hipStream_t st, dim3 grid, dim3 block, int site, std::function<void()> body,
             std::function<void(dim3)> check) {
+  const std::string name = "kernel launched at line " + std::to_string(site);
   emu_stream* s = S(st, "hipLaunchKernelGGL");
   if (grid.x == 0 || grid.y == 0 || grid.z == 0 || block.x * block.y * block.z == 0 ||
       block.x * block.y * block.z > 1024 || grid.y > 65536 || grid.z > 65536) {
-    std::fprintf(stderr, "EMU: invalid launch geometry of %s (%u %u %u)\n", name, grid.x, grid.y, grid.z);
+    std::fprintf(stderr, "EMU: invalid launch geometry of %s (%u %u %u)\n", name.c_str(), grid.x, grid.y,
+                 grid.z);
     g_last = hipErrorInvalidValue;
     return;
   }

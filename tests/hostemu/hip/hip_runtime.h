@@ -158,7 +158,10 @@ namespace emu {
 
 // Enqueue one kernel launch (run later, in stream order).  `check` runs with
 // the launch geometry when the launch executes, before the kernel body.
-void launch(hipStream_t s, dim3 grid, dim3 block, const char* name, std::function<void()> body,
+// `site` is the source line of the launch (a kernel name string would be one
+// literal repeated in many template instantiations, which ASan's global
+// registration mistakes for an ODR violation).
+void launch(hipStream_t s, dim3 grid, dim3 block, int site, std::function<void()> body,
             std::function<void(dim3)> check);
 
 // Range checks of the engine's pass and table launches (tests/hostemu/emu.cpp);
@@ -173,5 +176,5 @@ void check_args(dim3 grid, const brahms::TableArgs* const& targs);
 }  // namespace emu
 
 #define hipLaunchKernelGGL(K, G, B, SHMEM, ST, ...)                                     \
-  ::emu::launch((ST), dim3(G), dim3(B), #K, [=]() { K(__VA_ARGS__); },                  \
+  ::emu::launch((ST), dim3(G), dim3(B), __LINE__, [=]() { K(__VA_ARGS__); },            \
                 [=](dim3 grid_) { ::emu::check_args(grid_, __VA_ARGS__); })

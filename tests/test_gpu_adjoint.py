@@ -7,6 +7,7 @@ import torch
 from oracle import adjoint as oadj
 from oracle import ssfm
 from paper_2609_08384_amd import autograd, brahms, inputs
+from tests.sketch import count_sketch
 from tests.util import oracle_problem, rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -55,7 +56,7 @@ def _oracle_grads(wl):
 
 @pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("nf,shape,nz,every", [(2, (16, 16, 8), 12, 5), (3, (8, 16, 16), 9, 4),
-                                                (2, (32, 8, 16), 7, 7),
+                                                (2, (32, 8, 16), 7, 7), (3, (24, 12, 6), 8, 3),
                                                 # reduced dimensions: the forward leaves out the
                                                 # passes along length-1 axes, the reverse sweep not
                                                 (2, (32, 16, 1), 10, 4), (3, (1, 1, 64), 11, 5)])
@@ -117,6 +118,11 @@ def test_inverse_design_workload_vs_oracle(order):
     gf = x[0].grad.cpu().numpy().reshape(-1)
     assert rel_l2(gf[g["uniform_idx"]], g["gF_uniform"]) < 1e-4
     assert rel_l2(gf[g["top_idx"]], g["gF_top"]) < 1e-4
+    # the whole gradient: relative L2 estimated from a count sketch of every
+    # grid value (tests/sketch.py; seed 8000 as in make_adjoint_golden.py)
+    ref = g["gF_sketch"].astype(np.complex128)
+    est = float(np.linalg.norm(count_sketch(gf, ref.size, 8000) - ref) / np.sqrt(g["gF_norm2"]))
+    assert est < 1e-4, est
     power = (np.abs(x[0].grad.cpu().numpy().astype(np.complex128)) ** 2).sum(axis=(1, 2))
     assert rel_l2(power, g["gF_power"]) < 2e-4
 
@@ -143,6 +149,50 @@ def test_inverse_design_forward_fields_vs_oracle():
         torch.cuda.synchronize()
         for j, f in enumerate(fields):
             flat = f.cpu().numpy().reshape(-1)
+            # whole field, from the count sketch (seed 7000 + j, make_golden.py)
+            ref = g[f"f{j}_sketch"].astype(np.complex128)
+            est = float(np.linalg.norm(count_sketch(flat, ref.size, 7000 + j) - ref) / np.sqrt(g["energies"][j]))
+            assert est < 2e-5, (adjoint, j, est)
             assert rel_l2(flat[g["uniform_idx"]], g[f"f{j}_uniform"]) < 2e-5, (adjoint, j)
             assert rel_l2(flat[g[f"f{j}_top_idx"]], g[f"f{j}_top"]) < 2e-5, (adjoint, j)
         plan.destroy()
+
+
+@pytest.mark.parametrize("alias", [False, True])
+def test_one_call_adjoint_equals_split_calls(alias):
+    """brahms_adjoint (fields in, cotangent out -> cotangent in, dJ/ddk in
+    one call) gives the bits of brahms_adjoint_forward + _backward, with
+    separate or aliased buffers; the bound fields end at the forward output."""
+    wl = _case(3, (16, 8, 16), 11, seed=5)
+    params = brahms.params_from_workload(wl)
+    rng = np.random.default_rng(9)
+    gout = [torch.from_numpy((rng.standard_normal(a.shape) + 1j * rng.standard_normal(a.shape))
+                             .astype(np.complex64)).to(DEV) for a in wl.init]
+    # split calls
+    f1 = [torch.from_numpy(a).to(DEV) for a in wl.init]
+    p1 = brahms.Plan(wl.nx, wl.ny, wl.nt, wl.nf, params).bind(f1)
+    p1.adjoint_forward(wl.nz, 4)
+    g1 = [g.clone() for g in gout]
+    gdk1 = p1.adjoint_backward(g1)
+    torch.cuda.synchronize()
+    # one call
+    bound = [torch.zeros_like(f) for f in f1]
+    p2 = brahms.Plan(wl.nx, wl.ny, wl.nt, wl.nf, params).bind(bound)
+    fin = [torch.from_numpy(a).to(DEV) for a in wl.init]
+    if alias:
+        for b, a in zip(bound, fin):
+            b.copy_(a)
+        fin = bound
+        g2 = [g.clone() for g in gout]
+        gdk2 = p2.adjoint(wl.nz, 4, fin, g2, g2)
+    else:
+        g2 = [torch.zeros_like(g) for g in gout]
+        gdk2 = p2.adjoint(wl.nz, 4, fin, gout, g2)
+    torch.cuda.synchronize()
+    for a, b in zip(g1, g2):
+        assert torch.equal(a, b)
+    assert np.array_equal(gdk1, gdk2)
+    for a, b in zip(f1, bound):
+        assert torch.equal(a, b)
+    p1.destroy()
+    p2.destroy()

@@ -7,6 +7,7 @@ import torch
 
 from oracle import ssfm
 from paper_2609_08384_amd import brahms, inputs
+from tests.sketch import count_sketch
 from tests.util import oracle_problem, oracle_run, rel_l2, to_torch
 
 pytestmark = pytest.mark.gpu
@@ -65,6 +66,71 @@ def test_batch_equals_plain_runs_bitwise(group_max):
     batch.destroy()
 
 
+def test_batch_of_three_times_power_of_two_lengths():
+    """Axis lengths 3 * 2^a (3 .. 192) in one batch, three fields and two,
+    merged and literal: bitwise equal to the problems run alone, and within
+    the oracle tolerance."""
+    rng = np.random.default_rng(61)
+    wls = []
+    for (nx, ny, nt), nf, nz in [((24, 12, 6), 3, 9), ((24, 12, 6), 3, 5), ((192, 3, 4), 2, 7),
+                                 ((6, 48, 12), 2, 11)]:
+        fs = [inputs.FieldSpec(kappa=1.0 + 0.2 * j, diffraction=float(rng.uniform(0.5, 2.0)),
+                               tan_rho=float(rng.uniform(-0.5, 0.5)), delay=float(rng.uniform(-1, 1)),
+                               k2=float(rng.uniform(-2, 2))) for j in range(nf)]
+        wl = inputs.Workload("b3", nx, ny, nt, nf, nz, 1.0 / nz, fs, dk_const=float(rng.uniform(-3, 3)))
+        wl.init = inputs.random_fields(rng, nf, nx, ny, nt, scale=0.7, smooth=2.0)
+        wls.append(wl)
+    for merge in (0, 1):
+        probs = [(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls]
+        batch = brahms.Batch(probs)
+        batch.set_merge_halves(merge)
+        fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
+        batch.bind(fields)
+        batch.run()
+        torch.cuda.synchronize()
+        out = [[f.clone() for f in fs] for fs in fields]
+        batch.destroy()
+        for w, fs in zip(wls, out):
+            alone = brahms.run_workload(w, device=DEV, merge_halves=merge)
+            for a, b in zip(fs, alone):
+                assert torch.equal(a, b), (w.nx, w.ny, w.nt, merge)
+            for a, r in zip(fs, oracle_run(w, merge=bool(merge))):
+                assert rel_l2(a.cpu().numpy(), r.numpy()) < 1e-5, (w.nx, w.ny, w.nt, merge)
+
+
+@pytest.mark.parametrize("merge", [0, 1])
+def test_run_with_fewer_steps(merge):
+    """brahms_batch_run_steps: per-problem step counts below those given at
+    creation replay the same graph with new descriptors; each problem equals
+    the same problem propagated alone for its new count (with merged
+    half-steps its last step ends on its own second half-step), and counts
+    above those at creation are refused."""
+    wls = _problems(seed=14)
+    for w in wls:
+        w.dk = None
+    probs = [(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls]
+    batch = brahms.Batch(probs)
+    batch.set_merge_halves(merge)
+    fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
+    batch.bind(fields)
+    batch.run()
+    counts = [max(0, w.nz - 3 * k) for k, w in enumerate(wls)]
+    for fs, w in zip(fields, wls):
+        for f, a in zip(fs, w.init):
+            f.copy_(torch.from_numpy(a).to(DEV))
+    batch.run(counts)
+    torch.cuda.synchronize()
+    out = [[f.clone() for f in fs] for fs in fields]
+    with pytest.raises(brahms.BrahmsError) as ei:
+        batch.run([w.nz + 1 for w in wls])
+    assert ei.value.status == brahms.BRAHMS_E_INVALID_ARG
+    batch.destroy()
+    for w, fs, n in zip(wls, out, counts):
+        alone = brahms.run_workload(w, nsteps=n, device=DEV, merge_halves=merge)
+        for a, b in zip(fs, alone):
+            assert torch.equal(a, b), (w.nx, w.ny, w.nt, n)
+
+
 def test_batch_matches_oracle():
     wls = _problems(seed=12)
     probs = [(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls]
@@ -102,8 +168,8 @@ def test_sweep_instances_match_oracle():
 def test_whole_sweep_matches_oracle_and_single_runs():
     """All 64 problems of the seeded SHG sweep (the batched benchmark
     workload) in one autotuned batch: every problem within 2e-5 relative L2
-    of the oracle per field (estimated from the reference data's uniform
-    samples and energies; power traces within 4e-5), and
+    of the oracle per field over the whole field (estimated from a count
+    sketch of every grid value; power traces within 4e-5), and
     bitwise equal to the same problem propagated alone with the same pass
     order."""
     import os
@@ -126,17 +192,19 @@ def test_whole_sweep_matches_oracle_and_single_runs():
         assert list(g[key + "shape"]) == [w.nx, w.ny, w.nt] and int(g[key + "nz"]) == w.nz
         for j, f in enumerate(fs):
             flat = f.cpu().numpy().reshape(-1)
-            # whole-field relative L2: the squared error summed over the
-            # uniform samples, scaled to the grid, over the oracle's energy (a
-            # focused beam fills little of the window, so the samples' own
-            # relative error would measure only the beam's far tails)
-            idx = g[key + "uniform_idx"]
-            err2 = np.sum(np.abs(flat[idx].astype(np.complex128) - g[key + f"f{j}_uniform"]) ** 2)
-            est = np.sqrt(err2 * flat.size / idx.size / g[key + "energies"][j])
+            # whole-field relative L2 (the stated per-instance tolerance),
+            # estimated from a count sketch of every grid value
+            # (tests/sketch.py; seed 9000 + 16 i + j as in make_sweep_golden.py)
+            ref = g[key + f"f{j}_sketch"].astype(np.complex128)
+            est = float(np.linalg.norm(count_sketch(flat, ref.size, 9000 + 16 * i + j) - ref) /
+                        np.sqrt(g[key + "energies"][j]))
             assert est < 2e-5, (i, j, est)
-            # and, looser, the relative L2 at the points where the field is
-            # largest (for the most tightly focused beam, whose peak during
-            # the run is ~9 times its exit amplitude, these sit at 2e-5)
+            # the 512 points of largest amplitude: a subset, not the stated
+            # whole-field measure.  For the most tightly focused beams (peak
+            # amplitude during the run ~9x the exit one) rounding near the
+            # focus leaves these points at up to ~2e-5 while the whole field
+            # stays below it, so this looser check only guards against a
+            # wrong beam core.
             assert rel_l2(flat[g[key + f"f{j}_top_idx"]], g[key + f"f{j}_top"]) < 3e-5, (i, j)
             p = (np.abs(f.cpu().numpy().astype(np.complex128)) ** 2).sum(axis=(1, 2))
             assert rel_l2(p, g[key + f"f{j}_power"]) < 4e-5, (i, j)

@@ -23,12 +23,13 @@ import subprocess
 
 import pytest
 
+from paper_2609_08384_amd.build import SOURCES as LIB_SOURCES
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 EMU = os.path.join(ROOT, "tests", "hostemu")
 CSRC = os.path.join(ROOT, "paper_2609_08384_amd", "csrc")
-LIB_SOURCES = ["engine.hip", "batch.hip", "adjoint.hip", "diag.hip", "noalloc.hip"]
 SCENARIOS = ["plain_batches", "merged_batches", "long_tau_batches", "long_tau_fused", "three_field",
-             "reduced_dims", "tuner_sequence", "plans"]
+             "reduced_dims", "tuner_sequence", "plans", "three_lengths"]
 VARIANT_SCENARIOS = ["plain_batches", "merged_batches", "long_tau_batches", "long_tau_fused",
                      "three_field", "reduced_dims", "tuner_sequence"]
 
@@ -59,12 +60,13 @@ def _source_hash():
     files = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC))]
     files += [os.path.join(ROOT, "include", "brahms.h")]
     files += [os.path.join(EMU, f) for f in ("emu.cpp", "emu.hpp", "drive.cpp")]
-    files += [os.path.join(EMU, "hip", "hip_runtime.h"), os.path.abspath(__file__)]
+    files += [os.path.join(EMU, "hip", "hip_runtime.h")]
     for f in files:
         h.update(f.encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
     h.update(" ".join(_flags()).encode())
+    h.update(repr((_BRANCHES, _LONG_TAU_REFUSAL)).encode())
     return h.hexdigest()[:16]
 
 
@@ -93,8 +95,7 @@ def _build(out):
 
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(srcs), os.cpu_count() or 4)) as ex:
         objs = dict(zip([os.path.basename(s) for s in srcs], ex.map(compile_one, srcs)))
-    common = [objs[k] for k in ("emu.cpp", "drive.cpp", "engine.hip", "adjoint.hip", "diag.hip",
-                                "noalloc.hip")]
+    common = [objs[k] for k in ["emu.cpp", "drive.cpp"] + [s for s in LIB_SOURCES if s != "batch.hip"]]
     exes = {}
     for name, batch in (("drive", "batch.hip"), ("drive_variant", "batch_variant.hip")):
         exe = os.path.join(out, name)
