@@ -205,13 +205,24 @@ brahms_status brahms_plan_destroy(brahms_plan plan);
  *     three.  Calls run without it while merge_halves is suspended.
  *     BRAHMS_E_INVALID_ARG without merge_halves, BRAHMS_E_UNSUPPORTED for
  *     other step structures.
+ *   split (bits 1 = x, 2 = y, 4 = tau): a line of length N = N1 N2 is
+ *     transformed by N2 lanes of N1 values each (a register DFT, one exchange
+ *     through LDS, a second register DFT); lengths 8, 12, 16, 24, 32, 48 and
+ *     64 also have a second split with half the lanes per line (or one lane)
+ *     and so twice the lines per block: 8 = 8 x 1, 12 = 12 x 1, 16 = 8 x 2,
+ *     24 = 24 x 1, 32 = 16 x 2, 48 = 24 x 2, 64 = 16 x 4 (the first splits
+ *     are 4 x 2, 6 x 2, 4 x 4, 12 x 2, 8 x 4, 12 x 4, 8 x 8).  A set bit takes
+ *     the second split on that axis where its length has one (other axes,
+ *     the adjoint passes and long tau axes keep the first).  The result
+ *     agrees to rounding.  BRAHMS_E_INVALID_ARG outside 0 .. 7.
  * The autotuner in the Python package times the candidates per grid shape. */
 typedef struct {
   int pass_order;
   int graph;
   int merge_halves;
   int fuse_steps;
-  int reserved[4];
+  int split;        /* bit a (x = 1, y = 2, tau = 4): second register/lane split of that axis */
+  int reserved[3];
 } brahms_schedule;
 
 brahms_status brahms_plan_set_schedule(brahms_plan plan, const brahms_schedule* sched);
@@ -337,6 +348,23 @@ brahms_status brahms_adjoint(brahms_plan plan, int nsteps, int checkpoint_every,
  *   launch).  Needs merged half-steps (BRAHMS_E_INVALID_ARG otherwise);
  *   BRAHMS_E_UNSUPPORTED for a batch that holds a problem with a tau axis
  *   longer than 256.  Invalidates the binding.
+ * brahms_batch_set_splits: per-problem register/lane splits (n entries, the
+ *   schedule field split of plans: bits x = 1, y = 2, tau = 4), or NULL for
+ *   the first split everywhere; problems of one shape with different splits
+ *   go to different launch groups.  Invalidates the binding.  Errors:
+ *   BRAHMS_E_INVALID_ARG outside 0 .. 7.
+ * brahms_batch_set_streams: 1 (default) captures the run into one hipGraph
+ *   whose launch groups run one after the other (largest first); 2 .. 4
+ *   issues the run's launches directly on that many streams, the caller's
+ *   stream hip_stream and streams - 1 side streams of the batch, forked from
+ *   hip_stream and joined back into it with events: launch groups, largest
+ *   first, each go to the stream with the least work so far, so groups of
+ *   large and of small grids execute at the same time.  With largest_alone
+ *   = 1 the largest group instead runs after the others have finished, on
+ *   hip_stream (the smaller groups share the chip, the largest fills it
+ *   alone).  Same kernels and tables, bitwise the same result.  Errors:
+ *   BRAHMS_E_INVALID_ARG for streams outside 1 .. 4 or largest_alone
+ *   outside {0, 1}.
  * brahms_batch_set_group_limits: per-problem launch-group sizes (n entries,
  *   0 = from the cache budget) that replace group_max; a group takes the
  *   limit of its first problem, so give problems of one shape the same one.
@@ -364,6 +392,8 @@ brahms_status brahms_batch_create(int n, const int* shapes, const brahms_params*
                                   const int* nsteps, void* hip_stream, brahms_batch* out);
 brahms_status brahms_batch_set_schedule(brahms_batch batch, int group_max, const int* pass_order);
 brahms_status brahms_batch_set_group_limits(brahms_batch batch, const int* limits);
+brahms_status brahms_batch_set_streams(brahms_batch batch, int streams, int largest_alone);
+brahms_status brahms_batch_set_splits(brahms_batch batch, const int* splits);
 brahms_status brahms_batch_set_merge_halves(brahms_batch batch, int merge_halves);
 brahms_status brahms_batch_set_fuse_steps(brahms_batch batch, int fuse_steps);
 brahms_status brahms_batch_workspace_size(brahms_batch batch, size_t* bytes);

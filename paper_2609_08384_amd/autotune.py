@@ -43,7 +43,18 @@ def _arch(device) -> str:
 
 
 def _key(arch: str, nx: int, ny: int, nt: int, nf: int, merge: int) -> str:
-    return f"v4:{arch}:{nx}x{ny}x{nt}:nf{nf}:m{merge}"
+    return f"v5:{arch}:{nx}x{ny}x{nt}:nf{nf}:m{merge}"
+
+
+def split_masks(nx: int, ny: int, nt: int):
+    """Every choice of register/lane split (schedule field split) that
+    changes something for this shape: subsets of the axes whose length has a
+    second split (long tau axes keep theirs)."""
+    bits = [1 << a for a, n in enumerate((nx, ny, nt)) if n in brahms.ALT_SPLIT_LENGTHS]
+    masks = [0]
+    for b in bits:
+        masks += [m | b for m in masks]
+    return masks
 
 
 def can_merge(params: brahms.Params) -> bool:
@@ -125,6 +136,14 @@ def tune(nx: int, ny: int, nt: int, nf: int, params: brahms.Params, device="cuda
         g_ms, g = min(((t, c) for t, c in times if c["graph"]), key=lambda tc: tc[0])
         if g_ms < 0.98 * best_ms:
             best_ms, best = g_ms, g
+        # the register/lane splits of the axes that have two, on the best
+        # schedule so far (it picks lines per block against values per lane)
+        for mask in split_masks(nx, ny, nt)[1:]:
+            c = dict(best, split=mask)
+            t = measure(nx, ny, nt, nf, scratch, c, device)
+            times.append((t, c))
+            if t < best_ms:
+                best_ms, best = t, c
         _memo[key] = dict(best)
         disk = _load()
         disk[key] = {"schedule": dict(best), "ms_per_step": best_ms,
@@ -142,6 +161,9 @@ def apply(plan: brahms.Plan, device="cuda:0", merge_halves: bool = True) -> dict
 
 GROUP_CANDIDATES = (0, 1 << 30)   # cache-budget groups, or every same-shape problem at once
 LIMIT_CANDIDATES = (0, 1, 2, 4, 1 << 30)   # per-shape launch-group sizes
+# one captured graph, or launches issued on 2 or 4 streams (all groups at
+# once, or the largest group after the others)
+STREAM_CANDIDATES = ((1, 0), (2, 0), (4, 0), (3, 1), (4, 1))
 
 
 def _probe_time(batch: "brahms.Batch", fields, device) -> float:
@@ -160,16 +182,21 @@ def _probe_time(batch: "brahms.Batch", fields, device) -> float:
 
 def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
                merge_halves: bool = True) -> dict:
-    """Pick the pass orders and the launch-group sizes of a batch by timing
-    copies of it on scratch fields, with at most max_steps steps per problem:
+    """Pick the pass orders, the launch-group sizes and the launch mode of a
+    batch by timing copies of it on scratch fields, with at most max_steps
+    steps per problem:
+    * per grid shape, the register/lane splits that `tune` found fastest for
+      a plain solve;
     * per grid shape alone, the group sizes LIMIT_CANDIDATES (the fastest
       differs between shapes: small grids want many problems per launch,
-      large ones few, so that groups of different shapes overlap);
+      large ones few);
     * the whole batch with those per-shape sizes, and with the global sizes
       GROUP_CANDIDATES, each with the per-shape orders of `tune` (the fastest
-      for a plain solve) and with one order for every problem (concurrent
-      groups compete for the chip, so the best order alone need not be the
-      best order together).
+      for a plain solve) and with one order for every problem, each as one
+      captured graph (groups in sequence) and with its launches issued on
+      STREAM_CANDIDATES streams (groups of different shapes at the same
+      time, where concurrent groups compete for the chip, so the best order
+      or group size alone need not be the best together).
     Merged half-steps are taken when every problem allows them; fused step
     pairs are timed against three passes per step on the fastest choice.
     Applies the fastest choice to `batch`."""
@@ -179,8 +206,10 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
     # (batches holding a long tau problem do not fuse)
     fuse = int(merge and all(nt <= 256 for (_, _, nt, _, _, _) in problems) and
                any(can_fuse(nx, ny, nt) for (nx, ny, nt, _, _, _) in problems))
-    tuned = [tune(nx, ny, nt, nf, prm, device, merge_halves=bool(merge))["pass_order"]
+    sched = [tune(nx, ny, nt, nf, prm, device, merge_halves=bool(merge))
              for (nx, ny, nt, nf, prm, _) in problems]
+    tuned = [sc["pass_order"] for sc in sched]
+    splits = [sc.get("split", 0) for sc in sched]
     order_sets = {"per_shape": tuned, "all_0": [0] * n, "all_1": [1] * n}
     short = [(nx, ny, nt, nf, prm, min(ns, max_steps)) for (nx, ny, nt, nf, prm, ns) in problems]
     gen = torch.Generator(device="cpu").manual_seed(7)
@@ -196,6 +225,7 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
         sub = brahms.Batch([short[i] for i in idx])
         sub.set_merge_halves(merge)
         sub.set_fuse_steps(fuse)
+        sub.set_splits([splits[i] for i in idx])
         sub.set_schedule(0, [tuned[i] for i in idx])
         times = []
         for lim in LIMIT_CANDIDATES:
@@ -210,33 +240,41 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
     probe = brahms.Batch(short)
     probe.set_merge_halves(merge)
     probe.set_fuse_steps(fuse)
+    probe.set_splits(splits)
     candidates = []
-    probe.set_schedule(0, tuned)
-    probe.set_group_limits(limits)
-    candidates.append((_probe_time(probe, fields, device), "per_shape_limits", None, "per_shape"))
-    probe.set_group_limits(None)
-    for gm in GROUP_CANDIDATES:
-        for name, orders in order_sets.items():
-            probe.set_schedule(gm, orders)
-            candidates.append((_probe_time(probe, fields, device), f"group_max={gm}", gm, name))
-    best = min(candidates, key=lambda c: c[0])
-    _, label, gm, oname = best
-    if fuse:
-        # the same choice with three passes per step
-        probe.set_fuse_steps(0)
+
+    def configure(gm, oname):
         if gm is None:
             probe.set_schedule(0, order_sets[oname])
             probe.set_group_limits(limits)
         else:
             probe.set_group_limits(None)
             probe.set_schedule(gm, order_sets[oname])
+
+    for streams in STREAM_CANDIDATES:
+        probe.set_streams(*streams)
+        configure(None, "per_shape")
+        candidates.append((_probe_time(probe, fields, device), "per_shape_limits", None, "per_shape", streams))
+        for gm in GROUP_CANDIDATES:
+            for name in order_sets:
+                configure(gm, name)
+                candidates.append((_probe_time(probe, fields, device), f"group_max={gm}", gm, name, streams))
+    best = min(candidates, key=lambda c: c[0])
+    _, label, gm, oname, streams = best
+    if fuse:
+        # the same choice with three passes per step
+        probe.set_fuse_steps(0)
+        probe.set_streams(*streams)
+        configure(gm, oname)
         t3 = _probe_time(probe, fields, device)
-        candidates.append((t3, label + "/three_passes", gm, oname))
+        candidates.append((t3, label + "/three_passes", gm, oname, streams))
         if t3 < best[0]:
             fuse = 0
     probe.destroy()
     batch.set_merge_halves(merge)
     batch.set_fuse_steps(fuse)
+    batch.set_splits(splits)
+    batch.set_streams(*streams)
     if gm is None:
         batch.set_schedule(0, order_sets[oname])
         batch.set_group_limits(limits)
@@ -245,4 +283,8 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
         batch.set_schedule(gm, order_sets[oname])
     return {"choice": label, "group_max": gm, "group_limits": limits if gm is None else None,
             "pass_orders": order_sets[oname], "orders": oname, "merge_halves": merge, "fuse_steps": fuse,
-            "probe_ms": {f"{c[1]}/{c[3]}": c[0] for c in candidates}, "shape_probe_ms": shape_ms}
+            "splits": splits,
+            "streams": streams,
+            "probe_ms": {f"{c[1]}/{c[3]}/streams={c[4][0]}{'/largest_alone' if c[4][1] else ''}": c[0]
+                         for c in candidates},
+            "shape_probe_ms": shape_ms}

@@ -30,6 +30,8 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_UNSUPPORTED", 3: "E_DEVICE",
                 4: "E_NONFINITE", 5: "E_STATE"}
 
 SUPPORTED_LENGTHS = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256)
+# lengths with a second register/lane split (schedule field split)
+ALT_SPLIT_LENGTHS = (8, 12, 16, 24, 32, 48, 64)
 TIMING_KINDS = 4
 TIMING_NAMES = ("x_pass", "y_pass", "t_pass", "tables")
 
@@ -43,7 +45,7 @@ class BrahmsError(RuntimeError):
 class ScheduleC(ctypes.Structure):
     _fields_ = [("pass_order", ctypes.c_int), ("graph", ctypes.c_int),
                 ("merge_halves", ctypes.c_int), ("fuse_steps", ctypes.c_int),
-                ("reserved", ctypes.c_int * 4)]
+                ("split", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
 
 
 class FieldParamsC(ctypes.Structure):
@@ -95,6 +97,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                 ctypes.POINTER(vp)],
         "brahms_batch_set_schedule": [vp, i, ctypes.POINTER(i)],
         "brahms_batch_set_group_limits": [vp, ctypes.POINTER(i)],
+        "brahms_batch_set_streams": [vp, i, i],
+        "brahms_batch_set_splits": [vp, ctypes.POINTER(i)],
         "brahms_batch_set_merge_halves": [vp, i],
         "brahms_batch_set_fuse_steps": [vp, i],
         "brahms_batch_workspace_size": [vp, ctypes.POINTER(ctypes.c_size_t)],
@@ -286,15 +290,17 @@ class Plan:
         _check(self._lib.brahms_set_z(self._h, float(z)), "brahms_set_z")
 
     def set_schedule(self, pass_order: int, graph: int = 0, merge_halves: int = 0,
-                     fuse_steps: int = 0):
+                     fuse_steps: int = 0, split: int = 0):
         """Pass order 0-3, graph replay of 64-step chunks, merged RK4
-        half-steps within a call (constant dk, no transverse map), and fused
-        step pairs (with merged half-steps: two passes per step)."""
+        half-steps within a call (constant dk, no transverse map), fused
+        step pairs (with merged half-steps: two passes per step), and the
+        per-axis choice of register/lane split (bits x = 1, y = 2, tau = 4)."""
         sc = ScheduleC()
         sc.pass_order = int(pass_order)
         sc.graph = int(graph)
         sc.merge_halves = int(merge_halves)
         sc.fuse_steps = int(fuse_steps)
+        sc.split = int(split)
         _check(self._lib.brahms_plan_set_schedule(self._h, ctypes.byref(sc)),
                "brahms_plan_set_schedule")
 
@@ -303,7 +309,7 @@ class Plan:
         _check(self._lib.brahms_plan_get_schedule(self._h, ctypes.byref(sc)),
                "brahms_plan_get_schedule")
         return {"pass_order": sc.pass_order, "graph": sc.graph, "merge_halves": sc.merge_halves,
-                "fuse_steps": sc.fuse_steps}
+                "fuse_steps": sc.fuse_steps, "split": sc.split}
 
     # --- adjoint (reverse-mode gradient of the z-loop) ---
     def adjoint_workspace_bytes(self, nsteps: int, checkpoint_every: int) -> int:
@@ -448,14 +454,14 @@ class Plan:
 def run_workload(wl, nsteps: Optional[int] = None, device: str = "cuda:0",
                  stream: Optional[torch.cuda.Stream] = None,
                  pass_order: Optional[int] = None,
-                 merge_halves: int = 0, fuse_steps: int = 0) -> List[torch.Tensor]:
+                 merge_halves: int = 0, fuse_steps: int = 0, split: int = 0) -> List[torch.Tensor]:
     """Upload a seeded workload's entrance fields, propagate nsteps (default:
     all of them) and return the device fields."""
     nsteps = wl.nz if nsteps is None else nsteps
     fields = [torch.from_numpy(a).to(device) for a in wl.init]
     plan = Plan(wl.nx, wl.ny, wl.nt, wl.nf, params_from_workload(wl), stream=stream)
-    if pass_order is not None or merge_halves:
-        plan.set_schedule(pass_order or 0, 0, merge_halves, fuse_steps)
+    if pass_order is not None or merge_halves or split:
+        plan.set_schedule(pass_order or 0, 0, merge_halves, fuse_steps, split)
     plan.bind(fields)
     plan.step(nsteps)
     torch.cuda.synchronize()
@@ -527,6 +533,23 @@ class Batch:
         _check(self._lib.brahms_batch_set_group_limits(self._h, arr), "brahms_batch_set_group_limits")
         if self.fields is not None:
             self.bind(self.fields)
+
+    def set_splits(self, splits: Optional[Sequence[int]]):
+        """Per-problem register/lane splits (bits x = 1, y = 2, tau = 4), or None."""
+        arr = None
+        if splits is not None:
+            arr = (ctypes.c_int * len(self.problems))(*[int(v) for v in splits])
+        _check(self._lib.brahms_batch_set_splits(self._h, arr), "brahms_batch_set_splits")
+        if self.fields is not None:
+            self.bind(self.fields)
+
+    def set_streams(self, streams: int, largest_alone: int = 0):
+        """1: the run is one captured hipGraph (groups in sequence); 2-4:
+        its launches go directly to that many streams, so that launch groups
+        of different shapes execute at the same time (with largest_alone,
+        all but the largest group, which then runs alone)."""
+        _check(self._lib.brahms_batch_set_streams(self._h, int(streams), int(largest_alone)),
+               "brahms_batch_set_streams")
 
     def workspace_bytes(self) -> int:
         out = ctypes.c_size_t()

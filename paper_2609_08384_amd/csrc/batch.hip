@@ -58,12 +58,16 @@ struct brahms_batch_s {
   int group_max = 0;                   // 0: choose from the cache budget
   std::vector<int> group_limit;        // per problem, overrides group_max (empty: none)
   bool merge = false;                  // merged RK4 half-steps (constant dk only)
+  int streams = 1;                     // 1: one captured graph; 2..4: eager launches on that
+                                       // many streams (the caller's and side streams)
+  bool largest_alone = false;          // eager: the largest group after the others, alone
+  bool eager_pending = false;          // an eager run may still be running on side streams
   bool fuse = false;                   // fused step pairs (groups of three-pass steps)
   // launch groups and descriptor placement (rebuilt when the schedule changes)
   struct Group {
     std::vector<int> members;
     int axis_len[3];
-    int nf, order, max_steps;
+    int nf, order, split, max_steps;
     size_t desc_off;                   // [3 passes][kChunk slots][members] PassArgs
     size_t targs_off;                  // [chunks][members] TableArgs
   };
@@ -166,7 +170,7 @@ void make_groups(brahms_batch_s& b) {
     const brahms::detail::StepPasses sp = brahms::detail::step_passes(p, true);
     int code = sp.n;
     for (int k = 0; k < sp.n; ++k) code = code * 8 + sp.ax[k];
-    by_key[{p.nx, p.ny, p.nt, p.nf, p.order, code}].push_back(i);
+    by_key[{p.nx, p.ny, p.nt, p.nf, p.order * 8 + p.split, code}].push_back(i);
   }
   for (auto& kv : by_key) {
     const std::vector<int>& ids = kv.second;
@@ -181,6 +185,7 @@ void make_groups(brahms_batch_s& b) {
       g.axis_len[2] = p0.nt;
       g.nf = p0.nf;
       g.order = p0.order;
+      g.split = p0.split;
       g.max_steps = 0;
       for (int m : g.members) g.max_steps = std::max(g.max_steps, b.capacity[m]);
       b.groups.push_back(g);
@@ -246,6 +251,15 @@ void dispatch_group_long(int axis, int nl, const brahms_batch_s::Group& g, hipSt
 
 void dispatch_group_pass(int len, int axis, int nl, const brahms_batch_s::Group& g, hipStream_t st,
                          const PassArgs* d, long long step) {
+  if ((g.split >> axis) & 1) {
+    switch (len) {
+#define BRAHMS_CASE_(N, N1, N2) \
+  case N: brahms::detail::launch_group_pass<N1, N2>(axis, nl, geom_of(g), st, d, step); return;
+      BRAHMS_ALT_LENGTHS(BRAHMS_CASE_)
+#undef BRAHMS_CASE_
+      default: break;
+    }
+  }
   switch (len) {
 #define BRAHMS_CASE_(N, N1, N2) \
   case N: brahms::detail::launch_group_pass<N1, N2>(axis, nl, geom_of(g), st, d, step); break;
@@ -293,7 +307,7 @@ brahms_status upload_descriptors(brahms_batch_s& b) {
           a.tiles = 1;
           if (ax == AX_T) {
             const long lines = long(p.nx) * p.ny;
-            const int lpb = lines_per_block(len);
+            const int lpb = lines_per_block(len, ((p.split >> ax) & 1) != 0);
             a.tiles = unsigned((lines + lpb - 1) / lpb);
             a.tile_mul = brahms::detail::tile_multiplier(a.tiles);
           }
@@ -416,9 +430,55 @@ brahms_status enqueue_run(brahms_batch_s& b) {
   return BRAHMS_OK;
 }
 
+// The whole run issued directly (no graph) over b.streams streams: the
+// caller's stream and b.streams - 1 side streams, forked from and joined back
+// into the caller's stream; launch groups, largest first, each to the stream
+// with the least work so far.  The groups are independent, so large
+// bandwidth-bound groups and small latency-bound ones execute together.
+// With largest_alone the largest group runs after the others have joined,
+// on the caller's stream: groups that each leave much of the chip idle then
+// share it, and the largest group, which fills the chip, has it to itself.
+brahms_status run_eager(brahms_batch_s& b) {
+  std::vector<size_t> order(b.groups.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+  auto work = [&](size_t k) {
+    const auto& g = b.groups[k];
+    return double(g.axis_len[0]) * g.axis_len[1] * g.axis_len[2] * g.members.size() * g.max_steps;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) { return work(a) > work(c); });
+  std::vector<size_t> last;
+  if (b.largest_alone && order.size() > 1) {
+    last.push_back(order.front());
+    order.erase(order.begin());
+  }
+  const int ns = std::max(1, std::min<int>(b.streams, int(order.size())));
+  hipStream_t st[brahms_batch_s::kBranches + 1] = {b.caller};
+  for (int k = 1; k < ns; ++k) st[k] = b.side[k - 1];
+  if (ns > 1) {
+    HIP_TRY(hipEventRecord(b.fork, b.caller));
+    for (int k = 1; k < ns; ++k) HIP_TRY(hipStreamWaitEvent(st[k], b.fork, 0));
+  }
+  std::vector<double> load(size_t(ns), 0.0);
+  for (size_t k : order) {
+    const size_t s = size_t(std::min_element(load.begin(), load.end()) - load.begin());
+    load[s] += work(k);
+    if (brahms_status e = enqueue_group(b, b.groups[k], st[s])) return e;
+  }
+  for (int k = 1; k < ns; ++k) {
+    HIP_TRY(hipEventRecord(b.join[k - 1], st[k]));
+    HIP_TRY(hipStreamWaitEvent(b.caller, b.join[k - 1], 0));
+  }
+  for (size_t k : last)
+    if (brahms_status e = enqueue_group(b, b.groups[k], b.caller)) return e;
+  b.eager_pending = true;
+  return BRAHMS_OK;
+}
+
 void drop_graph(brahms_batch_s& b) {
-  // no launch of the graph may still run when it goes
-  if (b.exec) (void)hipStreamSynchronize(b.caller);
+  // no launch of the graph, and no eager run on the side streams, may still
+  // run when it goes (the caller's stream has joined the side streams)
+  if (b.exec || b.eager_pending) (void)hipStreamSynchronize(b.caller);
+  b.eager_pending = false;
   if (b.exec) (void)hipGraphExecDestroy(b.exec);
   if (b.graph) (void)hipGraphDestroy(b.graph);
   b.exec = nullptr;
@@ -539,6 +599,29 @@ brahms_status brahms_batch_set_fuse_steps(brahms_batch b, int fuse_steps) {
   return BRAHMS_OK;
 }
 
+brahms_status brahms_batch_set_streams(brahms_batch b, int streams, int largest_alone) {
+  if (brahms_status st = check_batch(b)) return st;
+  if (streams < 1 || streams > brahms_batch_s::kBranches)
+    return fail(BRAHMS_E_INVALID_ARG, "streams must be 1 .. 4");
+  if (largest_alone != 0 && largest_alone != 1) return fail(BRAHMS_E_INVALID_ARG, "largest_alone must be 0 or 1");
+  drop_graph(*b);
+  b->streams = streams;
+  b->largest_alone = largest_alone != 0;
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_batch_set_splits(brahms_batch b, const int* splits) {
+  if (brahms_status st = check_batch(b)) return st;
+  if (splits != nullptr)
+    for (int i = 0; i < b->n; ++i)
+      if (splits[i] < 0 || splits[i] > 7) return fail(BRAHMS_E_INVALID_ARG, "splits must be 0 .. 7");
+  for (int i = 0; i < b->n; ++i) b->plans[i]->split = splits == nullptr ? 0 : splits[i];
+  drop_graph(*b);
+  b->bound = false;
+  layout_batch(*b);
+  return BRAHMS_OK;
+}
+
 brahms_status brahms_batch_set_group_limits(brahms_batch b, const int* limits) {
   if (brahms_status st = check_batch(b)) return st;
   if (limits != nullptr)
@@ -581,6 +664,11 @@ brahms_status brahms_batch_bind(brahms_batch b, void* const* fields, void* works
 brahms_status brahms_batch_run(brahms_batch b) {
   if (brahms_status st = check_batch(b)) return st;
   if (!b->bound) return fail(BRAHMS_E_STATE, "brahms_batch_run before brahms_batch_bind");
+  if (b->streams > 1) {
+    if (brahms_status st = run_eager(*b)) return st;
+    for (int i = 0; i < b->n; ++i) b->plans[i]->step = b->nsteps[i];
+    return BRAHMS_OK;
+  }
   if (b->exec == nullptr) {
     HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     const brahms_status st = enqueue_run(*b);

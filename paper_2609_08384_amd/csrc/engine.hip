@@ -59,8 +59,18 @@ namespace {
 // passes (b transforms, a transforms with the propagator, inverse b)
 bool supported_long_tau(int n) { return n == 512 || n == 1024 || n == 2048 || n == 4096; }
 
-// One pass along an axis of length n (a supported line length).
-hipError_t dispatch_axis(int n, int axis, int nl, int nf, const brahms_plan_s& p, PassArgs a) {
+// One pass along an axis of length n (a supported line length), with the
+// second split of that length when alt is set and it has one.
+hipError_t dispatch_axis(int n, bool alt, int axis, int nl, int nf, const brahms_plan_s& p, PassArgs a) {
+  if (alt) {
+    switch (n) {
+#define BRAHMS_CASE_(N, N1, N2) \
+  case N: return brahms::detail::launch_axis<N1, N2>(axis, nl, nf, p, a);
+      BRAHMS_ALT_LENGTHS(BRAHMS_CASE_)
+#undef BRAHMS_CASE_
+      default: break;
+    }
+  }
   switch (n) {
 #define BRAHMS_CASE_(N, N1, N2) \
   case N: return brahms::detail::launch_axis<N1, N2>(axis, nl, nf, p, a);
@@ -302,7 +312,7 @@ brahms_status timed_dispatch(brahms_plan_s& p, int ax, int nlmode, const PassArg
     HIP_TRY(dispatch_long(ax, nlmode, p.nf, p, a));
   } else {
     const int n[3] = {p.nx, p.ny, p.nt};
-    HIP_TRY(dispatch_axis(n[ax], ax, nlmode, p.nf, p, a));
+    HIP_TRY(dispatch_axis(n[ax], ((p.split >> ax) & 1) != 0, ax, nlmode, p.nf, p, a));
   }
   if (timed)
     if (brahms_status st = timing_stop(p)) return st;
@@ -766,10 +776,13 @@ brahms_status brahms_plan_set_schedule(brahms_plan plan, const brahms_schedule* 
     return fail(BRAHMS_E_INVALID_ARG, "fuse_steps needs merge_halves");
   if (sched->fuse_steps && !detail::long_tau(*plan) && detail::step_passes(*plan, false).n != 3)
     return fail(BRAHMS_E_UNSUPPORTED, "fuse_steps needs an x and a y pass (not nx = ny = 1 with tau <= 256)");
+  if (sched->split < 0 || sched->split > 7) return fail(BRAHMS_E_INVALID_ARG, "split must be 0 .. 7");
   if (plan->order != sched->pass_order || plan->use_graph != (sched->graph != 0) ||
-      plan->merge != (sched->merge_halves != 0) || plan->fuse != (sched->fuse_steps != 0))
+      plan->merge != (sched->merge_halves != 0) || plan->fuse != (sched->fuse_steps != 0) ||
+      plan->split != sched->split)
     drop_chunk_graph(*plan);
   plan->order = sched->pass_order;
+  plan->split = sched->split;
   plan->use_graph = sched->graph != 0;
   plan->merge = sched->merge_halves != 0;
   plan->fuse = sched->fuse_steps != 0;
@@ -786,6 +799,7 @@ brahms_status brahms_plan_get_schedule(brahms_plan plan, brahms_schedule* sched)
   sched->graph = plan->use_graph ? 1 : 0;
   sched->merge_halves = plan->merge ? 1 : 0;
   sched->fuse_steps = plan->fuse ? 1 : 0;
+  sched->split = plan->split;
   return BRAHMS_OK;
 }
 

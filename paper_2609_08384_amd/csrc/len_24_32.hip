@@ -1,6 +1,9 @@
 // Pass launchers of plans, batches and the adjoint for line lengths
-// 12x2 8x4 (N1 x N2; see launch.hpp and lengths.hpp).
+// 12x2 8x4 (N1 x N2; see launch.hpp and lengths.hpp), and second splits.
 #include "launch_impl.hpp"
 
 BRAHMS_INSTANTIATE_LENGTH(12, 2)
 BRAHMS_INSTANTIATE_LENGTH(8, 4)
+// second splits (lengths.hpp: BRAHMS_ALT_LENGTHS)
+BRAHMS_INSTANTIATE_LENGTH(24, 1)
+BRAHMS_INSTANTIATE_LENGTH(16, 2)

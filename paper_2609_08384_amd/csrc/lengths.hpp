@@ -18,6 +18,13 @@
   X(24, 12, 2) X(32, 8, 4) X(48, 12, 4) X(64, 8, 8) X(96, 24, 4) X(128, 16, 8) X(192, 24, 8) \
   X(256, 16, 16)
 
+// X(N, N1, N2): a second split of some lengths, with twice as many lines per
+// block (N2 halved) or a whole line per lane.  Which split runs faster depends
+// on the grid (lines per launch against values per lane); a plan's schedule
+// field `split` picks it per axis and the autotuner times both.
+#define BRAHMS_ALT_LENGTHS(X) \
+  X(8, 8, 1) X(12, 12, 1) X(16, 8, 2) X(24, 24, 1) X(32, 16, 2) X(48, 24, 2) X(64, 16, 4)
+
 // X(N, N1, N2) for the sub-transform lengths of a long tau axis.
 #define BRAHMS_LONG_SUBLENGTHS(X) X(16, 4, 4) X(32, 8, 4) X(64, 8, 8)
 
@@ -32,8 +39,23 @@ inline bool line_length(int n) {
   return false;
 }
 
-// Lines per block of the transform of length n (256 / N2), or 0.
-inline int lines_per_block(int n) {
+// Whether length n has a second split.
+inline bool has_alt_split(int n) {
+#define BRAHMS_CASE_(N, N1, N2) \
+  if (n == N) return true;
+  BRAHMS_ALT_LENGTHS(BRAHMS_CASE_)
+#undef BRAHMS_CASE_
+  return false;
+}
+
+// Lines per block of the transform of length n (256 / N2) with its first
+// split, or with its second one when alt is set and it has one; 0 for an
+// unsupported length.
+inline int lines_per_block(int n, bool alt = false) {
+#define BRAHMS_CASE_(N, N1, N2) \
+  if (alt && n == N) return 256 / N2;
+  BRAHMS_ALT_LENGTHS(BRAHMS_CASE_)
+#undef BRAHMS_CASE_
 #define BRAHMS_CASE_(N, N1, N2) \
   if (n == N) return 256 / N2;
   BRAHMS_LENGTHS(BRAHMS_CASE_)

@@ -33,6 +33,9 @@ struct brahms_plan_s {
   // axis order so that step n's last transform, the RK4 step and step n+1's
   // first transform run as one pass
   bool fuse = false;
+  // schedule field split: bit a (x = 1, y = 2, tau = 4) runs that axis's line
+  // transforms with the second split of its length (lengths.hpp), if any
+  int split = 0;
   // hipGraph replay of whole 64-step chunks (schedule field `graph`)
   bool use_graph = false;
   hipGraph_t chunk_graph = nullptr;

@@ -137,7 +137,7 @@ struct BatchRun {
 // The sequence of the batch tests: create, schedule calls, bind, run, wait,
 // destroy, with the workspace and fields released after the destroy.
 BatchRun run_batch(std::vector<Problem>& ps, int group_max, const std::vector<int>* orders,
-                   const std::vector<int>* limits, int merge, int fuse, int runs = 1) {
+                   const std::vector<int>* limits, int merge, int fuse, int runs = 1, int streams = 1) {
   const int n = int(ps.size());
   std::vector<int> shapes, steps;
   std::vector<brahms_params> prm;
@@ -153,6 +153,7 @@ BatchRun run_batch(std::vector<Problem>& ps, int group_max, const std::vector<in
   if (limits) OK(brahms_batch_set_group_limits(b, limits->data()));
   if (merge) OK(brahms_batch_set_merge_halves(b, 1));
   if (fuse) OK(brahms_batch_set_fuse_steps(b, 1));
+  if (streams != 1) OK(brahms_batch_set_streams(b, streams > 0 ? streams : -streams, streams < 0));
   Fields f = upload(ps);
   size_t ws_bytes = 0;
   OK(brahms_batch_workspace_size(b, &ws_bytes));
@@ -346,6 +347,94 @@ void scenario_reduced_dims() {
   }
 }
 
+// the second register/lane splits: plans with every axis on its second split
+// and batches with per-problem splits
+void scenario_splits() {
+  Rng r(83);
+  std::vector<Problem> ps;
+  const int spec[4][5] = {{64, 16, 32, 2, 9}, {64, 16, 32, 2, 7}, {48, 24, 8, 3, 6}, {8, 12, 64, 3, 5}};
+  for (auto& s : spec) ps.push_back(make_problem(r, s[0], s[1], s[2], s[3], s[4], false, r.uniform(-3, 3)));
+  const std::vector<int> splits = {7, 1, 5, 6};
+  for (int merge : {0, 1}) {
+    const int n = int(ps.size());
+    std::vector<int> shapes, steps;
+    std::vector<brahms_params> prm;
+    for (Problem& p : ps) {
+      shapes.insert(shapes.end(), {p.nx, p.ny, p.nt, p.nf});
+      steps.push_back(p.nz);
+      prm.push_back(p.prm);
+    }
+    brahms_batch b = nullptr;
+    OK(brahms_batch_create(n, shapes.data(), prm.data(), steps.data(), nullptr, &b));
+    OK(brahms_batch_set_splits(b, splits.data()));
+    if (merge) {
+      OK(brahms_batch_set_merge_halves(b, 1));
+      OK(brahms_batch_set_fuse_steps(b, 1));
+    }
+    Fields f = upload(ps);
+    size_t ws_bytes = 0;
+    OK(brahms_batch_workspace_size(b, &ws_bytes));
+    void* ws = emu::device_alloc(ws_bytes);
+    emu::clear_regions();
+    emu::register_region(ws, ws_bytes, -1, "batch workspace");
+    for (size_t k = 0; k < f.ptr.size(); ++k) emu::register_region(f.ptr[k], f.bytes[k], -1, "field");
+    std::vector<void*> fp(f.ptr.begin(), f.ptr.end());
+    OK(brahms_batch_bind(b, fp.data(), ws));
+    OK(brahms_batch_run(b));
+    OK(hipDeviceSynchronize() == hipSuccess ? BRAHMS_OK : BRAHMS_E_DEVICE);
+    OK(brahms_batch_destroy(b));
+    size_t fi = 0;
+    for (int i = 0; i < n; ++i) {
+      std::vector<std::vector<float2>> got;
+      for (int j = 0; j < ps[i].nf; ++j, ++fi) got.emplace_back(f.ptr[fi], f.ptr[fi] + f.bytes[fi] / sizeof(float2));
+      // a plan with the same split
+      set_profile(ps[i]);
+      std::vector<Problem> one{ps[i]};
+      Fields g = upload(one);
+      brahms_plan plan = nullptr;
+      OK(brahms_plan_create(ps[i].nx, ps[i].ny, ps[i].nt, ps[i].nf, &ps[i].prm, nullptr, &plan));
+      brahms_schedule sc{};
+      sc.merge_halves = merge;
+      sc.fuse_steps = merge;
+      sc.split = splits[size_t(i)];
+      OK(brahms_plan_set_schedule(plan, &sc));
+      size_t pw = 0;
+      OK(brahms_plan_workspace_size(plan, &pw));
+      void* pws = emu::device_alloc(pw);
+      emu::clear_regions();
+      for (size_t k = 0; k < g.ptr.size(); ++k) emu::register_region(g.ptr[k], g.bytes[k], 0, "field");
+      emu::register_region(pws, pw, 0, "plan workspace");
+      std::vector<void*> gp(g.ptr.begin(), g.ptr.end());
+      OK(brahms_plan_bind(plan, gp.data(), pws));
+      OK(brahms_step(plan, ps[i].nz));
+      OK(hipDeviceSynchronize() == hipSuccess ? BRAHMS_OK : BRAHMS_E_DEVICE);
+      std::vector<std::vector<float2>> want;
+      for (size_t k = 0; k < g.ptr.size(); ++k) want.emplace_back(g.ptr[k], g.ptr[k] + g.bytes[k] / sizeof(float2));
+      expect_equal(got, want, "split batch problem " + std::to_string(i));
+      OK(brahms_plan_destroy(plan));
+      emu::device_free(pws);
+      release(g);
+    }
+    emu::device_free(ws);
+    release(f);
+    emu::clear_regions();
+    std::printf("splits merge=%d: ok\n", merge);
+  }
+}
+
+// launches issued on several streams instead of one captured graph
+void scenario_eager_streams() {
+  for (int streams : {2, 4, -3})   // negative: the largest group alone after the others
+    for (int merge : {0, 1}) {
+      auto ps = mixed_problems(19, false);
+      std::vector<int> orders;
+      for (size_t k = 0; k < ps.size(); ++k) orders.push_back(int((k + 2) % 4));
+      const BatchRun br = run_batch(ps, 1, &orders, nullptr, merge, merge, 2, streams);
+      compare_with_plans(ps, br, orders, merge, merge, "eager batch");
+      std::printf("eager streams=%d merge=%d: ok\n", streams, merge);
+    }
+}
+
 // axis lengths 3 * 2^a in batches and plans
 void scenario_three_lengths() {
   Rng r(61);
@@ -450,6 +539,8 @@ int main(int argc, char** argv) {
   else if (s == "tuner_sequence") scenario_tuner_sequence();
   else if (s == "plans") scenario_plans();
   else if (s == "three_lengths") scenario_three_lengths();
+  else if (s == "eager_streams") scenario_eager_streams();
+  else if (s == "splits") scenario_splits();
   else {
     std::fprintf(stderr, "unknown scenario %s\n", s.c_str());
     return 2;

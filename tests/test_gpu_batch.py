@@ -131,6 +131,76 @@ def test_run_with_fewer_steps(merge):
             assert torch.equal(a, b), (w.nx, w.ny, w.nt, n)
 
 
+@pytest.mark.parametrize("merge", [0, 1])
+def test_streams_mode_equals_graph(merge):
+    """Launches issued on 2 or 4 streams (launch groups of different shapes
+    at the same time) give the bits of the captured graph, over two runs and
+    a run with fewer steps."""
+    wls = _problems(seed=15)
+    for w in wls:
+        w.dk = None
+    probs = [(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls]
+    counts = [max(0, w.nz - 2 * k) for k, w in enumerate(wls)]
+    results = {}
+    for streams in (1, 2, 4, -3):        # -3: three streams, the largest group alone last
+        batch = brahms.Batch(probs)
+        batch.set_schedule(1)
+        batch.set_merge_halves(merge)
+        batch.set_fuse_steps(merge)
+        batch.set_streams(abs(streams), int(streams < 0))
+        fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
+        batch.bind(fields)
+        outs = []
+        for run in (None, None, counts):
+            for fs, w in zip(fields, wls):
+                for f, a in zip(fs, w.init):
+                    f.copy_(torch.from_numpy(a).to(DEV))
+            batch.run(run)
+            torch.cuda.synchronize()
+            outs.append([[f.clone() for f in fs] for fs in fields])
+        batch.destroy()
+        results[streams] = outs
+    for streams in (2, 4, -3):
+        for a_run, b_run in zip(results[1], results[streams]):
+            for fa, fb in zip(a_run, b_run):
+                for a, b in zip(fa, fb):
+                    assert torch.equal(a, b), streams
+
+
+def test_batch_with_second_splits():
+    """Per-problem register/lane splits in a batch: problems of one shape
+    with different splits go to different launch groups, and each is
+    bitwise equal to a plan with the same split."""
+    rng = np.random.default_rng(71)
+    wls = []
+    for (nx, ny, nt), nf, nz in [((64, 16, 32), 2, 9), ((64, 16, 32), 2, 7), ((48, 24, 8), 3, 6),
+                                 ((64, 16, 32), 2, 5)]:
+        fs = [inputs.FieldSpec(kappa=1.0 + 0.2 * j, diffraction=float(rng.uniform(0.5, 2.0)),
+                               tan_rho=float(rng.uniform(-0.5, 0.5)), delay=float(rng.uniform(-1, 1)),
+                               k2=float(rng.uniform(-2, 2))) for j in range(nf)]
+        wl = inputs.Workload("s", nx, ny, nt, nf, nz, 1.0 / nz, fs, dk_const=float(rng.uniform(-3, 3)))
+        wl.init = inputs.random_fields(rng, nf, nx, ny, nt, scale=0.7, smooth=3.0)
+        wls.append(wl)
+    splits = [7, 1, 5, 0]
+    batch = brahms.Batch([(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls])
+    batch.set_merge_halves(1)
+    batch.set_fuse_steps(1)
+    batch.set_splits(splits)
+    assert len(batch.groups()) == 4
+    fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
+    batch.bind(fields)
+    batch.run()
+    torch.cuda.synchronize()
+    out = [[f.clone() for f in fs] for fs in fields]
+    with pytest.raises(brahms.BrahmsError):
+        batch.set_splits([8, 0, 0, 0])
+    batch.destroy()
+    for w, fs, sp in zip(wls, out, splits):
+        alone = brahms.run_workload(w, device=DEV, merge_halves=1, fuse_steps=1, split=sp)
+        for a, b in zip(fs, alone):
+            assert torch.equal(a, b), (w.nx, w.ny, w.nt, sp)
+
+
 def test_batch_matches_oracle():
     wls = _problems(seed=12)
     probs = [(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls]
@@ -187,7 +257,7 @@ def test_whole_sweep_matches_oracle_and_single_runs():
     batch.run()
     torch.cuda.synchronize()
     batch.destroy()
-    for i, (w, fs, o) in enumerate(zip(wls, fields, tuned["pass_orders"])):
+    for i, (w, fs, o, sp) in enumerate(zip(wls, fields, tuned["pass_orders"], tuned["splits"])):
         key = f"i{i:02d}_"
         assert list(g[key + "shape"]) == [w.nx, w.ny, w.nt] and int(g[key + "nz"]) == w.nz
         for j, f in enumerate(fs):
@@ -209,7 +279,7 @@ def test_whole_sweep_matches_oracle_and_single_runs():
             p = (np.abs(f.cpu().numpy().astype(np.complex128)) ** 2).sum(axis=(1, 2))
             assert rel_l2(p, g[key + f"f{j}_power"]) < 4e-5, (i, j)
         alone = brahms.run_workload(w, device=DEV, pass_order=o, merge_halves=tuned["merge_halves"],
-                                    fuse_steps=tuned["fuse_steps"])
+                                    fuse_steps=tuned["fuse_steps"], split=sp)
         for a, b in zip(fs, alone):
             assert torch.equal(a, b), i
 

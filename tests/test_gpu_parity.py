@@ -127,6 +127,27 @@ def test_coupled_steps_random(nf, shape, order, merge):
         assert rel_l2(g[j], o[j]) < 5e-6, j
 
 
+@pytest.mark.parametrize("fuse", [0, 1])
+@pytest.mark.parametrize("shape", [(8, 12, 16), (24, 32, 48), (64, 16, 24), (48, 64, 8), (12, 8, 64)])
+def test_second_splits_match_oracle(shape, fuse):
+    """The second register/lane split of every length that has one
+    (schedule field split, all three axes), three fields, literal and fused
+    schedules, against the oracle; and it really is another kernel (the bits
+    differ from the first split's)."""
+    nx, ny, nt = shape
+    rng = np.random.default_rng(500 + sum(shape))
+    init = inputs.random_fields(rng, 3, nx, ny, nt, scale=0.7, smooth=min(nx, ny, nt) / 2.0)
+    wl = _wl(nx, ny, nt, 3, 9, 0.02, _all_terms(3, kappa=1.5), dk_const=2.3, init=init)
+    merge = fuse
+    out = brahms.run_workload(wl, device=DEV, pass_order=0, merge_halves=merge, fuse_steps=fuse, split=7)
+    g = [f.cpu().numpy() for f in out]
+    o = _oracle(wl, merge=merge)
+    for j in range(3):
+        assert rel_l2(g[j], o[j]) < 5e-6, j
+    first = _gpu(wl, pass_order=0, merge=merge, fuse=fuse)
+    assert any(not np.array_equal(a, b) for a, b in zip(g, first))
+
+
 @pytest.mark.parametrize("shape", [(32, 16, 8), (1, 1, 256), (256, 2, 1), (8, 96, 1), (96, 64, 2)])
 def test_merged_half_steps_differ_from_literal_by_truncation_only(shape):
     """Merged halves really run (the bits differ from the literal splitting)
