@@ -122,34 +122,50 @@ __device__ inline void rotate_products(float2* q, float2 w) {
 
 // MAP: w[0], w[1], w[2] are the transverse phase factors at z_a, z_a + h/2
 // and z_a + h (unused otherwise).
+//
+// The update sums stage values rather than increments: a1 = 3 b1, a2 = 3 b2 / 2
+// and a3 = 3 b2, so b1 Q(y) = (y2 - y) / 3, b2 Q(y2) = 2 (y3 - y) / 3 and
+// b2 Q(y3) = (y4 - y) / 3, and
+//   y' = y + (y2 + 2 y3 + y4 - 4 y) / 3 + b4 Q(y4).
+// Two operations per stage and field replace the complex multiply-add of
+// each increment.  The factor 1/3 (rounded to FP32) scales only the O(h)
+// bracket, so its rounding biases the nonlinear increment by ~3e-8 of itself
+// and never the field; the bracket's rounding errors are of the size of the
+// increment sums' (about one ulp of y per step) and independent from step to
+// step.
 template <int NF, bool MAP = false>
 __device__ inline void rk4_point(float2* y, const float2 (*co)[kNlCoef], const float2* w = nullptr) {
-  float2 q[NF], acc[NF], ys[NF];
+  constexpr float kThird = 1.0f / 3.0f;
+  float2 q[NF], s[NF], ys[NF];
   chi2_products<NF>(y, q);
   if constexpr (MAP) rotate_products<NF>(q, w[0]);
 #pragma unroll
   for (int j = 0; j < NF; ++j) {
-    acc[j] = cfma(y[j], co[j][3], q[j]);
-    ys[j] = cfma(y[j], co[j][0], q[j]);
+    ys[j] = cfma(y[j], co[j][0], q[j]);   // y2
+    s[j] = ys[j];
   }
   chi2_products<NF>(ys, q);
   if constexpr (MAP) rotate_products<NF>(q, w[1]);
 #pragma unroll
   for (int j = 0; j < NF; ++j) {
-    acc[j] = cfma(acc[j], co[j][4], q[j]);
-    ys[j] = cfma(y[j], co[j][1], q[j]);
+    ys[j] = cfma(y[j], co[j][1], q[j]);   // y3
+    s[j] = make_float2(fmaf(2.0f, ys[j].x, s[j].x), fmaf(2.0f, ys[j].y, s[j].y));
   }
   chi2_products<NF>(ys, q);
   if constexpr (MAP) rotate_products<NF>(q, w[1]);
 #pragma unroll
   for (int j = 0; j < NF; ++j) {
-    acc[j] = cfma(acc[j], co[j][4], q[j]);
-    ys[j] = cfma(y[j], co[j][2], q[j]);
+    ys[j] = cfma(y[j], co[j][2], q[j]);   // y4
+    s[j] = cadd(s[j], ys[j]);
   }
   chi2_products<NF>(ys, q);
   if constexpr (MAP) rotate_products<NF>(q, w[2]);
 #pragma unroll
-  for (int j = 0; j < NF; ++j) y[j] = cfma(acc[j], co[j][5], q[j]);
+  for (int j = 0; j < NF; ++j) {
+    const float2 d = make_float2(fmaf(-4.0f, y[j].x, s[j].x), fmaf(-4.0f, y[j].y, s[j].y));
+    const float2 u = make_float2(fmaf(kThird, d.x, y[j].x), fmaf(kThird, d.y, y[j].y));
+    y[j] = cfma(u, co[j][5], q[j]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -231,6 +247,34 @@ __device__ __forceinline__ void point_link(float2* y, float2 (&v)[NF][N1], int p
 #pragma unroll
   for (int j = 0; j < NF; ++j)
     asm volatile("" : "+v"(y[j].x), "+v"(y[j].y), "+v"(v[j][prev].x), "+v"(v[j][prev].y));
+}
+
+// The fields of a pass are read and written through buffer resources: the
+// field's base and byte size sit in scalar registers, a lane's slot e at the
+// lane's byte offset plus the uniform offset 8 e estep, which the scalar unit
+// forms, so the slots' addresses take no vector instructions (global
+// addressing takes a 64-bit add per slot).  The byte offsets fit 32 bits:
+// a field holds at most 2^28 values.  Accesses past the size read zero and
+// store nothing.
+constexpr int kRsrcWord3 = 0x00020000;   // raw, untyped 32-bit buffer
+
+__device__ inline __amdgpu_buffer_rsrc_t field_rsrc(const float2* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(base), short(0), int(bytes), kRsrcWord3);
+}
+
+template <bool NT>
+__device__ inline float2 load_slot(__amdgpu_buffer_rsrc_t r, unsigned lane_bytes, unsigned slot_bytes) {
+  const f32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, lane_bytes, slot_bytes, NT ? 2 : 0);
+  return make_float2(v.x, v.y);
+}
+
+template <bool NT>
+__device__ inline void store_slot(__amdgpu_buffer_rsrc_t r, unsigned lane_bytes, unsigned slot_bytes,
+                                  float2 v) {
+  f32x2 w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_amdgcn_raw_buffer_store_b64(w, r, lane_bytes, slot_bytes, NT ? 2 : 0);
 }
 
 template <bool NT>
@@ -425,12 +469,21 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
   float2* lbuf = (N2 > 1) ? lds + li * G::LSTRIDE : lds;
   const DftConsts K = *args.consts;
 
+  const unsigned field_bytes = unsigned(args.nx) * unsigned(args.ny) * unsigned(args.nt) * 8u;
+  const unsigned lane_bytes = idx0 * 8u;
+  const unsigned slot_bytes = estep * 8u;
+  __amdgpu_buffer_rsrc_t rin[NF], rout[NF];
+#pragma unroll
+  for (int j = 0; j < NF; ++j) {
+    rin[j] = field_rsrc(fin[j], field_bytes);
+    rout[j] = field_rsrc(fout[j], field_bytes);
+  }
   float2 v[NF][N1];
 #pragma unroll
   for (int j = 0; j < NF; ++j) {
 #pragma unroll
     for (int e = 0; e < N1; ++e)
-      v[j][e] = valid ? load_field<NT>(fin[j], idx0 + unsigned(e) * estep) : make_float2(0.f, 0.f);
+      v[j][e] = valid ? load_slot<NT>(rin[j], lane_bytes, unsigned(e) * slot_bytes) : make_float2(0.f, 0.f);
   }
   __syncthreads();  // s_tw, s_prop staged
 
@@ -483,7 +536,7 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
     if constexpr ((NLM & NL_AFTER) == 0) {
       if (valid) {
 #pragma unroll
-        for (int e = 0; e < N1; ++e) store_field<NT>(fout[j], idx0 + unsigned(e) * estep, v[j][e]);
+        for (int e = 0; e < N1; ++e) store_slot<NT>(rout[j], lane_bytes, unsigned(e) * slot_bytes, v[j][e]);
       }
     }
   }
@@ -534,7 +587,7 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
 #pragma unroll
       for (int j = 0; j < NF; ++j)
 #pragma unroll
-        for (int e = 0; e < N1; ++e) store_field<NT>(fout[j], idx0 + unsigned(e) * estep, v[j][e]);
+        for (int e = 0; e < N1; ++e) store_slot<NT>(rout[j], lane_bytes, unsigned(e) * slot_bytes, v[j][e]);
     }
   }
 }
