@@ -187,7 +187,21 @@ struct LineGeom {
   static constexpr int LDS_ELEMS = (N2 > 1) ? LPB * LSTRIDE : 1;
 };
 
-template <int N1, int N2, bool INV>
+// Synchronisation of a line's lanes around its LDS exchange: the block's
+// barrier, or, when every line lies within one wavefront (WAVE), only an
+// ordering fence (a wave's LDS instructions complete in issue order).
+template <bool WAVE>
+__device__ __forceinline__ void line_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <int N1, int N2, bool INV, bool WAVE = false>
 __device__ inline void line_fft(float2 (&v)[N1], int t, float2* lbuf, const float2* tw,
                                 const DftConsts& K) {
   using G = LineGeom<N1, N2>;
@@ -199,10 +213,10 @@ __device__ inline void line_fft(float2 (&v)[N1], int t, float2* lbuf, const floa
       if (INV) w.y = -w.y;
       v[k1] = cmul(v[k1], w);
     }
-    __syncthreads();  // earlier readers of this block's LDS are done
+    line_sync<WAVE>();  // earlier readers of this line's LDS row are done
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) lbuf[k1 * G::ROW + t] = v[k1];
-    __syncthreads();
+    line_sync<WAVE>();
     constexpr int R = N1 / N2;
 #pragma unroll
     for (int a = 0; a < R; ++a) {
@@ -336,6 +350,8 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
   constexpr bool NT = (AX == AX_X) ? bool(BRAHMS_NT_X) : bool(BRAHMS_NT_YT);
   constexpr bool LONG = long_tau_kind(AX);
   constexpr bool FUSE = (NL & NL_FUSE) != 0;   // and the next step's transform
+  // x lines: a line's N2 lanes are consecutive threads, within one wavefront
+  constexpr bool WL = AX == AX_X && N2 <= 64 && 64 % N2 == 0;
   static_assert(!(MAP && (NLM == NL_BOTH || AX == AX_Y)),
                 "the transverse map runs only with a half-step per pass on x or tau");
   static_assert(!FUSE || (NLM == NL_AFTER && !MAP && !LONG),
@@ -510,7 +526,7 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
   for (int j = 0; j < NF; ++j) {
     if constexpr (AX == AX_TAF) {
       // B-point transform, then exp(-2 pi i a k_b / nt) on output k_b
-      line_fft<N1, N2, false>(v[j], t, lbuf, s_tw, K);
+      line_fft<N1, N2, false, WL>(v[j], t, lbuf, s_tw, K);
 #pragma unroll
       for (int e = 0; e < N1; ++e)
         v[j][e] = cmul(v[j][e], s_long[(lidx * unsigned(t + N2 * e)) & unsigned(args.nt - 1)]);
@@ -519,19 +535,19 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
 #pragma unroll
       for (int e = 0; e < N1; ++e)
         v[j][e] = cmulc(v[j][e], s_long[(lidx * unsigned(t + N2 * e)) & unsigned(args.nt - 1)]);
-      line_fft<N1, N2, true>(v[j], t, lbuf, s_tw, K);
+      line_fft<N1, N2, true, WL>(v[j], t, lbuf, s_tw, K);
     } else if constexpr (AX == AX_TB) {
       // A-point transform over a gives frequency k = k_b + B k_a in slot k_a
-      line_fft<N1, N2, false>(v[j], t, lbuf, s_tw, K);
+      line_fft<N1, N2, false, WL>(v[j], t, lbuf, s_tw, K);
       const unsigned nb = unsigned(args.nt) / unsigned(N);
 #pragma unroll
       for (int e = 0; e < N1; ++e) v[j][e] = cmul(v[j][e], s_long[lidx + nb * unsigned(t + N2 * e)]);
-      line_fft<N1, N2, true>(v[j], t, lbuf, s_tw, K);
+      line_fft<N1, N2, true, WL>(v[j], t, lbuf, s_tw, K);
     } else {
-      line_fft<N1, N2, false>(v[j], t, lbuf, s_tw, K);
+      line_fft<N1, N2, false, WL>(v[j], t, lbuf, s_tw, K);
 #pragma unroll
       for (int e = 0; e < N1; ++e) v[j][e] = cmul(v[j][e], s_prop[j * N + t + N2 * e]);
-      line_fft<N1, N2, true>(v[j], t, lbuf, s_tw, K);
+      line_fft<N1, N2, true, WL>(v[j], t, lbuf, s_tw, K);
     }
     if constexpr ((NLM & NL_AFTER) == 0) {
       if (valid) {
@@ -577,10 +593,10 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
       const DftConsts K2 = *args.consts2;
 #pragma unroll
       for (int j = 0; j < NF; ++j) {
-        line_fft<N1, N2, false>(v[j], t, lbuf, s_tw2, K2);
+        line_fft<N1, N2, false, WL>(v[j], t, lbuf, s_tw2, K2);
 #pragma unroll
         for (int e = 0; e < N1; ++e) v[j][e] = cmul(v[j][e], s_prop2[j * N + t + N2 * e]);
-        line_fft<N1, N2, true>(v[j], t, lbuf, s_tw2, K2);
+        line_fft<N1, N2, true, WL>(v[j], t, lbuf, s_tw2, K2);
       }
     }
     if (valid) {
@@ -738,7 +754,7 @@ __device__ __forceinline__ void step_tables_body(const TableArgs& a, long gid) {
                            0.86602540378443864676, 0.96592582628906828675, 0.25881904510252076235};
       float* out = reinterpret_cast<float*>(row + (a.nf + 1) * per_field);
       for (int k = 0; k < 6; ++k) out[k] = stochastic_round(v[k], entry_bits(n, 0x40000000u + k));
-      out[6] = 0.f;
+      out[6] = stochastic_round(0.41421356237309504880, entry_bits(n, 0x40000006u));   // tan(pi/8)
       out[7] = 0.f;
       return;
     }

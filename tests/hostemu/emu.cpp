@@ -32,6 +32,11 @@ namespace emu {
 
 using emu::die;
 
+[[noreturn]] void emu_buffer_fault(int op, unsigned long offset, unsigned bytes) {
+  die(std::string(op == 0 ? "buffer load" : "buffer store") + " at byte " + std::to_string(offset) +
+      " of a " + std::to_string(bytes) + "-byte buffer");
+}
+
 // ---------------------------------------------------------------------------
 // handles: never freed, only marked dead, so that any later use is reported
 // ---------------------------------------------------------------------------

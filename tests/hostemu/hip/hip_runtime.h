@@ -73,6 +73,41 @@ inline int __float_as_int(float f) {
 }
 #define __builtin_amdgcn_readfirstlane(x) (x)
 #define __builtin_amdgcn_sched_barrier(x) ((void)0)
+// a wavefront-scope exchange point: every thread of the block reaches it
+// together here, so the block barrier (which switches fibers) stands in
+#define __builtin_amdgcn_fence(order, scope) ((void)0)
+#define __builtin_amdgcn_wave_barrier() __syncthreads()
+
+// Buffer resources (raw, untyped): a base and a size in bytes.  The engine
+// never relies on the hardware's out-of-range handling, so an access that
+// does not lie wholly inside [base, base + size) stops the run.
+struct emu_buffer_rsrc {
+  char* base;
+  unsigned bytes;
+};
+typedef float emu_f32x2 __attribute__((ext_vector_type(2)));
+// (op 0: load, 1: store; an int rather than a string literal, whose copies in
+// every translation unit ASan would report as an ODR violation)
+[[noreturn]] void emu_buffer_fault(int op, unsigned long offset, unsigned bytes);
+inline emu_buffer_rsrc emu_make_buffer_rsrc(const void* base, short, int num_records, int) {
+  return emu_buffer_rsrc{static_cast<char*>(const_cast<void*>(base)), unsigned(num_records)};
+}
+inline emu_f32x2 emu_raw_buffer_load_b64(emu_buffer_rsrc r, unsigned voffset, unsigned soffset, int) {
+  const unsigned long off = (unsigned long)voffset + soffset;
+  if (off + 8 > r.bytes) emu_buffer_fault(0, off, r.bytes);
+  emu_f32x2 v;
+  memcpy(&v, r.base + off, 8);
+  return v;
+}
+inline void emu_raw_buffer_store_b64(emu_f32x2 v, emu_buffer_rsrc r, unsigned voffset, unsigned soffset, int) {
+  const unsigned long off = (unsigned long)voffset + soffset;
+  if (off + 8 > r.bytes) emu_buffer_fault(1, off, r.bytes);
+  memcpy(r.base + off, &v, 8);
+}
+#define __amdgpu_buffer_rsrc_t emu_buffer_rsrc
+#define __builtin_amdgcn_make_buffer_rsrc emu_make_buffer_rsrc
+#define __builtin_amdgcn_raw_buffer_load_b64 emu_raw_buffer_load_b64
+#define __builtin_amdgcn_raw_buffer_store_b64 emu_raw_buffer_store_b64
 
 inline int atomicOr(int* p, int v) {
   const int old = *p;

@@ -39,17 +39,22 @@ def test_tuner_takes_the_fastest_order_and_caches(fake_tuner, tmp_path):
     best = autotune.tune(32, 32, 32, 2, _params())
     # the graph is not 2 % faster than the best launch-by-launch order
     assert best == {"pass_order": 1, "graph": 0, "merge_halves": 1, "fuse_steps": 0}
-    # constant dk: merged half-steps, with and without fused step pairs
-    assert len(calls) == 2 * len(autotune.CANDIDATES)
+    # constant dk: merged half-steps, with and without fused step pairs; a
+    # warm-up run, then every candidate in each timing round, then the
+    # register/lane splits of the three axes (length 32 has a second one)
+    n_split = len(autotune.split_masks(32, 32, 32)) - 1
+    assert n_split == 7
+    n_calls = 1 + autotune.ROUNDS * (2 * len(autotune.CANDIDATES) + n_split)
+    assert len(calls) == n_calls
     assert all(c["merge_halves"] == 1 for c in calls)
     assert {c["fuse_steps"] for c in calls} == {0, 1}
     with open(os.path.join(str(tmp_path), "schedules.json")) as fh:
         disk = json.load(fh)
     (key, entry), = disk.items()
-    assert key == "v4:gfx950:32x32x32:nf2:m1" and entry["schedule"] == best
+    assert key == "v7:gfx950:32x32x32:nf2:m1" and entry["schedule"] == best
     autotune._memo.clear()
     assert autotune.tune(32, 32, 32, 2, _params()) == best     # from the disk cache
-    assert len(calls) == 2 * len(autotune.CANDIDATES)
+    assert len(calls) == n_calls
 
 
 def test_tuner_takes_the_graph_when_clearly_faster(fake_tuner):
