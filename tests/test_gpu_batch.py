@@ -257,6 +257,7 @@ def test_whole_sweep_matches_oracle_and_single_runs():
     batch.run()
     torch.cuda.synchronize()
     batch.destroy()
+    worst = (0.0, None)
     for i, (w, fs, o, sp) in enumerate(zip(wls, fields, tuned["pass_orders"], tuned["splits"])):
         key = f"i{i:02d}_"
         assert list(g[key + "shape"]) == [w.nx, w.ny, w.nt] and int(g[key + "nz"]) == w.nz
@@ -269,6 +270,7 @@ def test_whole_sweep_matches_oracle_and_single_runs():
             est = float(np.linalg.norm(count_sketch(flat, ref.size, 9000 + 16 * i + j) - ref) /
                         np.sqrt(g[key + "energies"][j]))
             assert est < 2e-5, (i, j, est)
+            worst = max(worst, (est, (i, j)))
             # the 512 points of largest amplitude: a subset, not the stated
             # whole-field measure.  For the most tightly focused beams (peak
             # amplitude during the run ~9x the exit one) rounding near the
@@ -282,6 +284,7 @@ def test_whole_sweep_matches_oracle_and_single_runs():
                                     fuse_steps=tuned["fuse_steps"], split=sp)
         for a, b in zip(fs, alone):
             assert torch.equal(a, b), i
+    print(f"worst whole-field relative L2 (sketch estimate) {worst[0]:.3g} at (problem, field) {worst[1]}")
 
 
 @pytest.mark.skip(reason="a run of this test ([0-0]) ended in a host segfault inside the next "
