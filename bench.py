@@ -275,8 +275,10 @@ def paper_grids(dev, steps=200):
 def batch_ratio(dev):
     """Seeded SHG sweep (64 problems over 64^3, 96x96x64, 128x128x64 and
     128x128x256 grids, dk L in [-6, 6], xi in [0.1, 10], 200-600 steps): one
-    batched run (autotuned, hipGraph) against the same 64 problems propagated
-    one after another with plain plans (tuned pass order); medians of 3."""
+    batched run (autotuned: one hipGraph, or its launch groups on several
+    streams) against the same 64 problems propagated one after another with
+    plain plans (each with its shape's tuned schedule, no synchronisation
+    between them); medians of 3."""
     import torch
     from paper_2609_08384_amd import autotune, brahms, inputs
     wls = inputs.shg_sweep(seed=4, count=64)
