@@ -242,10 +242,11 @@ __device__ inline void line_fft(float2 (&v)[N1], int t, float2* lbuf, const floa
 #define BRAHMS_NT_YT 0
 #endif
 // Blocks of kBlock threads per CU the pass kernels are compiled for: 3 is
-// 3 waves per SIMD, a budget of 168 VGPRs.  The three-field passes that
-// carry an RK4 step need 162-170; at 170 the allocation (granules of 8 out
-// of 512) rounds up to 176 and leaves room for 2 waves only, which cost the
-// fused step-pair pass ~15 % of its speed.  Kernels whose LDS already limits
+// 3 waves per SIMD, a budget of 168 VGPRs (granules of 8 out of 512).  The
+// three-field passes that carry an RK4 step take 132-148 and the fused
+// step-pair pass's LDS allows 3 blocks as well; without the bound the
+// compiler may take more registers and leave room for 2 waves only, which
+// cost the fused pass ~15 % of its speed.  Kernels whose LDS already limits
 // them to fewer blocks keep their register count.
 #ifndef BRAHMS_MIN_BLOCKS
 #define BRAHMS_MIN_BLOCKS 3
