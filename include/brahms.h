@@ -215,6 +215,14 @@ brahms_status brahms_plan_destroy(brahms_plan plan);
  *     the second split on that axis where its length has one (other axes,
  *     the adjoint passes and long tau axes keep the first).  The result
  *     agrees to rounding.  BRAHMS_E_INVALID_ARG outside 0 .. 7.
+ *   wide (bits 1 = x, 2 = y, 4 = tau): the linear passes along a set axis
+ *     (one field per block, no RK4 step: the middle axis of fused step
+ *     pairs, the first axis of merged steps) run blocks of 512 threads
+ *     instead of 256, twice the lines per block; y and tau lines are then
+ *     read and written in row segments twice as long (32 columns for a
+ *     256-point axis).  Every line is transformed as before: bitwise the same
+ *     result.  Plans only (batches and the adjoint keep 256).
+ *     BRAHMS_E_INVALID_ARG outside 0 .. 7.
  * The autotuner in the Python package times the candidates per grid shape. */
 typedef struct {
   int pass_order;
@@ -222,7 +230,8 @@ typedef struct {
   int merge_halves;
   int fuse_steps;
   int split;        /* bit a (x = 1, y = 2, tau = 4): second register/lane split of that axis */
-  int reserved[3];
+  int wide;         /* bit a: that axis's linear passes with 512-thread blocks */
+  int reserved[2];
 } brahms_schedule;
 
 brahms_status brahms_plan_set_schedule(brahms_plan plan, const brahms_schedule* sched);

@@ -44,7 +44,7 @@ def _arch(device) -> str:
 
 
 def _key(arch: str, nx: int, ny: int, nt: int, nf: int, merge: int) -> str:
-    return f"v7:{arch}:{nx}x{ny}x{nt}:nf{nf}:m{merge}"
+    return f"v8:{arch}:{nx}x{ny}x{nt}:nf{nf}:m{merge}"
 
 
 def split_masks(nx: int, ny: int, nt: int):
@@ -55,6 +55,24 @@ def split_masks(nx: int, ny: int, nt: int):
     masks = [0]
     for b in bits:
         masks += [m | b for m in masks]
+    return masks
+
+
+def wide_masks(schedule: dict, nx: int, ny: int, nt: int):
+    """Values of the schedule field `wide` worth timing: each axis whose
+    passes are linear in this schedule (the middle axis; with merged
+    half-steps and no fused pairs also the first), alone and together;
+    none for long tau axes, and none on axes of length 1."""
+    if nt > 256:
+        return []
+    order = [(0, 1, 2), (2, 1, 0), (0, 2, 1), (1, 2, 0)][schedule["pass_order"]]
+    linear = [order[1]]
+    if schedule.get("merge_halves") and not schedule.get("fuse_steps"):
+        linear.append(order[0])
+    bits = [1 << a for a in linear if (nx, ny, nt)[a] > 1]
+    masks = list(bits)
+    if len(bits) > 1:
+        masks.append(sum(bits))
     return masks
 
 
@@ -150,6 +168,14 @@ def tune(nx: int, ny: int, nt: int, nf: int, params: brahms.Params, device="cuda
         # schedule so far (it picks lines per block against values per lane)
         for mask in split_masks(nx, ny, nt)[1:]:
             c = dict(best, split=mask)
+            t = min(measure(nx, ny, nt, nf, scratch, c, device) for _ in range(ROUNDS))
+            times.append((t, c))
+            if t < best_ms:
+                best_ms, best = t, c
+        # 512-thread blocks for the linear passes, on the axes whose passes
+        # are linear in the best schedule
+        for mask in wide_masks(best, nx, ny, nt):
+            c = dict(best, wide=mask)
             t = min(measure(nx, ny, nt, nf, scratch, c, device) for _ in range(ROUNDS))
             times.append((t, c))
             if t < best_ms:

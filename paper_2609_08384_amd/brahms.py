@@ -45,7 +45,7 @@ class BrahmsError(RuntimeError):
 class ScheduleC(ctypes.Structure):
     _fields_ = [("pass_order", ctypes.c_int), ("graph", ctypes.c_int),
                 ("merge_halves", ctypes.c_int), ("fuse_steps", ctypes.c_int),
-                ("split", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+                ("split", ctypes.c_int), ("wide", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
 
 
 class FieldParamsC(ctypes.Structure):
@@ -290,17 +290,19 @@ class Plan:
         _check(self._lib.brahms_set_z(self._h, float(z)), "brahms_set_z")
 
     def set_schedule(self, pass_order: int, graph: int = 0, merge_halves: int = 0,
-                     fuse_steps: int = 0, split: int = 0):
+                     fuse_steps: int = 0, split: int = 0, wide: int = 0):
         """Pass order 0-3, graph replay of 64-step chunks, merged RK4
         half-steps within a call (constant dk, no transverse map), fused
-        step pairs (with merged half-steps: two passes per step), and the
-        per-axis choice of register/lane split (bits x = 1, y = 2, tau = 4)."""
+        step pairs (with merged half-steps: two passes per step), the
+        per-axis choice of register/lane split and the per-axis choice of
+        512-thread blocks for linear passes (bits x = 1, y = 2, tau = 4)."""
         sc = ScheduleC()
         sc.pass_order = int(pass_order)
         sc.graph = int(graph)
         sc.merge_halves = int(merge_halves)
         sc.fuse_steps = int(fuse_steps)
         sc.split = int(split)
+        sc.wide = int(wide)
         _check(self._lib.brahms_plan_set_schedule(self._h, ctypes.byref(sc)),
                "brahms_plan_set_schedule")
 
@@ -309,7 +311,7 @@ class Plan:
         _check(self._lib.brahms_plan_get_schedule(self._h, ctypes.byref(sc)),
                "brahms_plan_get_schedule")
         return {"pass_order": sc.pass_order, "graph": sc.graph, "merge_halves": sc.merge_halves,
-                "fuse_steps": sc.fuse_steps, "split": sc.split}
+                "fuse_steps": sc.fuse_steps, "split": sc.split, "wide": sc.wide}
 
     # --- adjoint (reverse-mode gradient of the z-loop) ---
     def adjoint_workspace_bytes(self, nsteps: int, checkpoint_every: int) -> int:
@@ -454,14 +456,15 @@ class Plan:
 def run_workload(wl, nsteps: Optional[int] = None, device: str = "cuda:0",
                  stream: Optional[torch.cuda.Stream] = None,
                  pass_order: Optional[int] = None,
-                 merge_halves: int = 0, fuse_steps: int = 0, split: int = 0) -> List[torch.Tensor]:
+                 merge_halves: int = 0, fuse_steps: int = 0, split: int = 0,
+                 wide: int = 0) -> List[torch.Tensor]:
     """Upload a seeded workload's entrance fields, propagate nsteps (default:
     all of them) and return the device fields."""
     nsteps = wl.nz if nsteps is None else nsteps
     fields = [torch.from_numpy(a).to(device) for a in wl.init]
     plan = Plan(wl.nx, wl.ny, wl.nt, wl.nf, params_from_workload(wl), stream=stream)
-    if pass_order is not None or merge_halves or split:
-        plan.set_schedule(pass_order or 0, 0, merge_halves, fuse_steps, split)
+    if pass_order is not None or merge_halves or split or wide:
+        plan.set_schedule(pass_order or 0, 0, merge_halves, fuse_steps, split, wide)
     plan.bind(fields)
     plan.step(nsteps)
     torch.cuda.synchronize()

@@ -777,12 +777,14 @@ brahms_status brahms_plan_set_schedule(brahms_plan plan, const brahms_schedule* 
   if (sched->fuse_steps && !detail::long_tau(*plan) && detail::step_passes(*plan, false).n != 3)
     return fail(BRAHMS_E_UNSUPPORTED, "fuse_steps needs an x and a y pass (not nx = ny = 1 with tau <= 256)");
   if (sched->split < 0 || sched->split > 7) return fail(BRAHMS_E_INVALID_ARG, "split must be 0 .. 7");
+  if (sched->wide < 0 || sched->wide > 7) return fail(BRAHMS_E_INVALID_ARG, "wide must be 0 .. 7");
   if (plan->order != sched->pass_order || plan->use_graph != (sched->graph != 0) ||
       plan->merge != (sched->merge_halves != 0) || plan->fuse != (sched->fuse_steps != 0) ||
-      plan->split != sched->split)
+      plan->split != sched->split || plan->wide != sched->wide)
     drop_chunk_graph(*plan);
   plan->order = sched->pass_order;
   plan->split = sched->split;
+  plan->wide = sched->wide;
   plan->use_graph = sched->graph != 0;
   plan->merge = sched->merge_halves != 0;
   plan->fuse = sched->fuse_steps != 0;
@@ -800,6 +802,7 @@ brahms_status brahms_plan_get_schedule(brahms_plan plan, brahms_schedule* sched)
   sched->merge_halves = plan->merge ? 1 : 0;
   sched->fuse_steps = plan->fuse ? 1 : 0;
   sched->split = plan->split;
+  sched->wide = plan->wide;
   return BRAHMS_OK;
 }
 

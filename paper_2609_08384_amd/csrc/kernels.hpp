@@ -25,7 +25,7 @@
 
 namespace brahms {
 
-constexpr int kBlock = 256;        // threads per block in every pass
+constexpr int kBlock = 256;        // threads per block in every pass but the wide linear ones
 constexpr int kNlCoef = 6;         // RK4 coefficients per field per half-step
 
 enum Axis { AX_X = 0, AX_Y = 1, AX_T = 2,
@@ -177,10 +177,10 @@ __device__ inline void rk4_point(float2* y, const float2 (*co)[kNlCoef], const f
 // holds index t + N2 e in slot e, so the inverse transform starts from the
 // same layout without another exchange.
 // ---------------------------------------------------------------------------
-template <int N1, int N2>
+template <int N1, int N2, int BLOCK = kBlock>
 struct LineGeom {
   static constexpr int N = N1 * N2;
-  static constexpr int LPB = kBlock / N2;                  // lines per block
+  static constexpr int LPB = BLOCK / N2;                   // lines per block
   static constexpr int ROW = (N2 > 1) ? N2 + 1 : 1;        // padded LDS row
   static constexpr int LS0 = N1 * ROW;
   static constexpr int LSTRIDE = (N2 > 1) ? (LS0 | 1) : LS0;  // odd stride
@@ -341,10 +341,10 @@ __device__ __forceinline__ void map_factors(const float2* map, unsigned plane, u
 // handled (y pass: the block's field); next: a fused pass also applies the
 // next step's transform (false: the problem's last step, which ends on its
 // own second half-step).
-template <int N1, int N2, int AX, int NF, int NL, bool FULL>
+template <int N1, int N2, int AX, int NF, int NL, bool FULL, int BLOCK = kBlock>
 __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx, int field0,
                                                bool next = true) {
-  using G = LineGeom<N1, N2>;
+  using G = LineGeom<N1, N2, BLOCK>;
   constexpr int N = G::N;
   constexpr int NLM = NL & 3;                  // where the RK4 half-step goes
   constexpr bool MAP = (NL & NL_MAP) != 0;     // transverse mismatch map
@@ -383,27 +383,27 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
     // of length N take every (nt / N)-th entry
     const int nt = args.nt;
     const int stride = nt / N;
-    for (int i = tid; i < N; i += kBlock) s_tw[i] = args.tw[i * stride];
+    for (int i = tid; i < N; i += BLOCK) s_tw[i] = args.tw[i * stride];
     if constexpr (AX == AX_TB) {
       const float2* pr = args.prop + field0 * args.field_stride + args.axis_off;
-      for (int i = tid; i < nt; i += kBlock) {
+      for (int i = tid; i < nt; i += BLOCK) {
         float2 pv = pr[i];
         if (args.conj) pv.y = -pv.y;
         s_long[i] = pv;
       }
     } else {
-      for (int i = tid; i < nt; i += kBlock) s_long[i] = args.tw[i];
+      for (int i = tid; i < nt; i += BLOCK) s_long[i] = args.tw[i];
     }
   } else {
-    for (int i = tid; i < N; i += kBlock) s_tw[i] = args.tw[i];
-    for (int i = tid; i < NF * N; i += kBlock) {
+    for (int i = tid; i < N; i += BLOCK) s_tw[i] = args.tw[i];
+    for (int i = tid; i < NF * N; i += BLOCK) {
       float2 pv = args.prop[(field0 + i / N) * args.field_stride + args.axis_off + i % N];
       if (args.conj) pv.y = -pv.y;
       s_prop[i] = pv;
     }
     if constexpr (FUSE) {
-      for (int i = tid; i < N; i += kBlock) s_tw2[i] = args.tw2[i];
-      for (int i = tid; i < NF * N; i += kBlock)
+      for (int i = tid; i < N; i += BLOCK) s_tw2[i] = args.tw2[i];
+      for (int i = tid; i < NF * N; i += BLOCK)
         s_prop2[i] = args.prop2[(field0 + i / N) * args.field_stride + args.axis_off + i % N];
     }
   }
@@ -609,12 +609,18 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
   }
 }
 
-// One pass of one problem.
-template <int N1, int N2, int AX, int NF, int NL, bool FULL>
-__global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass(PassArgs args) {
+// Threads per block of the wide linear passes (schedule field `wide`): twice
+// the lines of a kBlock block, so y and tau rows are read in segments twice
+// as long; their LDS allows two blocks per CU.
+constexpr int kWideBlock = 2 * kBlock;
+
+// One pass of one problem; BLOCK threads per block (kBlock, or kWideBlock
+// for the wide linear passes of the schedule field `wide`).
+template <int N1, int N2, int AX, int NF, int NL, bool FULL, int BLOCK = kBlock>
+__global__ __launch_bounds__(BLOCK, BLOCK == kBlock ? BRAHMS_MIN_BLOCKS : 2) void axis_pass(PassArgs args) {
   // passes with one field per block take it from blockIdx.z
   constexpr bool per_field = NF == 1;
-  axis_pass_body<N1, N2, AX, NF, NL, FULL>(args, blockIdx.x, per_field ? int(blockIdx.z) : 0);
+  axis_pass_body<N1, N2, AX, NF, NL, FULL, BLOCK>(args, blockIdx.x, per_field ? int(blockIdx.z) : 0);
 }
 
 // One pass over a group of problems of the same shape (a batch): descs[i]

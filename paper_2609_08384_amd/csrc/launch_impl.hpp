@@ -11,10 +11,25 @@ namespace detail {
 // plans: each supported axis length maps to a (N1, N2) split with N2 threads
 // per line and N1 values per thread
 // ---------------------------------------------------------------------------
-template <int N1, int N2, int AX, int NF, int NL>
+template <int N1, int N2, int AX, int NF, int NL, int BLOCK = kBlock>
 void launch_pass(bool full, dim3 grid, hipStream_t st, const PassArgs& a) {
-  if (full) hipLaunchKernelGGL((axis_pass<N1, N2, AX, NF, NL, true>), grid, dim3(kBlock), 0, st, a);
-  else hipLaunchKernelGGL((axis_pass<N1, N2, AX, NF, NL, false>), grid, dim3(kBlock), 0, st, a);
+  if (full) hipLaunchKernelGGL((axis_pass<N1, N2, AX, NF, NL, true, BLOCK>), grid, dim3(BLOCK), 0, st, a);
+  else hipLaunchKernelGGL((axis_pass<N1, N2, AX, NF, NL, false, BLOCK>), grid, dim3(BLOCK), 0, st, a);
+}
+
+// A linear pass (one field per block) over `lines` lines along AX, with
+// kBlock or (wide) kWideBlock threads per block.
+template <int N1, int N2, int AX>
+void launch_linear(bool wide, long lines, int nf, hipStream_t st, const PassArgs& a) {
+  if (wide) {
+    constexpr int LPB = LineGeom<N1, N2, kWideBlock>::LPB;
+    const dim3 grid(unsigned((lines + LPB - 1) / LPB), 1, unsigned(nf));
+    launch_pass<N1, N2, AX, 1, NL_NONE, kWideBlock>(lines % LPB == 0, grid, st, a);
+  } else {
+    constexpr int LPB = LineGeom<N1, N2>::LPB;
+    const dim3 grid(unsigned((lines + LPB - 1) / LPB), 1, unsigned(nf));
+    launch_pass<N1, N2, AX, 1, NL_NONE>(lines % LPB == 0, grid, st, a);
+  }
 }
 
 template <int N1, int N2, int AX, int NF>
@@ -62,11 +77,11 @@ hipError_t launch_axis(int axis, int nl, int nf, const brahms_plan_s& p, PassArg
   using G = LineGeom<N1, N2>;
   a.tile_mul = 1;
   a.tiles = 1;
+  const bool wide = ((p.wide >> axis) & 1) != 0;
   if (axis == AX_X) {
     const long lines = long(p.ny) * p.nt;
     if (nl == NL_NONE) {
-      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(nf));
-      launch_pass<N1, N2, AX_X, 1, NL_NONE>(lines % G::LPB == 0, grid, p.stream, a);
+      launch_linear<N1, N2, AX_X>(wide, lines, nf, p.stream, a);
     } else {
       const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
       launch_nl<N1, N2, AX_X>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
@@ -74,8 +89,7 @@ hipError_t launch_axis(int axis, int nl, int nf, const brahms_plan_s& p, PassArg
   } else if (axis == AX_Y) {
     const long lines = long(p.nx) * p.nt;
     if (nl == NL_NONE) {
-      const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB), 1, unsigned(nf));
-      launch_pass<N1, N2, AX_Y, 1, NL_NONE>(lines % G::LPB == 0, grid, p.stream, a);
+      launch_linear<N1, N2, AX_Y>(wide, lines, nf, p.stream, a);
     } else {
       const dim3 grid(unsigned((lines + G::LPB - 1) / G::LPB));
       launch_plain_nl<N1, N2, AX_Y>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
@@ -86,9 +100,14 @@ hipError_t launch_axis(int axis, int nl, int nf, const brahms_plan_s& p, PassArg
     a.tile_mul = tile_multiplier(grid.x);
     a.tiles = grid.x;
     if (nl == NL_NONE) {
-      // linear tau pass (orders 2 and 3): one field per block
-      const dim3 gridf(grid.x, 1, unsigned(nf));
-      launch_pass<N1, N2, AX_T, 1, NL_NONE>(lines % G::LPB == 0, gridf, p.stream, a);
+      // linear tau pass (orders 2 and 3): one field per block, its tiles
+      // those of its own block size
+      if (wide) {
+        constexpr int LPB = LineGeom<N1, N2, kWideBlock>::LPB;
+        a.tiles = unsigned((lines + LPB - 1) / LPB);
+        a.tile_mul = tile_multiplier(a.tiles);
+      }
+      launch_linear<N1, N2, AX_T>(wide, lines, nf, p.stream, a);
     } else if (nl == NL_BOTH) {
       launch_plain_nl<N1, N2, AX_T>(nf, nl, lines % G::LPB == 0, grid, p.stream, a);
     } else {

@@ -36,6 +36,9 @@ struct brahms_plan_s {
   // schedule field split: bit a (x = 1, y = 2, tau = 4) runs that axis's line
   // transforms with the second split of its length (lengths.hpp), if any
   int split = 0;
+  // schedule field wide: bit a (x = 1, y = 2, tau = 4) runs that axis's
+  // linear passes (one field per block) with kWideBlock threads per block
+  int wide = 0;
   // hipGraph replay of whole 64-step chunks (schedule field `graph`)
   bool use_graph = false;
   hipGraph_t chunk_graph = nullptr;

@@ -98,7 +98,8 @@ void release(Fields& f) {
 }
 
 // One problem alone through a plan with the given schedule.
-std::vector<std::vector<float2>> run_alone(Problem& p, int order, int merge, int fuse, int graph = 0) {
+std::vector<std::vector<float2>> run_alone(Problem& p, int order, int merge, int fuse, int graph = 0,
+                                           int wide = 0) {
   set_profile(p);
   std::vector<Problem> one{p};
   Fields f = upload(one);
@@ -109,6 +110,7 @@ std::vector<std::vector<float2>> run_alone(Problem& p, int order, int merge, int
   sc.merge_halves = merge;
   sc.fuse_steps = fuse;
   sc.graph = graph;
+  sc.wide = wide;
   size_t ws_bytes = 0;
   OK(brahms_plan_workspace_size(plan, &ws_bytes));
   void* ws = emu::device_alloc(ws_bytes);
@@ -519,6 +521,12 @@ void scenario_plans() {
   expect_equal(run_alone(lt, 0, 1, 1, 0), run_alone(lt, 0, 1, 1, 1), "long tau graph replay");
   Problem prof = make_problem(r, 8, 16, 16, 2, 66, true, 0.0);
   expect_equal(run_alone(prof, 1, 0, 0, 0), run_alone(prof, 1, 0, 0, 1), "profile graph replay");
+  // 512-thread linear passes on every axis, in every order, merged and
+  // fused (partial blocks: 16 x 8 x 32 has 128 y lines and 128 tau lines)
+  for (int order = 0; order < 4; ++order)
+    for (int fuse = 0; fuse < 2; ++fuse)
+      expect_equal(run_alone(p, order, 1, fuse, 0, 7), run_alone(p, order, 1, fuse, 0, 0),
+                   "wide linear passes order " + std::to_string(order));
   std::printf("plans: ok\n");
 }
 

@@ -212,6 +212,15 @@ def test_schedule_host_checks(lib):
     assert lib.brahms_plan_set_schedule(h, ctypes.byref(sc)) == brahms.BRAHMS_OK
     assert lib.brahms_plan_get_schedule(h, ctypes.byref(out)) == brahms.BRAHMS_OK
     assert (out.merge_halves, out.fuse_steps) == (1, 1)
+    # 512-thread linear passes: a bit per axis
+    for bad in (-1, 8):
+        sc.wide = bad
+        assert lib.brahms_plan_set_schedule(h, ctypes.byref(sc)) == brahms.BRAHMS_E_INVALID_ARG
+    sc.wide = 5
+    assert lib.brahms_plan_set_schedule(h, ctypes.byref(sc)) == brahms.BRAHMS_OK
+    assert lib.brahms_plan_get_schedule(h, ctypes.byref(out)) == brahms.BRAHMS_OK
+    assert out.wide == 5
+    sc.wide = 0
     sc.fuse_steps = 0
     lib.brahms_plan_destroy(h)
     # a long tau axis sits between the x and y passes of fused pairs; plane

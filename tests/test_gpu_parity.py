@@ -223,6 +223,36 @@ def test_plan_on_a_side_stream():
     plan.destroy()
 
 
+@pytest.mark.parametrize("nf,shape", [(3, (32, 16, 8)), (2, (96, 64, 2)), (3, (24, 48, 192)), (2, (256, 2, 1)),
+                                      (3, (16, 128, 64)), (2, (3, 6, 12)), (3, (128, 96, 96))])
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
+def test_wide_linear_passes_bitwise(nf, shape, order):
+    """512-thread blocks for the linear passes (schedule field `wide`, every
+    axis) transform every line as the 256-thread blocks do: the same bits,
+    literal, merged and fused, over calls that cross a 64-step chunk, with
+    partial last blocks (lines not a multiple of the lines per block)."""
+    nx, ny, nt = shape
+    rng = np.random.default_rng(700 + nf + nt + order)
+    init = inputs.random_fields(rng, nf, nx, ny, nt, scale=0.6, smooth=max(1.0, min(shape) / 2.0))
+    wl = _wl(nx, ny, nt, nf, 70, 0.01, _all_terms(nf, kappa=1.4), dk_const=1.7, init=init)
+    for merge, fuse in ((0, 0), (1, 0), (1, 1)):
+        ref = brahms.run_workload(wl, device=DEV, pass_order=order, merge_halves=merge, fuse_steps=fuse)
+        out = brahms.run_workload(wl, device=DEV, pass_order=order, merge_halves=merge, fuse_steps=fuse,
+                                  wide=7)
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b), (merge, fuse)
+
+
+def test_opg256_wide_middle_pass_bitwise():
+    """The benchmark workload with its middle (y) pass on 512-thread blocks:
+    the bits of 256-thread blocks after 12 fused steps."""
+    wl = inputs.opg256()
+    ref = brahms.run_workload(wl, 12, device=DEV, pass_order=0, merge_halves=1, fuse_steps=1)
+    out = brahms.run_workload(wl, 12, device=DEV, pass_order=0, merge_halves=1, fuse_steps=1, wide=2)
+    for a, b in zip(out, ref):
+        assert torch.equal(a, b)
+
+
 def test_nonfinite_detected():
     """A dz far too large for kappa |A| (Sec. 3.2) blows the fields up; with
     BRAHMS_CHECK_FINITE the call reports E_NONFINITE."""

@@ -44,14 +44,18 @@ def test_tuner_takes_the_fastest_order_and_caches(fake_tuner, tmp_path):
     # register/lane splits of the three axes (length 32 has a second one)
     n_split = len(autotune.split_masks(32, 32, 32)) - 1
     assert n_split == 7
-    n_calls = 1 + autotune.ROUNDS * (2 * len(autotune.CANDIDATES) + n_split)
+    # then 512-thread blocks on the linear axes (merged, unfused order 1:
+    # tau first and y in the middle, alone and together)
+    n_wide = len(autotune.wide_masks(best, 32, 32, 32))
+    assert autotune.wide_masks(best, 32, 32, 32) == [2, 4, 6]
+    n_calls = 1 + autotune.ROUNDS * (2 * len(autotune.CANDIDATES) + n_split + n_wide)
     assert len(calls) == n_calls
     assert all(c["merge_halves"] == 1 for c in calls)
     assert {c["fuse_steps"] for c in calls} == {0, 1}
     with open(os.path.join(str(tmp_path), "schedules.json")) as fh:
         disk = json.load(fh)
     (key, entry), = disk.items()
-    assert key == "v7:gfx950:32x32x32:nf2:m1" and entry["schedule"] == best
+    assert key == "v8:gfx950:32x32x32:nf2:m1" and entry["schedule"] == best
     autotune._memo.clear()
     assert autotune.tune(32, 32, 32, 2, _params()) == best     # from the disk cache
     assert len(calls) == n_calls
