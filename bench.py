@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle z-steps in the CPU sample")
     ap.add_argument("--pass-order", default="auto", choices=["auto", "0", "1", "2", "3"],
                     help="plan schedule: autotuned (default) or a fixed pass order")
+    ap.add_argument("--wide", type=int, default=0,
+                    help="with a fixed pass order: axes (bits x=1, y=2, tau=4) whose linear passes "
+                         "run 512-thread blocks")
     ap.add_argument("--literal-halves", action="store_true",
                     help="keep both RK4 half-steps of every step (no merging of adjacent halves)")
     ap.add_argument("--no-fuse", action="store_true",
@@ -386,7 +389,7 @@ def fused_pass_flops(nf: int, points: int, n_axis: int) -> float:
 
 
 def measured_traffic(workload: str, pass_name: str, pass_order: int, merge_halves: int = 0,
-                     fuse_steps: int = 0):
+                     fuse_steps: int = 0, wide: int = 0):
     """HBM bytes per launch of one pass kernel from the hardware-counter
     summary profiles/hbm_traffic_<workload>.json (FETCH_SIZE and WRITE_SIZE
     per dispatch, each scaled by what the counter reads for a plain copy of
@@ -400,7 +403,10 @@ def measured_traffic(workload: str, pass_name: str, pass_order: int, merge_halve
         return None
     if rec.get("kernel_digest") != kernel_digest():
         return None
-    key = f"{pass_name}:{nl_of_pass(pass_order, merge_halves, fuse_steps)[pass_name]}"
+    mode = nl_of_pass(pass_order, merge_halves, fuse_steps)[pass_name]
+    axis_bit = {"x_pass": 1, "y_pass": 2, "t_pass": 4}[pass_name]
+    # linear passes on 512-thread blocks are kernels of their own
+    key = f"{pass_name}:{mode}" + (":wide" if mode == "none" and wide & axis_bit else "")
     k = rec.get("kernels", {}).get(key)
     if k is None:
         return None
@@ -474,7 +480,7 @@ def main():
         schedule = autotune.apply(plan, dev, merge_halves=not args.literal_halves)
     else:
         merge = 0 if args.literal_halves else 1
-        plan.set_schedule(int(args.pass_order), 0, merge, merge and not args.no_fuse)
+        plan.set_schedule(int(args.pass_order), 0, merge, merge and not args.no_fuse, 0, args.wide)
         schedule = plan.get_schedule()
 
     def reset():
@@ -568,7 +574,8 @@ def main():
     step_ms = ev_ms / steps
     step_gbs = step_bytes / (step_ms * 1e-3) / 1e9
     traffic = None
-    pass_traffic = {k: measured_traffic(wl.name, k, order, merge, fuse) for k in passes if passes[k][1]}
+    pass_traffic = {k: measured_traffic(wl.name, k, order, merge, fuse, int(schedule.get("wide", 0)))
+                    for k in passes if passes[k][1]}
     if pass_traffic and all(v is not None for v in pass_traffic.values()):
         # launches per step of each pass kind in the steady state
         traffic = int(round(sum(pass_traffic[k] * passes[k][1] for k in pass_traffic) / timed_steps))
