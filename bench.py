@@ -338,7 +338,7 @@ def batch_ratio(dev):
             "grid_point_steps": work, "batched_ms": t_batch * 1e3, "sequential_ms": t_seq * 1e3,
             "speedup": t_seq / t_batch, "batched_rate": work / t_batch,
             "sequential_rate": work / t_seq, "launch_groups": groups,
-            "schedule": tuned["choice"], "group_max": tuned["group_max"], "streams": list(tuned["streams"]),
+            "schedule": tuned["choice"], "group_max": tuned["group_max"], "streams": list(tuned["streams"]), "wide": tuned.get("wide"),
             "group_limits": tuned["group_limits"], "batch_orders": tuned["orders"],
             "tuner_probe_ms": tuned["probe_ms"], "tuner_shape_probe_ms": tuned["shape_probe_ms"]}
 

@@ -362,6 +362,13 @@ brahms_status brahms_adjoint(brahms_plan plan, int nsteps, int checkpoint_every,
  *   the first split everywhere; problems of one shape with different splits
  *   go to different launch groups.  Invalidates the binding.  Errors:
  *   BRAHMS_E_INVALID_ARG outside 0 .. 7.
+ * brahms_batch_set_wide: per-problem 512-thread blocks for the linear x and
+ *   y passes (n entries, the schedule field wide of plans restricted to the
+ *   bits x = 1 and y = 2: a batch's linear tau passes share their block-to-
+ *   tile map with the tau launches that carry a half-step, and keep 256
+ *   threads), or NULL for none; bitwise the same result.  Problems of one
+ *   shape with different values go to different launch groups.  Invalidates
+ *   the binding.  Errors: BRAHMS_E_INVALID_ARG outside 0 .. 3.
  * brahms_batch_set_streams: 1 (default) captures the run into one hipGraph
  *   whose launch groups run one after the other (largest first); 2 .. 4
  *   issues the run's launches directly on that many streams, the caller's
@@ -403,6 +410,7 @@ brahms_status brahms_batch_set_schedule(brahms_batch batch, int group_max, const
 brahms_status brahms_batch_set_group_limits(brahms_batch batch, const int* limits);
 brahms_status brahms_batch_set_streams(brahms_batch batch, int streams, int largest_alone);
 brahms_status brahms_batch_set_splits(brahms_batch batch, const int* splits);
+brahms_status brahms_batch_set_wide(brahms_batch batch, const int* wide);
 brahms_status brahms_batch_set_merge_halves(brahms_batch batch, int merge_halves);
 brahms_status brahms_batch_set_fuse_steps(brahms_batch batch, int fuse_steps);
 brahms_status brahms_batch_workspace_size(brahms_batch batch, size_t* bytes);

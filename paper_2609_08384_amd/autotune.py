@@ -221,8 +221,8 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
     """Pick the pass orders, the launch-group sizes and the launch mode of a
     batch by timing copies of it on scratch fields, with at most max_steps
     steps per problem:
-    * per grid shape, the register/lane splits that `tune` found fastest for
-      a plain solve;
+    * per grid shape, the register/lane splits and the 512-thread linear x
+      and y passes that `tune` found fastest for a plain solve;
     * per grid shape alone, the group sizes LIMIT_CANDIDATES (the fastest
       differs between shapes: small grids want many problems per launch,
       large ones few);
@@ -246,6 +246,8 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
              for (nx, ny, nt, nf, prm, _) in problems]
     tuned = [sc["pass_order"] for sc in sched]
     splits = [sc.get("split", 0) for sc in sched]
+    # (a batch's linear tau passes keep 256-thread blocks)
+    wides = [sc.get("wide", 0) & 3 for sc in sched]
     order_sets = {"per_shape": tuned, "all_0": [0] * n, "all_1": [1] * n}
     short = [(nx, ny, nt, nf, prm, min(ns, max_steps)) for (nx, ny, nt, nf, prm, ns) in problems]
     gen = torch.Generator(device="cpu").manual_seed(7)
@@ -262,6 +264,7 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
         sub.set_merge_halves(merge)
         sub.set_fuse_steps(fuse)
         sub.set_splits([splits[i] for i in idx])
+        sub.set_wide([wides[i] for i in idx])
         sub.set_schedule(0, [tuned[i] for i in idx])
         times = []
         for lim in LIMIT_CANDIDATES:
@@ -277,6 +280,7 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
     probe.set_merge_halves(merge)
     probe.set_fuse_steps(fuse)
     probe.set_splits(splits)
+    probe.set_wide(wides)
     candidates = []
 
     def configure(gm, oname):
@@ -310,6 +314,7 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
     batch.set_merge_halves(merge)
     batch.set_fuse_steps(fuse)
     batch.set_splits(splits)
+    batch.set_wide(wides)
     batch.set_streams(*streams)
     if gm is None:
         batch.set_schedule(0, order_sets[oname])
@@ -320,6 +325,7 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
     return {"choice": label, "group_max": gm, "group_limits": limits if gm is None else None,
             "pass_orders": order_sets[oname], "orders": oname, "merge_halves": merge, "fuse_steps": fuse,
             "splits": splits,
+            "wide": wides,
             "streams": streams,
             "probe_ms": {f"{c[1]}/{c[3]}/streams={c[4][0]}{'/largest_alone' if c[4][1] else ''}": c[0]
                          for c in candidates},

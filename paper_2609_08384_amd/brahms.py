@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "brahms_batch_set_schedule": [vp, i, ctypes.POINTER(i)],
         "brahms_batch_set_group_limits": [vp, ctypes.POINTER(i)],
         "brahms_batch_set_streams": [vp, i, i],
+        "brahms_batch_set_wide": [vp, ctypes.POINTER(i)],
         "brahms_batch_set_splits": [vp, ctypes.POINTER(i)],
         "brahms_batch_set_merge_halves": [vp, i],
         "brahms_batch_set_fuse_steps": [vp, i],
@@ -543,6 +544,16 @@ class Batch:
         if splits is not None:
             arr = (ctypes.c_int * len(self.problems))(*[int(v) for v in splits])
         _check(self._lib.brahms_batch_set_splits(self._h, arr), "brahms_batch_set_splits")
+        if self.fields is not None:
+            self.bind(self.fields)
+
+    def set_wide(self, wide: Optional[Sequence[int]]):
+        """Per-problem 512-thread blocks for the linear x and y passes (bits
+        x = 1, y = 2), or None."""
+        arr = None
+        if wide is not None:
+            arr = (ctypes.c_int * len(self.problems))(*[int(v) for v in wide])
+        _check(self._lib.brahms_batch_set_wide(self._h, arr), "brahms_batch_set_wide")
         if self.fields is not None:
             self.bind(self.fields)
 

@@ -67,7 +67,7 @@ struct brahms_batch_s {
   struct Group {
     std::vector<int> members;
     int axis_len[3];
-    int nf, order, split, max_steps;
+    int nf, order, split, wide, max_steps;
     size_t desc_off;                   // [3 passes][kChunk slots][members] PassArgs
     size_t targs_off;                  // [chunks][members] TableArgs
   };
@@ -170,7 +170,7 @@ void make_groups(brahms_batch_s& b) {
     const brahms::detail::StepPasses sp = brahms::detail::step_passes(p, true);
     int code = sp.n;
     for (int k = 0; k < sp.n; ++k) code = code * 8 + sp.ax[k];
-    by_key[{p.nx, p.ny, p.nt, p.nf, p.order * 8 + p.split, code}].push_back(i);
+    by_key[{p.nx, p.ny, p.nt, p.nf, (p.order * 8 + p.split) * 8 + p.wide, code}].push_back(i);
   }
   for (auto& kv : by_key) {
     const std::vector<int>& ids = kv.second;
@@ -186,6 +186,7 @@ void make_groups(brahms_batch_s& b) {
       g.nf = p0.nf;
       g.order = p0.order;
       g.split = p0.split;
+      g.wide = p0.wide;
       g.max_steps = 0;
       for (int m : g.members) g.max_steps = std::max(g.max_steps, b.capacity[m]);
       b.groups.push_back(g);
@@ -225,7 +226,7 @@ size_t table_arg_bytes(brahms_batch_s& b) {
 
 brahms::detail::GroupGeom geom_of(const brahms_batch_s::Group& g) {
   return brahms::detail::GroupGeom{unsigned(g.members.size()), g.axis_len[0], g.axis_len[1], g.axis_len[2],
-                                   g.nf};
+                                   g.nf, g.wide};
 }
 
 template <int AX>
@@ -616,6 +617,18 @@ brahms_status brahms_batch_set_splits(brahms_batch b, const int* splits) {
     for (int i = 0; i < b->n; ++i)
       if (splits[i] < 0 || splits[i] > 7) return fail(BRAHMS_E_INVALID_ARG, "splits must be 0 .. 7");
   for (int i = 0; i < b->n; ++i) b->plans[i]->split = splits == nullptr ? 0 : splits[i];
+  drop_graph(*b);
+  b->bound = false;
+  layout_batch(*b);
+  return BRAHMS_OK;
+}
+
+brahms_status brahms_batch_set_wide(brahms_batch b, const int* wide) {
+  if (brahms_status st = check_batch(b)) return st;
+  if (wide != nullptr)
+    for (int i = 0; i < b->n; ++i)
+      if (wide[i] < 0 || wide[i] > 3) return fail(BRAHMS_E_INVALID_ARG, "wide must be 0 .. 3 in a batch");
+  for (int i = 0; i < b->n; ++i) b->plans[i]->wide = wide == nullptr ? 0 : wide[i];
   drop_graph(*b);
   b->bound = false;
   layout_batch(*b);

@@ -627,8 +627,8 @@ __global__ __launch_bounds__(BLOCK, BLOCK == kBlock ? BRAHMS_MIN_BLOCKS : 2) voi
 // describes problem i at this step; passes over all fields take the problem
 // from blockIdx.y, passes with one field per block from blockIdx.z / nf.  Problems whose own step count
 // is reached (step >= nz) leave at once.
-template <int N1, int N2, int AX, int NF, int NL, bool FULL>
-__global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass_batched(
+template <int N1, int N2, int AX, int NF, int NL, bool FULL, int BLOCK = kBlock>
+__global__ __launch_bounds__(BLOCK, BLOCK == kBlock ? BRAHMS_MIN_BLOCKS : 2) void axis_pass_batched(
     const PassArgs* descs, long long step, int nf) {
   // linear y and long-tau passes take one field per block: problem and field
   // from blockIdx.z
@@ -637,8 +637,8 @@ __global__ __launch_bounds__(kBlock, BRAHMS_MIN_BLOCKS) void axis_pass_batched(
   const PassArgs& a = descs[inst];
   if (step >= a.nz) return;
   // a fused pass ends the problem's last step without the next transform
-  axis_pass_body<N1, N2, AX, NF, NL, FULL>(a, blockIdx.x, per_field ? int(blockIdx.z % unsigned(nf)) : 0,
-                                           step + 1 < a.nz);
+  axis_pass_body<N1, N2, AX, NF, NL, FULL, BLOCK>(a, blockIdx.x, per_field ? int(blockIdx.z % unsigned(nf)) : 0,
+                                                  step + 1 < a.nz);
 }
 
 // ---------------------------------------------------------------------------

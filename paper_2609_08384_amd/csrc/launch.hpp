@@ -23,10 +23,13 @@ hipError_t launch_axis(int axis, int nl, int nf, const brahms_plan_s& p, PassArg
 template <int N1, int N2, int AX>
 hipError_t launch_long(int nl, int nf, const brahms_plan_s& p, PassArgs a);
 
-// Geometry of a batch launch group: m problems of one shape and field count.
+// Geometry of a batch launch group: m problems of one shape and field count;
+// wide: bits (x = 1, y = 2) of the axes whose linear passes run kWideBlock
+// threads per block.
 struct GroupGeom {
   unsigned m;
   int nx, ny, nt, nf;
+  int wide;
 };
 
 // One pass over a launch group (descriptors d[m] of this step).

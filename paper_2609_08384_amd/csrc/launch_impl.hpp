@@ -140,12 +140,22 @@ hipError_t launch_long(int nl, int nf, const brahms_plan_s& p, PassArgs a) {
 // batches: the problem index is a grid dimension (blockIdx.y for passes over
 // all fields, blockIdx.z / nf for passes of one field per block)
 // ---------------------------------------------------------------------------
-template <int N1, int N2, int AX, int NF, int NL>
+template <int N1, int N2, int AX, int NF, int NL, int BLOCK = kBlock>
 void launch_batched(bool full, dim3 grid, hipStream_t st, const PassArgs* d, long long step, int nf) {
   if (full)
-    hipLaunchKernelGGL((axis_pass_batched<N1, N2, AX, NF, NL, true>), grid, dim3(kBlock), 0, st, d, step, nf);
+    hipLaunchKernelGGL((axis_pass_batched<N1, N2, AX, NF, NL, true, BLOCK>), grid, dim3(BLOCK), 0, st, d, step,
+                       nf);
   else
-    hipLaunchKernelGGL((axis_pass_batched<N1, N2, AX, NF, NL, false>), grid, dim3(kBlock), 0, st, d, step, nf);
+    hipLaunchKernelGGL((axis_pass_batched<N1, N2, AX, NF, NL, false, BLOCK>), grid, dim3(BLOCK), 0, st, d, step,
+                       nf);
+}
+
+// A linear x or y pass over a launch group with kWideBlock threads per block.
+template <int N1, int N2, int AX>
+void launch_batched_wide(long lines, const GroupGeom& g, hipStream_t st, const PassArgs* d, long long step) {
+  constexpr int LPB = LineGeom<N1, N2, kWideBlock>::LPB;
+  const dim3 grid(unsigned((lines + LPB - 1) / LPB), 1, unsigned(g.nf) * g.m);
+  launch_batched<N1, N2, AX, 1, NL_NONE, kWideBlock>(lines % LPB == 0, grid, st, d, step, g.nf);
 }
 
 template <int N1, int N2, int AX, int NF>
@@ -178,7 +188,10 @@ void launch_group_pass(int axis, int nl, const GroupGeom& g, hipStream_t st, con
   const long lines = axis == AX_X ? long(g.ny) * g.nt : (axis == AX_Y ? long(g.nx) * g.nt : long(g.nx) * g.ny);
   const bool full = lines % G::LPB == 0;
   const unsigned blocks = unsigned((lines + G::LPB - 1) / G::LPB);
-  if (nl == NL_NONE) {
+  if (nl == NL_NONE && axis != AX_T && ((g.wide >> axis) & 1)) {
+    if (axis == AX_X) launch_batched_wide<N1, N2, AX_X>(lines, g, st, d, step);
+    else launch_batched_wide<N1, N2, AX_Y>(lines, g, st, d, step);
+  } else if (nl == NL_NONE) {
     const dim3 grid(blocks, 1, unsigned(g.nf) * m);
     if (axis == AX_X) launch_batched<N1, N2, AX_X, 1, NL_NONE>(full, grid, st, d, step, g.nf);
     else if (axis == AX_Y) launch_batched<N1, N2, AX_Y, 1, NL_NONE>(full, grid, st, d, step, g.nf);

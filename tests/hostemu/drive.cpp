@@ -357,6 +357,9 @@ void scenario_splits() {
   const int spec[4][5] = {{64, 16, 32, 2, 9}, {64, 16, 32, 2, 7}, {48, 24, 8, 3, 6}, {8, 12, 64, 3, 5}};
   for (auto& s : spec) ps.push_back(make_problem(r, s[0], s[1], s[2], s[3], s[4], false, r.uniform(-3, 3)));
   const std::vector<int> splits = {7, 1, 5, 6};
+  // and 512-thread linear x and y passes on some problems (bitwise the plan
+  // without them)
+  const std::vector<int> wide = {3, 0, 2, 1};
   for (int merge : {0, 1}) {
     const int n = int(ps.size());
     std::vector<int> shapes, steps;
@@ -369,6 +372,7 @@ void scenario_splits() {
     brahms_batch b = nullptr;
     OK(brahms_batch_create(n, shapes.data(), prm.data(), steps.data(), nullptr, &b));
     OK(brahms_batch_set_splits(b, splits.data()));
+    OK(brahms_batch_set_wide(b, wide.data()));
     if (merge) {
       OK(brahms_batch_set_merge_halves(b, 1));
       OK(brahms_batch_set_fuse_steps(b, 1));

@@ -201,6 +201,41 @@ def test_batch_with_second_splits():
             assert torch.equal(a, b), (w.nx, w.ny, w.nt, sp)
 
 
+@pytest.mark.parametrize("merge,fuse", [(0, 0), (1, 0), (1, 1)])
+def test_batch_with_wide_linear_passes(merge, fuse):
+    """Per-problem 512-thread linear x and y passes in a batch (partial last
+    blocks included): the same bits as plans with 256-thread blocks; the tau
+    bit is refused in batches."""
+    rng = np.random.default_rng(73 + merge + fuse)
+    wls = []
+    for (nx, ny, nt), nf, nz in [((64, 16, 32), 2, 9), ((64, 16, 32), 2, 7), ((48, 24, 8), 3, 6),
+                                 ((96, 12, 6), 2, 5)]:
+        fs = [inputs.FieldSpec(kappa=1.0 + 0.2 * j, diffraction=float(rng.uniform(0.5, 2.0)),
+                               tan_rho=float(rng.uniform(-0.5, 0.5)), delay=float(rng.uniform(-1, 1)),
+                               k2=float(rng.uniform(-2, 2))) for j in range(nf)]
+        wl = inputs.Workload("w", nx, ny, nt, nf, nz, 1.0 / nz, fs, dk_const=float(rng.uniform(-3, 3)))
+        wl.init = inputs.random_fields(rng, nf, nx, ny, nt, scale=0.7, smooth=3.0)
+        wls.append(wl)
+    wide = [3, 0, 2, 1]
+    batch = brahms.Batch([(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls])
+    batch.set_merge_halves(merge)
+    batch.set_fuse_steps(fuse)
+    batch.set_wide(wide)
+    assert len(batch.groups()) == 4
+    fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
+    batch.bind(fields)
+    batch.run()
+    torch.cuda.synchronize()
+    out = [[f.clone() for f in fs] for fs in fields]
+    with pytest.raises(brahms.BrahmsError):
+        batch.set_wide([4, 0, 0, 0])
+    batch.destroy()
+    for w, fs in zip(wls, out):
+        alone = brahms.run_workload(w, device=DEV, pass_order=0, merge_halves=merge, fuse_steps=fuse)
+        for a, b in zip(fs, alone):
+            assert torch.equal(a, b), (w.nx, w.ny, w.nt)
+
+
 def test_batch_matches_oracle():
     wls = _problems(seed=12)
     probs = [(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls]
