@@ -171,14 +171,27 @@ __global__ __launch_bounds__(kBlock) void adjoint_pass(AdjArgs args) {
   }
   const unsigned idx0 = base + unsigned(t) * estride;
   const unsigned estep = unsigned(N2) * estride;
+  // x lines: a line's N2 lanes are consecutive threads, within one wavefront
+  constexpr bool WL = AX == AX_X && N2 <= 64 && 64 % N2 == 0;
   // a line's LDS row (lines of one lane exchange nothing: no row)
   float2* lbuf = (N2 > 1) ? lds + li * G::LSTRIDE : lds;
   const DftConsts K = *args.consts;
+  // fields through buffer resources, as in the forward passes
+  const unsigned field_bytes = unsigned(args.nx) * unsigned(args.ny) * unsigned(args.nt) * 8u;
+  const unsigned lane_bytes = idx0 * 8u;
+  const unsigned slot_bytes = estep * 8u;
+  __amdgpu_buffer_rsrc_t rg[NF], ry[NF];
+#pragma unroll
+  for (int j = 0; j < NF; ++j) {
+    rg[j] = field_rsrc(args.g[j], field_bytes);
+    ry[j] = field_rsrc(args.y[j], field_bytes);
+  }
+  // RK4 coefficients: the same for every thread, in scalar registers
   float2 co[NF][kNlCoef];
 #pragma unroll
   for (int j = 0; j < NF; ++j)
 #pragma unroll
-    for (int c = 0; c < kNlCoef; ++c) co[j][c] = args.nl[j * kNlCoef + c];
+    for (int c = 0; c < kNlCoef; ++c) co[j][c] = wave_uniform(args.nl[j * kNlCoef + c]);
   float sigma[NF];
 #pragma unroll
   for (int j = 0; j < NF; ++j) sigma[j] = args.sigma[j];
@@ -189,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_pass(AdjArgs args) {
   for (int j = 0; j < NF; ++j)
 #pragma unroll
     for (int e = 0; e < N1; ++e)
-      v[j][e] = valid ? args.g[j][idx0 + unsigned(e) * estep] : make_float2(0.f, 0.f);
+      v[j][e] = valid ? load_slot<false>(rg[j], lane_bytes, unsigned(e) * slot_bytes) : make_float2(0.f, 0.f);
   __syncthreads();  // s_tw, s_prop staged
 
   auto reverse_rk4 = [&]() {
@@ -198,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_pass(AdjArgs args) {
       float2 yy[NF], gg[NF];
 #pragma unroll
       for (int j = 0; j < NF; ++j) {
-        yy[j] = valid ? args.y[j][idx0 + unsigned(e) * estep] : make_float2(0.f, 0.f);
+        yy[j] = valid ? load_slot<false>(ry[j], lane_bytes, unsigned(e) * slot_bytes) : make_float2(0.f, 0.f);
         gg[j] = v[j][e];
       }
       // One point at a time: tie this point's inputs to the phase sums of the
@@ -217,17 +230,17 @@ __global__ __launch_bounds__(kBlock) void adjoint_pass(AdjArgs args) {
   if constexpr (AT == VJP_FIRST) reverse_rk4();
 #pragma unroll
   for (int j = 0; j < NF; ++j) {
-    line_fft<N1, N2, false>(v[j], t, lbuf, s_tw, K);
+    line_fft<N1, N2, false, WL>(v[j], t, lbuf, s_tw, K);
 #pragma unroll
     for (int e = 0; e < N1; ++e) v[j][e] = cmulc(v[j][e], s_prop[j * N + t + N2 * e]);
-    line_fft<N1, N2, true>(v[j], t, lbuf, s_tw, K);
+    line_fft<N1, N2, true, WL>(v[j], t, lbuf, s_tw, K);
   }
   if constexpr (AT == VJP_LAST) reverse_rk4();
   if (valid) {
 #pragma unroll
     for (int j = 0; j < NF; ++j)
 #pragma unroll
-      for (int e = 0; e < N1; ++e) args.g[j][idx0 + unsigned(e) * estep] = v[j][e];
+      for (int e = 0; e < N1; ++e) store_slot<false>(rg[j], lane_bytes, unsigned(e) * slot_bytes, v[j][e]);
   }
 
   // block reduction of the three phase derivatives, fixed order
