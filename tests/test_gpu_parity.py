@@ -344,6 +344,20 @@ def test_opg256_full_run_vs_oracle(order, merge, fuse):
     assert np.allclose(e, g["energies"], rtol=6e-5)
 
 
+@pytest.mark.parametrize("order", [0, 1])
+def test_opg256_full_run_in_the_benchmark_schedule(order):
+    """OPG 256^3, all 1000 steps, in the schedule the benchmark's tuner picks
+    (merged half-steps, fused step pairs, the middle y pass on 512-thread
+    blocks): the same bounds as the other full runs, over the whole fields."""
+    if not os.path.exists(f"{GOLDEN}/opg256_1000.npz"):
+        pytest.skip("reference data not generated")
+    wl = inputs.opg256()
+    out = [f.cpu().numpy() for f in brahms.run_workload(wl, device=DEV, pass_order=order, merge_halves=1,
+                                                          fuse_steps=1, wide=2)]
+    g, whole = _check_golden(out, "opg256_1000", 3e-5)
+    assert len(whole) == 3
+
+
 def test_error_grows_like_sqrt_of_steps():
     """Rounding along z (reading T of the design notes): with the propagator
     phases telescoped and every per-step constant rounded afresh, the GPU's
