@@ -528,6 +528,34 @@ def test_fused_step_pairs_match_merged_oracle(nf, shape, order):
             assert rel_l2(g[j], o[j]) < 5e-6, (nz, j)
 
 
+@pytest.mark.parametrize("nf,shape", [(3, (32, 32, 32)), (2, (96, 64, 2)), (3, (24, 48, 12)), (2, (64, 16, 128)),
+                                      (3, (256, 8, 4))])
+def test_tuned_plans_match_oracle(nf, shape, tmp_path, monkeypatch):
+    """Whatever schedule the autotuner picks for a shape (pass order, graph,
+    merged halves, fused pairs, register/lane splits, wide linear passes),
+    the plan computes the oracle's loop (the merged one when the schedule
+    merges) to the fused-pair tolerance, over a call that crosses a 64-step
+    table chunk."""
+    from paper_2609_08384_amd import autotune
+    monkeypatch.setenv("BRAHMS_CACHE_DIR", str(tmp_path))
+    autotune._memo.clear()
+    nx, ny, nt = shape
+    rng = np.random.default_rng(900 + nf + nt)
+    init = inputs.random_fields(rng, nf, nx, ny, nt, scale=0.7, smooth=max(1.0, min(nx, ny, nt) / 2.0))
+    wl = _wl(nx, ny, nt, nf, 70, 0.01, _all_terms(nf, kappa=1.5), dk_const=2.3, init=init)
+    fields = [torch.from_numpy(a).to(DEV) for a in wl.init]
+    plan = brahms.Plan(nx, ny, nt, nf, brahms.params_from_workload(wl))
+    sched = autotune.apply(plan, DEV)
+    plan.bind(fields)
+    plan.step(wl.nz)
+    torch.cuda.synchronize()
+    plan.destroy()
+    autotune._memo.clear()
+    ref = _oracle(wl, merge=sched.get("merge_halves", 0))
+    for j in range(nf):
+        assert rel_l2(fields[j].cpu().numpy(), ref[j]) < 5e-6, (sched, j)
+
+
 def test_fused_step_pairs_refused_where_a_step_is_not_three_passes():
     wl = inputs.Workload("pw", 1, 1, 64, 2, 4, 0.1, _all_terms(2, kappa=1.0))
     plan = brahms.Plan(1, 1, 64, 2, brahms.params_from_workload(wl))
