@@ -89,6 +89,34 @@ def test_paper_grid_opg_64x64x1024():
             assert rel_l2(a.cpu().numpy(), r.numpy()) < 1e-5, (m, f)
 
 
+@pytest.mark.parametrize("schedule", [(0, 0, 0, 0), (0, 1, 1, 2), (1, 1, 0, 3)])
+def test_largest_grid_is_an_exact_shift(schedule):
+    """The largest grid the engine takes (256 x 256 x 4096: 2^28 values, 2 GiB
+    per field, the largest byte offsets of the fields' buffer addressing) with
+    only a group delay of one tau cell per step (delta dz = dt): each field is
+    its entrance field shifted by one cell per step along tau, exactly up to
+    the transforms' rounding.  Two fields with opposite delays, three steps,
+    literal, merged and fused schedules (x and y linear passes on
+    512-thread blocks in the last two)."""
+    order, merge, fuse, wide = schedule
+    nx, ny, nt, nsteps = 256, 256, 4096, 3
+    fs = [inputs.FieldSpec(kappa=0.0, delay=1.0), inputs.FieldSpec(kappa=0.0, delay=-1.0)]
+    wl = inputs.Workload("shift", nx, ny, nt, 2, nsteps, 1.0, fs)
+    gen = torch.Generator(device=DEV).manual_seed(5)
+    init = [torch.randn(nt, ny, nx, dtype=torch.complex64, device=DEV, generator=gen) for _ in range(2)]
+    fields = [a.clone() for a in init]
+    plan = brahms.Plan(nx, ny, nt, 2, brahms.params_from_workload(wl))
+    plan.set_schedule(order, 0, merge, fuse, 0, wide)
+    plan.bind(fields)
+    plan.step(nsteps)
+    torch.cuda.synchronize()
+    plan.destroy()
+    for f, a, shift in zip(fields, init, (nsteps, -nsteps)):
+        want = torch.roll(a, shifts=shift, dims=0)
+        err = float(torch.linalg.vector_norm(f - want) / torch.linalg.vector_norm(want))
+        assert err < 2e-6, (schedule, shift, err)
+
+
 @pytest.mark.parametrize("order", [0, 1])
 def test_long_tau_fused_graph_is_bitwise_eager(order):
     """Fused step pairs on a long tau axis: 64-step graph replays give the
