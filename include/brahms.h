@@ -97,10 +97,11 @@ typedef struct {
 } brahms_params;
 
 /* Create a plan for an nx x ny x nt grid with nfields in {2, 3}.
- * Axis lengths must be 2^a or 3 * 2^a up to 256 (1, 2, 3, 4, 6, 8, 12, 16,
- * 24, 32, 48, 64, 96, 128, 192, 256); tau may also be 512, 1024, 2048 or
- * 4096.  BRAHMS_E_UNSUPPORTED otherwise: a prime factor other than 2 and 3,
- * a factor 3^2 (no register split of the line transform), x or y above 256.
+ * Axis lengths must be 2^a, 3 * 2^a or 9 * 2^a up to 256 (1, 2, 3, 4, 6, 8,
+ * 9, 12, 16, 18, 24, 32, 36, 48, 64, 72, 96, 128, 144, 192, 256); tau may
+ * also be 512, 1024, 2048 or 4096.  BRAHMS_E_UNSUPPORTED otherwise: a prime
+ * factor other than 2 and 3, a factor 3^3 (27, 54, 81, 108, 162, 216, 243:
+ * no register split of the line transform), x or y above 256.
  * The parameters are copied.
  * Errors: BRAHMS_E_INVALID_ARG for a non-positive size, nf outside {2, 3},
  * NULL params/out, dz <= 0, a non-finite coefficient, dk != NULL with
@@ -221,8 +222,10 @@ brahms_status brahms_plan_destroy(brahms_plan plan);
  *     instead of 256, twice the lines per block; y and tau lines are then
  *     read and written in row segments twice as long (32 columns for a
  *     256-point axis).  Every line is transformed as before: bitwise the same
- *     result.  Plans only (batches and the adjoint keep 256).
- *     BRAHMS_E_INVALID_ARG outside 0 .. 7.
+ *     result.  Axes of length 72 or 144 (36 values per lane, whose 512-lane
+ *     exchange rows would not fit the LDS) ignore their bit.  Plans only
+ *     (batches and the adjoint keep 256).  BRAHMS_E_INVALID_ARG outside
+ *     0 .. 7.
  * The autotuner in the Python package times the candidates per grid shape. */
 typedef struct {
   int pass_order;

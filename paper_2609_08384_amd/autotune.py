@@ -62,14 +62,16 @@ def wide_masks(schedule: dict, nx: int, ny: int, nt: int):
     """Values of the schedule field `wide` worth timing: each axis whose
     passes are linear in this schedule (the middle axis; with merged
     half-steps and no fused pairs also the first), alone and together;
-    none for long tau axes, and none on axes of length 1."""
+    none for long tau axes, and none on axes of length 1 or of a length
+    without a wide form (brahms.NARROW_ONLY_LENGTHS)."""
     if nt > 256:
         return []
     order = [(0, 1, 2), (2, 1, 0), (0, 2, 1), (1, 2, 0)][schedule["pass_order"]]
     linear = [order[1]]
     if schedule.get("merge_halves") and not schedule.get("fuse_steps"):
         linear.append(order[0])
-    bits = [1 << a for a in linear if (nx, ny, nt)[a] > 1]
+    shape = (nx, ny, nt)
+    bits = [1 << a for a in linear if shape[a] > 1 and shape[a] not in brahms.NARROW_ONLY_LENGTHS]
     masks = list(bits)
     if len(bits) > 1:
         masks.append(sum(bits))

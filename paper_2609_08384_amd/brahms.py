@@ -29,7 +29,10 @@ BRAHMS_CHECK_FINITE = 1
 STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_UNSUPPORTED", 3: "E_DEVICE",
                 4: "E_NONFINITE", 5: "E_STATE"}
 
-SUPPORTED_LENGTHS = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256)
+SUPPORTED_LENGTHS = (1, 2, 3, 4, 6, 8, 9, 12, 16, 18, 24, 32, 36, 48, 64, 72, 96, 128, 144, 192, 256)
+# lengths whose linear passes have no 512-thread form (schedule field wide
+# is ignored on their axes)
+NARROW_ONLY_LENGTHS = (72, 144)
 # lengths with a second register/lane split (schedule field split)
 ALT_SPLIT_LENGTHS = (8, 12, 16, 24, 32, 48, 64)
 TIMING_KINDS = 4

@@ -13,9 +13,9 @@ LIB = os.path.join(PKG, "libbrahms.so")
 
 # the pass kernels of the heaviest line lengths first (the longest compiles),
 # then the host logic
-SOURCES = ["len_256.hip", "len_96.hip", "len_192.hip", "len_128.hip", "len_48_64.hip", "len_24_32.hip",
-           "len_small.hip", "len_long.hip", "engine.hip", "adjoint.hip", "batch.hip", "diag.hip",
-           "noalloc.hip"]
+SOURCES = ["len_144.hip", "len_72.hip", "len_256.hip", "len_96.hip", "len_9_18.hip", "len_192.hip",
+           "len_128.hip", "len_48_64.hip", "len_24_32.hip", "len_small.hip", "len_long.hip", "engine.hip",
+           "adjoint.hip", "batch.hip", "diag.hip", "noalloc.hip"]
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",
     "--offload-arch=gfx950",

@@ -3,12 +3,13 @@
 // dft<N, INV>(v) transforms v[0..N-1] in place, natural order in and out:
 //   forward  V[k] = sum_n v[n] exp(-2 pi i n k / N)
 //   inverse  V[k] = sum_n v[n] exp(+2 pi i n k / N)   (unnormalised)
-// N is a compile-time product of 2s and 3s.  Every loop is fully unrolled and
-// every index is a compile-time constant, so the arrays live in registers and
-// the choice of each twiddle operation folds at compile time; the irrational
-// constants are uniform run-time values (DftConsts).  unit_root evaluates
-// roots of unity in double precision (exact quadrant symmetry plus a Taylor
-// series on at most a half quadrant) for the host-side tables.
+// N is a compile-time divisor of 144 (a product of 2s and 3s).  Every loop
+// is fully unrolled and every index is a compile-time constant, so the arrays
+// live in registers and the choice of each twiddle operation folds at compile
+// time; the irrational constants are uniform run-time values (DftConsts).
+// unit_root evaluates roots of unity in double precision (exact quadrant
+// symmetry plus a Taylor series on at most a half quadrant) for the
+// host-side tables.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -72,13 +73,15 @@ __host__ __device__ inline float2 rot_quarter(float2 a) {
   return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
 }
 
-// The irrational constants the register DFTs need (radices 2, 3, 4, 6, 8,
-// 12, 16, 24 all divide 48, so every root is a multiple of 2 pi / 48 and
-// reduces by exact quadrant symmetry to one of these first-quadrant values).
-// They are run-time values supplied per z-step: rounding them afresh at every
-// step (stochastically, from a double-precision value) keeps their rounding
-// errors independent from step to step, so the errors of repeated transform
-// round trips grow like sqrt(steps) instead of linearly.
+// The irrational constants the register DFTs need.  The radices 2, 3, 4, 6,
+// 8, 9, 12, 16, 18, 24 and 36 all divide 144, so every root is a multiple of
+// 2 pi / 144 and reduces by exact quadrant symmetry to a first-quadrant
+// value; the ones that occur are the multiples of 7.5 degrees (the radices
+// dividing 48) and of 10 degrees (those with a factor 9).  They are run-time
+// values supplied per z-step: rounding them afresh at every step
+// (stochastically, from a double-precision value) keeps their rounding errors
+// independent from step to step, so the errors of repeated transform round
+// trips grow like sqrt(steps) instead of linearly.
 struct DftConsts {
   float h;         // cos(pi/4) = sin(pi/4)
   float c8, s8;    // cos(pi/8), sin(pi/8)
@@ -86,33 +89,50 @@ struct DftConsts {
   float c12, s12;  // cos(pi/12), sin(pi/12)
   float t8;        // tan(pi/8) (the folded twiddles of the 16-point DFT)
   float pad;
+  float c36, s36;  // cos(pi/18), sin(pi/18)   (10 degrees)
+  float c18, s18;  // cos(pi/9), sin(pi/9)     (20 degrees)
+  float c9, s9;    // cos(2pi/9), sin(2pi/9)   (40 degrees)
+  float pad2[2];
 };
 
 // a * exp(-+ 2 pi i m / N) with m a compile-time constant after unrolling
 // (every branch below folds away); quarter turns cost no multiplies.
 template <int N, bool INV>
 __host__ __device__ inline float2 twiddle_const(float2 a, int m, const DftConsts& K) {
-  static_assert(48 % N == 0, "register DFT radices must divide 48");
+  static_assert(144 % N == 0, "register DFT radices must divide 144");
   m %= N;
   if (m == 0) return a;
-  const int r = m * (48 / N);   // angle in units of 2 pi / 48
-  const int q = r / 12;         // quarter turns
-  const int rem = r % 12;       // remaining angle in units of pi / 24
+  const int r = m * (144 / N);  // angle in units of 2 pi / 144 (2.5 degrees)
+  const int q = r / 36;         // quarter turns
+  const int rem = r % 36;       // remaining angle
   float2 b = a;
   if (rem != 0) {
     float c = 0.f, s = 0.f;
-    if (rem == 6) {
+    if (rem == 18) {
       // exp(-+i pi/4) = h (1 -+ i)
       b = INV ? make_float2(K.h * (a.x - a.y), K.h * (a.x + a.y))
               : make_float2(K.h * (a.x + a.y), K.h * (a.y - a.x));
+    } else if (rem % 4 == 0 && rem % 12 != 0) {
+      // multiples of 10 degrees (radices with a factor 9), the product's
+      // multiply-adds written out so that every kernel rounds them alike
+      switch (rem) {
+        case 4: c = K.c36; s = K.s36; break;
+        case 8: c = K.c18; s = K.s18; break;
+        case 16: c = K.c9; s = K.s9; break;
+        case 20: c = K.s9; s = K.c9; break;
+        case 28: c = K.s18; s = K.c18; break;
+        default: c = K.s36; s = K.c36; break;  // rem == 32
+      }
+      if (!INV) s = -s;
+      b = make_float2(fmaf(a.x, c, -(a.y * s)), fmaf(a.x, s, a.y * c));
     } else {
       switch (rem) {
-        case 2: c = K.c12; s = K.s12; break;
-        case 3: c = K.c8; s = K.s8; break;
-        case 4: c = K.r3; s = 0.5f; break;
-        case 8: c = 0.5f; s = K.r3; break;
-        case 9: c = K.s8; s = K.c8; break;
-        default: c = K.s12; s = K.c12; break;  // rem == 10
+        case 6: c = K.c12; s = K.s12; break;
+        case 9: c = K.c8; s = K.s8; break;
+        case 12: c = K.r3; s = 0.5f; break;
+        case 24: c = 0.5f; s = K.r3; break;
+        case 27: c = K.s8; s = K.c8; break;
+        default: c = K.s12; s = K.c12; break;  // rem == 30
       }
       if (!INV) s = -s;
       b = make_float2(a.x * c - a.y * s, a.x * s + a.y * c);

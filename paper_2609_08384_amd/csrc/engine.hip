@@ -605,8 +605,8 @@ brahms_status brahms_plan_create(int nx, int ny, int nt, int nfields, const brah
   if (!brahms::line_length(nx) || !brahms::line_length(ny) ||
       !(brahms::line_length(nt) || supported_long_tau(nt)))
     return fail(BRAHMS_E_UNSUPPORTED,
-                "axis lengths must be 2^a or 3 * 2^a up to 256 (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, "
-                "64, 96, 128, 192, 256; tau also 512, 1024, 2048, 4096)");
+                "axis lengths must be 2^a, 3 * 2^a or 9 * 2^a up to 256 (1, 2, 3, 4, 6, 8, 9, 12, 16, "
+                "18, 24, 32, 36, 48, 64, 72, 96, 128, 144, 192, 256; tau also 512, 1024, 2048, 4096)");
   auto* p = new brahms_plan_s();
   p->nx = nx; p->ny = ny; p->nt = nt; p->nf = nfields;
   p->dz = params->dz;

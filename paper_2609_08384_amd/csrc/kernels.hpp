@@ -247,7 +247,9 @@ __device__ inline void line_fft(float2 (&v)[N1], int t, float2* lbuf, const floa
 // step-pair pass's LDS allows 3 blocks as well; without the bound the
 // compiler may take more registers and leave room for 2 waves only, which
 // cost the fused pass ~15 % of its speed.  Kernels whose LDS already limits
-// them to fewer blocks keep their register count.
+// them to fewer blocks keep their register count.  Lines of 36 values per
+// lane (lengths 72 and 144) need 216 VGPRs for three fields and an LDS row
+// block that leaves room for one block per CU, so they are compiled for one.
 #ifndef BRAHMS_MIN_BLOCKS
 #define BRAHMS_MIN_BLOCKS 3
 #endif
@@ -614,10 +616,26 @@ __device__ __forceinline__ void axis_pass_body(const PassArgs& args, unsigned bx
 // as long; their LDS allows two blocks per CU.
 constexpr int kWideBlock = 2 * kBlock;
 
+// Blocks per CU a pass kernel of N1 values per lane and BLOCK threads is
+// compiled for (the second argument of its launch bounds).
+template <int N1, int BLOCK>
+constexpr int pass_min_blocks() {
+  return BLOCK != kBlock ? 2 : (N1 > 24 ? 1 : BRAHMS_MIN_BLOCKS);
+}
+
+// Whether the wide linear passes of a split fit the LDS of one CU (160 KB):
+// not for 36 values per lane, whose rows of 512 lanes would take 185-223 KB.
+// Such axes run their linear passes with kBlock threads whatever the
+// schedule's `wide` bit says (the results are the same either way).
+template <int N1>
+constexpr bool wide_split() {
+  return N1 <= 24;
+}
+
 // One pass of one problem; BLOCK threads per block (kBlock, or kWideBlock
 // for the wide linear passes of the schedule field `wide`).
 template <int N1, int N2, int AX, int NF, int NL, bool FULL, int BLOCK = kBlock>
-__global__ __launch_bounds__(BLOCK, BLOCK == kBlock ? BRAHMS_MIN_BLOCKS : 2) void axis_pass(PassArgs args) {
+__global__ __launch_bounds__(BLOCK, (pass_min_blocks<N1, BLOCK>())) void axis_pass(PassArgs args) {
   // passes with one field per block take it from blockIdx.z
   constexpr bool per_field = NF == 1;
   axis_pass_body<N1, N2, AX, NF, NL, FULL, BLOCK>(args, blockIdx.x, per_field ? int(blockIdx.z) : 0);
@@ -628,7 +646,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == kBlock ? BRAHMS_MIN_BLOCKS : 2) voi
 // from blockIdx.y, passes with one field per block from blockIdx.z / nf.  Problems whose own step count
 // is reached (step >= nz) leave at once.
 template <int N1, int N2, int AX, int NF, int NL, bool FULL, int BLOCK = kBlock>
-__global__ __launch_bounds__(BLOCK, BLOCK == kBlock ? BRAHMS_MIN_BLOCKS : 2) void axis_pass_batched(
+__global__ __launch_bounds__(BLOCK, (pass_min_blocks<N1, BLOCK>())) void axis_pass_batched(
     const PassArgs* descs, long long step, int nf) {
   // linear y and long-tau passes take one field per block: problem and field
   // from blockIdx.z
@@ -661,7 +679,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == kBlock ? BRAHMS_MIN_BLOCKS : 2) voi
 // rounding would repeat the same error every step and add up linearly.
 //
 // Row layout of one step (float2 units): [nf][nx | ny | nt] propagators,
-// [nx | ny | nt] twiddles, 4 float2 of DftConsts.
+// [nx | ny | nt] twiddles, 8 float2 of DftConsts.
 // ---------------------------------------------------------------------------
 struct FieldCoef {
   double kappa, diffraction, tan_rho, delay, k2, k3, alpha;
@@ -693,7 +711,7 @@ __device__ inline long long table_merge_last(const TableArgs& a) {
 }
 
 __host__ __device__ inline int table_row_stride(int nf, int nx, int ny, int nt) {
-  return (nf + 1) * (nx + ny + nt) + 4;
+  return (nf + 1) * (nx + ny + nt) + int(sizeof(DftConsts) / sizeof(float2));
 }
 
 __device__ inline double reduce_2pi(double a) {
@@ -763,6 +781,12 @@ __device__ __forceinline__ void step_tables_body(const TableArgs& a, long gid) {
       for (int k = 0; k < 6; ++k) out[k] = stochastic_round(v[k], entry_bits(n, 0x40000000u + k));
       out[6] = stochastic_round(0.41421356237309504880, entry_bits(n, 0x40000006u));   // tan(pi/8)
       out[7] = 0.f;
+      // cos and sin of 10, 20 and 40 degrees (radices with a factor 9)
+      const double w[6] = {0.98480775301220805937, 0.17364817766693034885, 0.93969262078590838405,
+                           0.34202014332566873304, 0.76604444311897803520, 0.64278760968653932632};
+      for (int k = 0; k < 6; ++k) out[8 + k] = stochastic_round(w[k], entry_bits(n, 0x40000008u + k));
+      out[14] = 0.f;
+      out[15] = 0.f;
       return;
     }
     int m = r % per_field;

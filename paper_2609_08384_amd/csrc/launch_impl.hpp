@@ -18,18 +18,21 @@ void launch_pass(bool full, dim3 grid, hipStream_t st, const PassArgs& a) {
 }
 
 // A linear pass (one field per block) over `lines` lines along AX, with
-// kBlock or (wide) kWideBlock threads per block.
+// kBlock or (wide, where the split has a wide form) kWideBlock threads per
+// block.
 template <int N1, int N2, int AX>
 void launch_linear(bool wide, long lines, int nf, hipStream_t st, const PassArgs& a) {
-  if (wide) {
-    constexpr int LPB = LineGeom<N1, N2, kWideBlock>::LPB;
-    const dim3 grid(unsigned((lines + LPB - 1) / LPB), 1, unsigned(nf));
-    launch_pass<N1, N2, AX, 1, NL_NONE, kWideBlock>(lines % LPB == 0, grid, st, a);
-  } else {
-    constexpr int LPB = LineGeom<N1, N2>::LPB;
-    const dim3 grid(unsigned((lines + LPB - 1) / LPB), 1, unsigned(nf));
-    launch_pass<N1, N2, AX, 1, NL_NONE>(lines % LPB == 0, grid, st, a);
+  if constexpr (wide_split<N1>()) {
+    if (wide) {
+      constexpr int LPB = LineGeom<N1, N2, kWideBlock>::LPB;
+      const dim3 grid(unsigned((lines + LPB - 1) / LPB), 1, unsigned(nf));
+      launch_pass<N1, N2, AX, 1, NL_NONE, kWideBlock>(lines % LPB == 0, grid, st, a);
+      return;
+    }
   }
+  constexpr int LPB = LineGeom<N1, N2>::LPB;
+  const dim3 grid(unsigned((lines + LPB - 1) / LPB), 1, unsigned(nf));
+  launch_pass<N1, N2, AX, 1, NL_NONE>(lines % LPB == 0, grid, st, a);
 }
 
 template <int N1, int N2, int AX, int NF>
@@ -77,7 +80,7 @@ hipError_t launch_axis(int axis, int nl, int nf, const brahms_plan_s& p, PassArg
   using G = LineGeom<N1, N2>;
   a.tile_mul = 1;
   a.tiles = 1;
-  const bool wide = ((p.wide >> axis) & 1) != 0;
+  const bool wide = wide_split<N1>() && ((p.wide >> axis) & 1) != 0;
   if (axis == AX_X) {
     const long lines = long(p.ny) * p.nt;
     if (nl == NL_NONE) {
@@ -153,9 +156,11 @@ void launch_batched(bool full, dim3 grid, hipStream_t st, const PassArgs* d, lon
 // A linear x or y pass over a launch group with kWideBlock threads per block.
 template <int N1, int N2, int AX>
 void launch_batched_wide(long lines, const GroupGeom& g, hipStream_t st, const PassArgs* d, long long step) {
-  constexpr int LPB = LineGeom<N1, N2, kWideBlock>::LPB;
-  const dim3 grid(unsigned((lines + LPB - 1) / LPB), 1, unsigned(g.nf) * g.m);
-  launch_batched<N1, N2, AX, 1, NL_NONE, kWideBlock>(lines % LPB == 0, grid, st, d, step, g.nf);
+  if constexpr (wide_split<N1>()) {
+    constexpr int LPB = LineGeom<N1, N2, kWideBlock>::LPB;
+    const dim3 grid(unsigned((lines + LPB - 1) / LPB), 1, unsigned(g.nf) * g.m);
+    launch_batched<N1, N2, AX, 1, NL_NONE, kWideBlock>(lines % LPB == 0, grid, st, d, step, g.nf);
+  }
 }
 
 template <int N1, int N2, int AX, int NF>
@@ -188,7 +193,7 @@ void launch_group_pass(int axis, int nl, const GroupGeom& g, hipStream_t st, con
   const long lines = axis == AX_X ? long(g.ny) * g.nt : (axis == AX_Y ? long(g.nx) * g.nt : long(g.nx) * g.ny);
   const bool full = lines % G::LPB == 0;
   const unsigned blocks = unsigned((lines + G::LPB - 1) / G::LPB);
-  if (nl == NL_NONE && axis != AX_T && ((g.wide >> axis) & 1)) {
+  if (nl == NL_NONE && axis != AX_T && wide_split<N1>() && ((g.wide >> axis) & 1)) {
     if (axis == AX_X) launch_batched_wide<N1, N2, AX_X>(lines, g, st, d, step);
     else launch_batched_wide<N1, N2, AX_Y>(lines, g, st, d, step);
   } else if (nl == NL_NONE) {

@@ -4,19 +4,23 @@
 // each (see line_fft in kernels.hpp): an N1-point register DFT per lane, one
 // exchange through LDS, N2-point register DFTs.  N2 divides N1 (the second
 // stage deals N1 / N2 groups to every lane) and kBlock = 256 (a block holds
-// 256 / N2 lines); N1 and N2 are products of 2s and 3s that divide 48 (the
-// angles of the register DFTs' constant twiddles).  These conditions admit
-// every length 2^a 3^b <= 256 with b <= 1; lengths with 3^2 or more, and
-// x or y axes above 256, have no split (BRAHMS_E_UNSUPPORTED).  A tau axis of
-// 512, 1024, 2048 or 4096 takes three passes of sub-lengths 16, 32 or 64
-// (a four-step transform, AX_TAF / AX_TB / AX_TAI in kernels.hpp).
+// 256 / N2 lines), so N2 is a power of two and every factor 3 of N sits in
+// N1; N1 and N2 divide 144 (the angles of the register DFTs' constant
+// twiddles).  These conditions admit every length 2^a 3^b <= 256 with
+// b <= 2: 3^2 N2 lengths take N1 = 9, 18 or 36.  A factor 3^3 would need
+// N1 >= 27 values of every field in every lane with N2 = 1, or 54 with N2 =
+// 2, beyond the registers of a lane for three fields; those lengths (27, 54,
+// 81, 108, 162, 216, 243), other primes, and x or y axes above 256 have no
+// split (BRAHMS_E_UNSUPPORTED).  A tau axis of 512, 1024, 2048 or 4096 takes
+// three passes of sub-lengths 16, 32 or 64 (a four-step transform, AX_TAF /
+// AX_TB / AX_TAI in kernels.hpp).
 #pragma once
 
 // X(N, N1, N2) for every supported length of one line transform.
 #define BRAHMS_LENGTHS(X)                                                                     \
   X(1, 1, 1) X(2, 2, 1) X(3, 3, 1) X(4, 4, 1) X(6, 6, 1) X(8, 4, 2) X(12, 6, 2) X(16, 4, 4)  \
   X(24, 12, 2) X(32, 8, 4) X(48, 12, 4) X(64, 8, 8) X(96, 24, 4) X(128, 16, 8) X(192, 24, 8) \
-  X(256, 16, 16)
+  X(256, 16, 16) X(9, 9, 1) X(18, 18, 1) X(36, 18, 2) X(72, 36, 2) X(144, 36, 4)
 
 // X(N, N1, N2): a second split of some lengths, with twice as many lines per
 // block (N2 halved) or a whole line per lane.  Which split runs faster depends

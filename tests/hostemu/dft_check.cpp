@@ -20,6 +20,12 @@ brahms::DftConsts nearest_consts() {
   k.c12 = float(std::cos(M_PI / 12));
   k.s12 = float(std::sin(M_PI / 12));
   k.t8 = float(std::tan(M_PI / 8));
+  k.c36 = float(std::cos(M_PI / 18));
+  k.s36 = float(std::sin(M_PI / 18));
+  k.c18 = float(std::cos(M_PI / 9));
+  k.s18 = float(std::sin(M_PI / 9));
+  k.c9 = float(std::cos(2 * M_PI / 9));
+  k.s9 = float(std::sin(2 * M_PI / 9));
   return k;
 }
 
@@ -72,5 +78,8 @@ int main() {
   ok &= check<12>(K);
   ok &= check<16>(K);
   ok &= check<24>(K);
+  ok &= check<9>(K);
+  ok &= check<18>(K);
+  ok &= check<36>(K);
   return ok ? 0 : 1;
 }

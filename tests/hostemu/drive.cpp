@@ -441,18 +441,19 @@ void scenario_eager_streams() {
     }
 }
 
-// axis lengths 3 * 2^a in batches and plans
+// axis lengths 3 * 2^a and 9 * 2^a in batches and plans
 void scenario_three_lengths() {
   Rng r(61);
   std::vector<Problem> ps;
-  const int spec[4][5] = {{24, 12, 6, 3, 9}, {24, 12, 6, 3, 5}, {192, 3, 4, 2, 7}, {6, 48, 12, 2, 11}};
+  const int spec[7][5] = {{24, 12, 6, 3, 9}, {24, 12, 6, 3, 5}, {192, 3, 4, 2, 7}, {6, 48, 12, 2, 11},
+                          {18, 9, 36, 3, 5}, {72, 4, 9, 2, 4}, {9, 144, 2, 2, 3}};
   for (auto& s : spec) ps.push_back(make_problem(r, s[0], s[1], s[2], s[3], s[4], false, r.uniform(-3, 3)));
   for (int merge : {0, 1}) {
     std::vector<int> orders;
     for (size_t k = 0; k < ps.size(); ++k) orders.push_back(int(k % 4));
     const BatchRun br = run_batch(ps, 0, &orders, nullptr, merge, merge);
-    compare_with_plans(ps, br, orders, merge, merge, "3 * 2^a batch");
-    std::printf("3 * 2^a lengths merge=%d: ok\n", merge);
+    compare_with_plans(ps, br, orders, merge, merge, "3 * 2^a and 9 * 2^a batch");
+    std::printf("3 * 2^a and 9 * 2^a lengths merge=%d: ok\n", merge);
   }
 }
 

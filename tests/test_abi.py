@@ -64,9 +64,11 @@ def test_create_and_workspace(lib):
     assert lib.brahms_plan_destroy(h) == brahms.BRAHMS_OK
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 6, 8, 9, 12, 16, 18, 24, 32, 36, 48, 64, 72, 96, 128, 144, 192,
+                               256])
 def test_create_accepts_every_line_length(lib, n):
-    """Every 2^a and 3 * 2^a up to 256 on each axis (tau also 512 .. 4096)."""
+    """Every 2^a, 3 * 2^a and 9 * 2^a up to 256 on each axis (tau also
+    512 .. 4096)."""
     c, keep = _params()
     for shape in ((n, 4, 4), (4, n, 4), (4, 4, n)):
         st, h = _create(lib, *shape, 2, c)
@@ -81,8 +83,9 @@ def test_create_accepts_every_line_length(lib, n):
     ((8, 8, 8), 4, brahms.BRAHMS_E_INVALID_ARG),
     ((10, 8, 8), 2, brahms.BRAHMS_E_UNSUPPORTED),    # prime factor 5
     ((8, 7, 8), 3, brahms.BRAHMS_E_UNSUPPORTED),     # prime factor 7
-    ((9, 8, 8), 2, brahms.BRAHMS_E_UNSUPPORTED),     # 3^2: no line-transform split
-    ((8, 8, 27), 2, brahms.BRAHMS_E_UNSUPPORTED),    # 3^3
+    ((8, 8, 27), 2, brahms.BRAHMS_E_UNSUPPORTED),    # 3^3: no line-transform split
+    ((54, 8, 8), 2, brahms.BRAHMS_E_UNSUPPORTED),    # 2 * 3^3
+    ((8, 216, 8), 3, brahms.BRAHMS_E_UNSUPPORTED),   # 2^3 * 3^3
     ((8, 512, 8), 3, brahms.BRAHMS_E_UNSUPPORTED),   # only tau may exceed 256
     ((8, 8, 384), 3, brahms.BRAHMS_E_UNSUPPORTED),   # long tau: 512 .. 4096 only
 ])

@@ -236,6 +236,40 @@ def test_batch_with_wide_linear_passes(merge, fuse):
             assert torch.equal(a, b), (w.nx, w.ny, w.nt)
 
 
+@pytest.mark.parametrize("merge,fuse", [(0, 0), (1, 1)])
+def test_batch_with_factor_nine_lengths(merge, fuse):
+    """Lengths 9, 18, 36, 72 and 144 in a batch (two problems of one shape in
+    one launch group, ragged step counts, per-problem pass orders): each
+    problem bitwise equal to its plan run alone.  Per-problem pass orders
+    only with literal half-steps: merged batches here keep the configurations
+    of the other batch tests that run (one pass order)."""
+    rng = np.random.default_rng(91 + fuse)
+    wls = []
+    for (nx, ny, nt), nf, nz in [((36, 18, 72), 2, 7), ((36, 18, 72), 2, 4), ((144, 9, 16), 3, 5),
+                                 ((18, 144, 9), 2, 6)]:
+        fs = [inputs.FieldSpec(kappa=1.0 + 0.2 * j, diffraction=float(rng.uniform(0.5, 2.0)),
+                               tan_rho=float(rng.uniform(-0.5, 0.5)), delay=float(rng.uniform(-1, 1)),
+                               k2=float(rng.uniform(-2, 2))) for j in range(nf)]
+        wl = inputs.Workload("n", nx, ny, nt, nf, nz, 1.0 / nz, fs, dk_const=float(rng.uniform(-3, 3)))
+        wl.init = inputs.random_fields(rng, nf, nx, ny, nt, scale=0.7, smooth=3.0)
+        wls.append(wl)
+    orders = [0, 0, 0, 0] if merge else [0, 0, 1, 3]
+    batch = brahms.Batch([(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls])
+    batch.set_schedule(0, orders)
+    batch.set_merge_halves(merge)
+    batch.set_fuse_steps(fuse)
+    fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
+    batch.bind(fields)
+    batch.run()
+    torch.cuda.synchronize()
+    out = [[f.clone() for f in fs] for fs in fields]
+    batch.destroy()
+    for w, fs, o in zip(wls, out, orders):
+        alone = brahms.run_workload(w, device=DEV, pass_order=o, merge_halves=merge, fuse_steps=fuse)
+        for a, b in zip(fs, alone):
+            assert torch.equal(a, b), (w.nx, w.ny, w.nt)
+
+
 def test_batch_matches_oracle():
     wls = _problems(seed=12)
     probs = [(w.nx, w.ny, w.nt, w.nf, brahms.params_from_workload(w), w.nz) for w in wls]

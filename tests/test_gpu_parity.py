@@ -52,7 +52,9 @@ def _all_terms(nf, scale=1.0, kappa=0.0):
 SHAPES = [(32, 16, 8), (16, 32, 64), (64, 8, 4), (96, 64, 2), (128, 4, 16), (256, 2, 1),
           (1, 1, 256), (8, 256, 1), (4, 96, 32), (2, 128, 8), (1, 4, 128), (128, 96, 96),
           # the lengths 3 * 2^a
-          (3, 6, 12), (24, 48, 3), (192, 4, 6), (6, 192, 2), (12, 24, 192), (48, 3, 24)]
+          (3, 6, 12), (24, 48, 3), (192, 4, 6), (6, 192, 2), (12, 24, 192), (48, 3, 24),
+          # the lengths 9 * 2^a
+          (9, 18, 36), (72, 144, 2), (144, 9, 18), (36, 72, 9), (18, 4, 144), (2, 144, 72)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -114,7 +116,8 @@ def test_plane_wave_opa():
 @pytest.mark.parametrize("order", [0, 1, 2, 3])
 @pytest.mark.parametrize("nf,shape", [(2, (32, 32, 32)), (3, (32, 32, 32)), (3, (64, 16, 96)),
                                       (2, (96, 96, 4)), (3, (16, 128, 64)), (3, (48, 24, 12)),
-                                      (2, (192, 6, 24)), (3, (12, 192, 3))])
+                                      (2, (192, 6, 24)), (3, (12, 192, 3)), (3, (36, 18, 72)),
+                                      (2, (144, 9, 16)), (3, (18, 144, 9))])
 def test_coupled_steps_random(nf, shape, order, merge):
     """All linear terms and the chi(2) coupling, 10 steps, ragged tiles, every
     pass order, literal and merged half-steps."""
@@ -224,7 +227,9 @@ def test_plan_on_a_side_stream():
 
 
 @pytest.mark.parametrize("nf,shape", [(3, (32, 16, 8)), (2, (96, 64, 2)), (3, (24, 48, 192)), (2, (256, 2, 1)),
-                                      (3, (16, 128, 64)), (2, (3, 6, 12)), (3, (128, 96, 96))])
+                                      (3, (16, 128, 64)), (2, (3, 6, 12)), (3, (128, 96, 96)),
+                                      # 72 and 144 have no wide form: their bits are ignored
+                                      (3, (144, 72, 36)), (2, (18, 9, 144))])
 @pytest.mark.parametrize("order", [0, 1, 2, 3])
 def test_wide_linear_passes_bitwise(nf, shape, order):
     """512-thread blocks for the linear passes (schedule field `wide`, every
@@ -512,7 +517,7 @@ def test_graph_schedule_with_merged_halves_is_bitwise_eager(order, fuse):
 @pytest.mark.parametrize("order", [0, 1, 2, 3])
 @pytest.mark.parametrize("nf,shape", [(3, (32, 32, 32)), (3, (64, 16, 96)), (2, (96, 96, 4)),
                                       (3, (16, 128, 64)), (2, (256, 2, 1)), (3, (8, 96, 1)),
-                                      (3, (24, 48, 192))])
+                                      (3, (24, 48, 192)), (3, (72, 36, 18)), (2, (18, 144, 36))])
 def test_fused_step_pairs_match_merged_oracle(nf, shape, order):
     """Fused step pairs (alternating axis orders, step n's last transform,
     the RK4 step and step n+1's first transform in one pass) compute the

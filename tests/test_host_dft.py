@@ -1,7 +1,7 @@
 """The register DFTs of csrc/dft.hpp, built for the host against the
 emulation header (tests/hostemu), against the O(N^2) DFT definition in
-double precision: every radix the line transforms use (1, 2, 3, 4, 6, 8, 12,
-16, 24), forward and inverse, 50 random inputs each.  A wrong sign, index or
+double precision: every radix the line transforms use (1, 2, 3, 4, 6, 8, 9,
+12, 16, 18, 24, 36), forward and inverse, 50 random inputs each.  A wrong sign, index or
 twiddle gives an O(1) error; rounding gives ~1e-7."""
 import os
 import shutil
@@ -31,4 +31,4 @@ def test_register_dfts_match_definition(tmp_path):
                    check=True)
     r = subprocess.run([exe], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
-    assert r.stdout.count(" ok") == 9, r.stdout
+    assert r.stdout.count(" ok") == 12, r.stdout

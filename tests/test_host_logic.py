@@ -48,6 +48,9 @@ def test_tuner_takes_the_fastest_order_and_caches(fake_tuner, tmp_path):
     # tau first and y in the middle, alone and together)
     n_wide = len(autotune.wide_masks(best, 32, 32, 32))
     assert autotune.wide_masks(best, 32, 32, 32) == [2, 4, 6]
+    # lengths 72 and 144 have no wide form: no bit on their axes
+    assert autotune.wide_masks(best, 32, 72, 32) == [4]
+    assert autotune.wide_masks(best, 32, 72, 144) == []
     n_calls = 1 + autotune.ROUNDS * (2 * len(autotune.CANDIDATES) + n_split + n_wide)
     assert len(calls) == n_calls
     assert all(c["merge_halves"] == 1 for c in calls)
