@@ -37,7 +37,7 @@ def _pulse_fields(rng, nf, nx, ny, nt, scale):
 
 
 @pytest.mark.parametrize("shape", [(4, 2, 512), (2, 4, 1024), (1, 1, 2048), (2, 2, 4096), (8, 4, 1024),
-                                   (16, 2, 512)])
+                                   (16, 2, 512), (9, 2, 512), (3, 6, 1024)])
 def test_linear_long_tau(shape):
     """kappa = 0: one step is the linear step alone, all linear terms."""
     nx, ny, nt = shape
@@ -52,7 +52,8 @@ def test_linear_long_tau(shape):
 
 
 @pytest.mark.parametrize("nf,shape,profile,map_", [(3, (16, 8, 512), False, False), (2, (8, 8, 1024), True, True),
-                                                   (3, (4, 4, 4096), True, False), (2, (32, 4, 2048), False, True)])
+                                                   (3, (4, 4, 4096), True, False), (2, (32, 4, 2048), False, True),
+                                                   (3, (18, 9, 512), False, False), (2, (36, 4, 1024), True, True)])
 def test_coupled_long_tau(nf, shape, profile, map_):
     nx, ny, nt = shape
     rng = np.random.default_rng(nt + nf)

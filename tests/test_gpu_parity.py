@@ -54,7 +54,8 @@ SHAPES = [(32, 16, 8), (16, 32, 64), (64, 8, 4), (96, 64, 2), (128, 4, 16), (256
           # the lengths 3 * 2^a
           (3, 6, 12), (24, 48, 3), (192, 4, 6), (6, 192, 2), (12, 24, 192), (48, 3, 24),
           # the lengths 9 * 2^a
-          (9, 18, 36), (72, 144, 2), (144, 9, 18), (36, 72, 9), (18, 4, 144), (2, 144, 72)]
+          (9, 18, 36), (72, 144, 2), (144, 9, 18), (36, 72, 9), (18, 4, 144), (2, 144, 72),
+          (144, 144, 144)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
