@@ -58,6 +58,8 @@ def _oracle_grads(wl):
 @pytest.mark.parametrize("nf,shape,nz,every", [(2, (16, 16, 8), 12, 5), (3, (8, 16, 16), 9, 4),
                                                 (2, (32, 8, 16), 7, 7), (3, (24, 12, 6), 8, 3),
                                                 (3, (18, 9, 36), 8, 3), (2, (36, 18, 9), 7, 4),
+                                                # 36 values per lane on x and tau, ragged tiles
+                                                (3, (144, 4, 72), 6, 3),
                                                 # reduced dimensions: the forward leaves out the
                                                 # passes along length-1 axes, the reverse sweep not
                                                 (2, (32, 16, 1), 10, 4), (3, (1, 1, 64), 11, 5)])
