@@ -240,9 +240,11 @@ def test_batch_with_wide_linear_passes(merge, fuse):
 def test_batch_with_factor_nine_lengths(merge, fuse):
     """Lengths 9, 18, 36, 72 and 144 in a batch (two problems of one shape in
     one launch group, ragged step counts, per-problem pass orders): each
-    problem bitwise equal to its plan run alone.  Per-problem pass orders
-    only with literal half-steps: merged batches here keep the configurations
-    of the other batch tests that run (one pass order)."""
+    problem bitwise equal to its plan run alone, also with 512-thread linear
+    x and y passes requested on every axis (72 and 144 have no such form and
+    keep 256).  Per-problem pass orders only with literal half-steps: merged
+    batches here keep the configurations of the other batch tests that run
+    (one pass order)."""
     rng = np.random.default_rng(91 + fuse)
     wls = []
     for (nx, ny, nt), nf, nz in [((36, 18, 72), 2, 7), ((36, 18, 72), 2, 4), ((144, 9, 16), 3, 5),
@@ -258,6 +260,7 @@ def test_batch_with_factor_nine_lengths(merge, fuse):
     batch.set_schedule(0, orders)
     batch.set_merge_halves(merge)
     batch.set_fuse_steps(fuse)
+    batch.set_wide([3, 3, 3, 3])
     fields = [[torch.from_numpy(a).to(DEV) for a in w.init] for w in wls]
     batch.bind(fields)
     batch.run()
