@@ -535,7 +535,7 @@ def test_fused_step_pairs_match_merged_oracle(nf, shape, order):
 
 
 @pytest.mark.parametrize("nf,shape", [(3, (32, 32, 32)), (2, (96, 64, 2)), (3, (24, 48, 12)), (2, (64, 16, 128)),
-                                      (3, (256, 8, 4))])
+                                      (3, (256, 8, 4)), (3, (36, 72, 18)), (2, (144, 18, 9))])
 def test_tuned_plans_match_oracle(nf, shape, tmp_path, monkeypatch):
     """Whatever schedule the autotuner picks for a shape (pass order, graph,
     merged halves, fused pairs, register/lane splits, wide linear passes),
