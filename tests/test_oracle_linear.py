@@ -21,7 +21,7 @@ def _dft_matrix(n, sign):
     return np.exp(sign * 2j * np.pi * np.outer(j, j) / n)
 
 
-@pytest.mark.parametrize("shape", [(3, 6, 4), (2, 5, 3), (4, 4, 8)])
+@pytest.mark.parametrize("shape", [(3, 6, 4), (2, 5, 3), (4, 4, 8), (9, 18, 4), (2, 36, 9)])
 def test_linear_step_matches_bruteforce_dft(shape):
     """exp(L dz) = F^-1 diag(exp(Lambda dz)) F with F the plain O(n^2) DFT
     along each axis (forward sign -, inverse normalised by 1/n)."""
