@@ -374,14 +374,16 @@ brahms_status brahms_adjoint(brahms_plan plan, int nsteps, int checkpoint_every,
  *   the binding.  Errors: BRAHMS_E_INVALID_ARG outside 0 .. 3.
  * brahms_batch_set_streams: 1 (default) captures the run into one hipGraph
  *   whose launch groups run one after the other (largest first); 2 .. 4
- *   issues the run's launches directly on that many streams, the caller's
- *   stream hip_stream and streams - 1 side streams of the batch, forked from
- *   hip_stream and joined back into it with events: launch groups, largest
- *   first, each go to the stream with the least work so far, so groups of
- *   large and of small grids execute at the same time.  With largest_alone
- *   = 1 the largest group instead runs after the others have finished, on
- *   hip_stream (the smaller groups share the chip, the largest fills it
- *   alone).  Same kernels and tables, bitwise the same result.  Errors:
+ *   runs on that many streams, the caller's stream hip_stream and
+ *   streams - 1 side streams of the batch, forked from hip_stream and joined
+ *   back into it with events: launch groups, largest first, each go to the
+ *   stream with the least work so far, so groups of large and of small grids
+ *   execute at the same time.  Each stream's groups are captured into a
+ *   linear hipGraph of their own at the first run and replayed after that.
+ *   With largest_alone = 1 the largest group instead runs after the others
+ *   have finished, on hip_stream (the smaller groups share the chip, the
+ *   largest fills it alone).  Same kernels and tables, bitwise the same
+ *   result.  Errors:
  *   BRAHMS_E_INVALID_ARG for streams outside 1 .. 4 or largest_alone
  *   outside {0, 1}.
  * brahms_batch_set_group_limits: per-problem launch-group sizes (n entries,
@@ -392,8 +394,8 @@ brahms_status brahms_adjoint(brahms_plan plan, int nsteps, int checkpoint_every,
  * brahms_batch_bind: fields holds sum(nf_i) device pointers, problem-major,
  *   each in the field layout of brahms_plan_bind; workspace as for plans.
  * brahms_batch_run: propagate every problem nsteps[i] steps from z = 0
- *   (asynchronous, one graph launch on hip_stream; the first run also
- *   builds the graph).  Descriptor uploads at bind also go on hip_stream and
+ *   (asynchronous: one graph launch on hip_stream, or one per stream; the
+ *   first run also builds the graphs).  Descriptor uploads at bind also go on hip_stream and
  *   wait for it.
  * brahms_batch_run_steps: a run with per-problem step counts nsteps[i] (n
  *   entries, each between 0 and the count given at create): the counts go

@@ -13,7 +13,9 @@
 // branches of that graph (up to four side streams, groups dealt out largest
 // first) so that a bandwidth-bound group of large grids and latency-bound
 // groups of small grids execute at the same time; that is switched off (see
-// kParallelBranches) and the groups run one after the other, largest first.
+// kParallelBranches) and the groups run one after the other, largest first;
+// or (brahms_batch_set_streams) the groups are dealt over 2-4 streams, each
+// stream's groups captured into a linear graph of their own.
 // The default group size (a state of at most 160 MB) keeps a group's fields
 // in the last-level cache while it is propagated.
 //
@@ -58,10 +60,10 @@ struct brahms_batch_s {
   int group_max = 0;                   // 0: choose from the cache budget
   std::vector<int> group_limit;        // per problem, overrides group_max (empty: none)
   bool merge = false;                  // merged RK4 half-steps (constant dk only)
-  int streams = 1;                     // 1: one captured graph; 2..4: eager launches on that
-                                       // many streams (the caller's and side streams)
-  bool largest_alone = false;          // eager: the largest group after the others, alone
-  bool eager_pending = false;          // an eager run may still be running on side streams
+  int streams = 1;                     // 1: one captured graph; 2..4: one captured graph per
+                                       // stream (the caller's and side streams)
+  bool largest_alone = false;          // streams: the largest group after the others, alone
+  bool eager_pending = false;          // a run may still be running on side streams
   bool fuse = false;                   // fused step pairs (groups of three-pass steps)
   // launch groups and descriptor placement (rebuilt when the schedule changes)
   struct Group {
@@ -74,6 +76,15 @@ struct brahms_batch_s {
   std::vector<Group> groups;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
+  // streams > 1: one linear graph per stream (index into the caller's and
+  // side streams; the last, with largest_alone, on the caller's stream after
+  // the join)
+  static constexpr int kStreamGraphs = 6;
+  int nsg = 0;
+  hipGraph_t sgraph[kStreamGraphs] = {};
+  hipGraphExec_t sexec[kStreamGraphs] = {};
+  int sg_stream[kStreamGraphs] = {};
+  bool sg_after_join[kStreamGraphs] = {};
   // side streams and events of the capture: launch groups are independent,
   // so they become parallel branches of the graph
   static constexpr int kBranches = 4;
@@ -431,15 +442,44 @@ brahms_status enqueue_run(brahms_batch_s& b) {
   return BRAHMS_OK;
 }
 
-// The whole run issued directly (no graph) over b.streams streams: the
-// caller's stream and b.streams - 1 side streams, forked from and joined back
-// into the caller's stream; launch groups, largest first, each to the stream
-// with the least work so far.  The groups are independent, so large
-// bandwidth-bound groups and small latency-bound ones execute together.
-// With largest_alone the largest group runs after the others have joined,
-// on the caller's stream: groups that each leave much of the chip idle then
-// share it, and the largest group, which fills the chip, has it to itself.
-brahms_status run_eager(brahms_batch_s& b) {
+// Captures the launches of the given groups, in order, on b.stream into one
+// linear graph and instantiates it.
+brahms_status capture_groups(brahms_batch_s& b, const std::vector<size_t>& gs, hipGraph_t* graph_out,
+                             hipGraphExec_t* exec_out) {
+  HIP_TRY(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal));
+  brahms_status st = BRAHMS_OK;
+  for (size_t k : gs)
+    if ((st = enqueue_group(b, b.groups[k], b.stream)) != BRAHMS_OK) break;
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(b.stream, &graph);
+  if (st != BRAHMS_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st != BRAHMS_OK ? st
+                           : fail(BRAHMS_E_DEVICE, std::string("batch graph capture: ") + hipGetErrorString(e));
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(BRAHMS_E_DEVICE, std::string("batch graph instantiation: ") + hipGetErrorString(ei));
+  }
+  *graph_out = graph;
+  *exec_out = exec;
+  return BRAHMS_OK;
+}
+
+// The whole run over b.streams streams: the caller's stream and
+// b.streams - 1 side streams, forked from and joined back into the caller's
+// stream; launch groups, largest first, each to the stream with the least
+// work so far.  The groups are independent, so large bandwidth-bound groups
+// and small latency-bound ones execute together.  With largest_alone the
+// largest group runs after the others have joined, on the caller's stream:
+// groups that each leave much of the chip idle then share it, and the
+// largest group, which fills the chip, has it to itself.  Each stream's
+// groups are captured once into a linear graph of their own (no graph has
+// parallel branches) and replayed at every run, so that a run costs a few
+// graph launches instead of thousands of kernel launches from the host.
+brahms_status run_streams(brahms_batch_s& b) {
   std::vector<size_t> order(b.groups.size());
   for (size_t k = 0; k < order.size(); ++k) order[k] = k;
   auto work = [&](size_t k) {
@@ -455,35 +495,66 @@ brahms_status run_eager(brahms_batch_s& b) {
   const int ns = std::max(1, std::min<int>(b.streams, int(order.size())));
   hipStream_t st[brahms_batch_s::kBranches + 1] = {b.caller};
   for (int k = 1; k < ns; ++k) st[k] = b.side[k - 1];
+  if (b.nsg == 0) {
+    std::vector<std::vector<size_t>> per(static_cast<size_t>(ns));
+    std::vector<double> load(size_t(ns), 0.0);
+    for (size_t k : order) {
+      const size_t s = size_t(std::min_element(load.begin(), load.end()) - load.begin());
+      load[s] += work(k);
+      per[s].push_back(k);
+    }
+    for (int s = 0; s <= ns; ++s) {
+      const std::vector<size_t>& gs = s < ns ? per[size_t(s)] : last;
+      if (gs.empty()) continue;
+      const int i = b.nsg;
+      if (brahms_status e = capture_groups(b, gs, &b.sgraph[i], &b.sexec[i])) {
+        // release the graphs built so far: the next run builds them all again
+        for (int j = 0; j < i; ++j) {
+          (void)hipGraphExecDestroy(b.sexec[j]);
+          (void)hipGraphDestroy(b.sgraph[j]);
+          b.sexec[j] = nullptr;
+          b.sgraph[j] = nullptr;
+        }
+        b.nsg = 0;
+        return e;
+      }
+      b.sg_stream[i] = s < ns ? s : 0;
+      b.sg_after_join[i] = s == ns;
+      b.nsg = i + 1;
+    }
+  }
   if (ns > 1) {
     HIP_TRY(hipEventRecord(b.fork, b.caller));
     for (int k = 1; k < ns; ++k) HIP_TRY(hipStreamWaitEvent(st[k], b.fork, 0));
   }
-  std::vector<double> load(size_t(ns), 0.0);
-  for (size_t k : order) {
-    const size_t s = size_t(std::min_element(load.begin(), load.end()) - load.begin());
-    load[s] += work(k);
-    if (brahms_status e = enqueue_group(b, b.groups[k], st[s])) return e;
-  }
+  for (int i = 0; i < b.nsg; ++i)
+    if (!b.sg_after_join[i]) HIP_TRY(hipGraphLaunch(b.sexec[i], st[b.sg_stream[i]]));
   for (int k = 1; k < ns; ++k) {
     HIP_TRY(hipEventRecord(b.join[k - 1], st[k]));
     HIP_TRY(hipStreamWaitEvent(b.caller, b.join[k - 1], 0));
   }
-  for (size_t k : last)
-    if (brahms_status e = enqueue_group(b, b.groups[k], b.caller)) return e;
+  for (int i = 0; i < b.nsg; ++i)
+    if (b.sg_after_join[i]) HIP_TRY(hipGraphLaunch(b.sexec[i], b.caller));
   b.eager_pending = true;
   return BRAHMS_OK;
 }
 
 void drop_graph(brahms_batch_s& b) {
-  // no launch of the graph, and no eager run on the side streams, may still
+  // no launch of a graph, on the caller's stream or a side stream, may still
   // run when it goes (the caller's stream has joined the side streams)
-  if (b.exec || b.eager_pending) (void)hipStreamSynchronize(b.caller);
+  if (b.exec || b.eager_pending || b.nsg > 0) (void)hipStreamSynchronize(b.caller);
   b.eager_pending = false;
   if (b.exec) (void)hipGraphExecDestroy(b.exec);
   if (b.graph) (void)hipGraphDestroy(b.graph);
   b.exec = nullptr;
   b.graph = nullptr;
+  for (int i = 0; i < b.nsg; ++i) {
+    (void)hipGraphExecDestroy(b.sexec[i]);
+    (void)hipGraphDestroy(b.sgraph[i]);
+    b.sexec[i] = nullptr;
+    b.sgraph[i] = nullptr;
+  }
+  b.nsg = 0;
 }
 
 brahms_status check_batch(brahms_batch b) {
@@ -678,7 +749,7 @@ brahms_status brahms_batch_run(brahms_batch b) {
   if (brahms_status st = check_batch(b)) return st;
   if (!b->bound) return fail(BRAHMS_E_STATE, "brahms_batch_run before brahms_batch_bind");
   if (b->streams > 1) {
-    if (brahms_status st = run_eager(*b)) return st;
+    if (brahms_status st = run_streams(*b)) return st;
     for (int i = 0; i < b->n; ++i) b->plans[i]->step = b->nsteps[i];
     return BRAHMS_OK;
   }

@@ -133,9 +133,10 @@ def test_run_with_fewer_steps(merge):
 
 @pytest.mark.parametrize("merge", [0, 1])
 def test_streams_mode_equals_graph(merge):
-    """Launches issued on 2 or 4 streams (launch groups of different shapes
-    at the same time) give the bits of the captured graph, over two runs and
-    a run with fewer steps."""
+    """Runs on 2 or 4 streams (launch groups of different shapes at the same
+    time, each stream's groups replayed from a linear graph of their own)
+    give the bits of the one captured graph, over two runs and a run with
+    fewer steps (the same graphs replayed)."""
     wls = _problems(seed=15)
     for w in wls:
         w.dk = None
