@@ -562,9 +562,10 @@ class Batch:
 
     def set_streams(self, streams: int, largest_alone: int = 0):
         """1: the run is one captured hipGraph (groups in sequence); 2-4:
-        its launches go directly to that many streams, so that launch groups
-        of different shapes execute at the same time (with largest_alone,
-        all but the largest group, which then runs alone)."""
+        the run goes to that many streams, each replaying a linear graph of
+        its own groups, so that launch groups of different shapes execute at
+        the same time (with largest_alone, all but the largest group, which
+        then runs alone)."""
         _check(self._lib.brahms_batch_set_streams(self._h, int(streams), int(largest_alone)),
                "brahms_batch_set_streams")
 

@@ -428,16 +428,16 @@ void scenario_splits() {
   }
 }
 
-// launches issued on several streams instead of one captured graph
-void scenario_eager_streams() {
+// runs on several streams (a linear graph per stream) instead of one graph
+void scenario_stream_graphs() {
   for (int streams : {2, 4, -3})   // negative: the largest group alone after the others
     for (int merge : {0, 1}) {
       auto ps = mixed_problems(19, false);
       std::vector<int> orders;
       for (size_t k = 0; k < ps.size(); ++k) orders.push_back(int((k + 2) % 4));
       const BatchRun br = run_batch(ps, 1, &orders, nullptr, merge, merge, 2, streams);
-      compare_with_plans(ps, br, orders, merge, merge, "eager batch");
-      std::printf("eager streams=%d merge=%d: ok\n", streams, merge);
+      compare_with_plans(ps, br, orders, merge, merge, "streams batch");
+      std::printf("streams=%d merge=%d: ok\n", streams, merge);
     }
 }
 
@@ -552,7 +552,7 @@ int main(int argc, char** argv) {
   else if (s == "tuner_sequence") scenario_tuner_sequence();
   else if (s == "plans") scenario_plans();
   else if (s == "three_lengths") scenario_three_lengths();
-  else if (s == "eager_streams") scenario_eager_streams();
+  else if (s == "stream_graphs") scenario_stream_graphs();
   else if (s == "splits") scenario_splits();
   else {
     std::fprintf(stderr, "unknown scenario %s\n", s.c_str());

@@ -29,7 +29,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 EMU = os.path.join(ROOT, "tests", "hostemu")
 CSRC = os.path.join(ROOT, "paper_2609_08384_amd", "csrc")
 SCENARIOS = ["plain_batches", "merged_batches", "long_tau_batches", "long_tau_fused", "three_field",
-             "reduced_dims", "tuner_sequence", "plans", "three_lengths", "eager_streams", "splits"]
+             "reduced_dims", "tuner_sequence", "plans", "three_lengths", "stream_graphs", "splits"]
 VARIANT_SCENARIOS = ["plain_batches", "merged_batches", "long_tau_batches", "long_tau_fused",
                      "three_field", "reduced_dims", "tuner_sequence"]
 
