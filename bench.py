@@ -296,7 +296,9 @@ def batch_ratio(dev):
         torch.cuda.synchronize()
 
     batch = brahms.Batch(probs)
-    tuned = autotune.tune_batch(batch, dev)
+    # the tuner's six fastest probe candidates re-timed over whole runs of
+    # the sweep (fields restored after)
+    tuned = autotune.tune_batch(batch, dev, run_fields=fields)
     batch.bind(fields)
     batch.run()                      # builds the graph
 
@@ -340,7 +342,8 @@ def batch_ratio(dev):
             "sequential_rate": work / t_seq, "launch_groups": groups,
             "schedule": tuned["choice"], "group_max": tuned["group_max"], "streams": list(tuned["streams"]), "wide": tuned.get("wide"),
             "group_limits": tuned["group_limits"], "batch_orders": tuned["orders"],
-            "tuner_probe_ms": tuned["probe_ms"], "tuner_shape_probe_ms": tuned["shape_probe_ms"]}
+            "tuner_probe_ms": tuned["probe_ms"], "tuner_shape_probe_ms": tuned["shape_probe_ms"],
+            "tuner_whole_run_ms": tuned["whole_run_ms"]}
 
 
 # Sources that define the pass kernels and their launch configuration: the

@@ -20,6 +20,7 @@ from __future__ import annotations
 import json
 import os
 import threading
+import time
 from typing import Dict, Optional
 
 import torch
@@ -219,7 +220,7 @@ def _probe_time(batch: "brahms.Batch", fields, device) -> float:
 
 
 def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
-               merge_halves: bool = True) -> dict:
+               merge_halves: bool = True, run_fields=None, refine: int = 6) -> dict:
     """Pick the pass orders, the launch-group sizes and the launch mode of a
     batch by timing copies of it on scratch fields, with at most max_steps
     steps per problem:
@@ -237,13 +238,21 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
       or group size alone need not be the best together).
     Merged half-steps are taken when every problem allows them; fused step
     pairs are timed against three passes per step on the fastest choice.
-    Applies the fastest choice to `batch`."""
+    With `run_fields` (the caller's fields of the batch, per problem a list
+    of tensors) the `refine` fastest candidates are then timed on `batch`
+    itself, each over a whole run on those fields (saved first and restored
+    before every run) by wall clock, and the fastest of those is taken: the
+    short probes rank the launch modes, but a whole ragged run can order the
+    first few otherwise (and events on the caller's stream read runs on
+    several streams short).
+    Applies the chosen schedule to `batch`."""
     problems = batch.problems
     n = len(problems)
     merge = int(merge_halves and all(can_merge(prm) for (_, _, _, _, prm, _) in problems))
     # (batches holding a long tau problem do not fuse)
     fuse = int(merge and all(nt <= 256 for (_, _, nt, _, _, _) in problems) and
                any(can_fuse(nx, ny, nt) for (nx, ny, nt, _, _, _) in problems))
+    fuse_ok = fuse
     sched = [tune(nx, ny, nt, nf, prm, device, merge_halves=bool(merge))
              for (nx, ny, nt, nf, prm, _) in problems]
     tuned = [sc["pass_order"] for sc in sched]
@@ -313,17 +322,47 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
         if t3 < best[0]:
             fuse = 0
     probe.destroy()
-    batch.set_merge_halves(merge)
-    batch.set_fuse_steps(fuse)
-    batch.set_splits(splits)
-    batch.set_wide(wides)
-    batch.set_streams(*streams)
-    if gm is None:
-        batch.set_schedule(0, order_sets[oname])
-        batch.set_group_limits(limits)
-    else:
-        batch.set_group_limits(None)
-        batch.set_schedule(gm, order_sets[oname])
+
+    def apply(c_fuse, c_streams, c_gm, c_oname):
+        batch.set_merge_halves(merge)
+        batch.set_fuse_steps(c_fuse)
+        batch.set_splits(splits)
+        batch.set_wide(wides)
+        batch.set_streams(*c_streams)
+        if c_gm is None:
+            batch.set_schedule(0, order_sets[c_oname])
+            batch.set_group_limits(limits)
+        else:
+            batch.set_group_limits(None)
+            batch.set_schedule(c_gm, order_sets[c_oname])
+
+    whole_ms = {}
+    if run_fields is not None and refine > 0:
+        saved = [[f.clone() for f in fs] for fs in run_fields]
+
+        def restore():
+            for fs, ss in zip(run_fields, saved):
+                for f, g in zip(fs, ss):
+                    f.copy_(g)
+            torch.cuda.synchronize(device)
+
+        timed = []
+        for c in sorted(candidates, key=lambda c: c[0])[:refine]:
+            c_fuse = 0 if c[1].endswith("/three_passes") else fuse_ok
+            apply(c_fuse, c[4], c[2], c[3])
+            batch.bind(run_fields)
+            batch.run()                      # builds the graphs
+            torch.cuda.synchronize(device)
+            restore()
+            t0 = time.perf_counter()
+            batch.run()
+            torch.cuda.synchronize(device)
+            t = (time.perf_counter() - t0) * 1e3
+            timed.append((t, c, c_fuse))
+            whole_ms[f"{c[1]}/{c[3]}/streams={c[4][0]}{'/largest_alone' if c[4][1] else ''}"] = t
+        restore()
+        _, (_, label, gm, oname, streams), fuse = min(timed, key=lambda x: x[0])
+    apply(fuse, streams, gm, oname)
     return {"choice": label, "group_max": gm, "group_limits": limits if gm is None else None,
             "pass_orders": order_sets[oname], "orders": oname, "merge_halves": merge, "fuse_steps": fuse,
             "splits": splits,
@@ -331,4 +370,5 @@ def tune_batch(batch: "brahms.Batch", device="cuda:0", max_steps: int = 64,
             "streams": streams,
             "probe_ms": {f"{c[1]}/{c[3]}/streams={c[4][0]}{'/largest_alone' if c[4][1] else ''}": c[0]
                          for c in candidates},
-            "shape_probe_ms": shape_ms}
+            "shape_probe_ms": shape_ms,
+            "whole_run_ms": whole_ms}
